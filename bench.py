@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Benchmark of the SNeCT stratified-SGD hot path on one MI355X.
+
+A step is one epoch over the PanCan-shaped synthetic tensor (4,500 patients x
+14,000 genes x 5 platforms, 25M nonzeros, core 10x10x5, Barabasi-Albert gene
+graph with m = 10, P = 128 strata, T = 64): the network step, all strata
+(block kernels and core steps) and the end-of-epoch loss.  Inputs and factors
+are resident in HBM before the timed region starts; planning and upload are
+reported separately.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--ranks", type=str, default="10,10,5")
+    ap.add_argument("--strata", type=int, default=128)
+    ap.add_argument("--tile", type=int, default=64)
+    ap.add_argument("--nnz", type=int, default=25_000_000)
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-epochs", type=int, default=1)
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg, quiet=False):
+    if not quiet:
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_1711_08095_amd as sn
+    import snect_synth as synth
+
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    ranks = tuple(int(r) for r in args.ranks.split(","))
+    dims = (4500, 14000, 5)
+    t0 = time.time()
+    i, j, k, x, eu, ev = synth.pancan_like(nnz=args.nnz)
+    nnz = int(i.shape[0])
+    sigma = synth.default_sigma(x, ranks)
+    A, B, C, G = synth.normal_init(synth.INIT_SEED + 1, dims, ranks, sigma)
+    log(f"inputs: {nnz} nonzeros, {eu.shape[0]} edges in {time.time() - t0:.1f}s", args.quiet)
+
+    precision = sn.PRECISION_BF16 if args.precision == "bf16" else sn.PRECISION_FP32
+    hyper = sn.Hyper(ranks=ranks, lam=0.01, lam_g=0.1, lr=1e-3, core_lr_scale=1.0, P=args.strata,
+                     T=args.tile, precision=precision, seed=synth.PLAN_SEED + 1)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    ctx = sn.Context(0, stream.cuda_stream)
+    prob = sn.Problem(ctx, dims, i, j, k, x, eu, ev, None, hyper)
+    info = prob.info()
+    log(f"plan {info['plan_seconds']:.2f}s upload {info['upload_seconds']:.2f}s tiles {info['ntiles']}",
+        args.quiet)
+    f = [torch.tensor(a.astype(np.float32), device=dev).contiguous() for a in (A, B, C, G)]
+
+    # warmup epochs, then exactly `steps` timed epochs
+    if args.warmup > 0:
+        prob.train(*f, epochs=args.warmup, start_epoch=0)
+    prob.set_profiling(True)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    loss, rmse = prob.train(*f, epochs=args.steps, start_epoch=args.warmup)
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    tm = prob.last_timing()
+    wall = te - ts
+    ms_step = 1e3 * wall / max(args.steps, 1)
+    value = nnz * args.steps / wall
+    log(f"loss {loss} rmse {rmse}", args.quiet)
+    log(f"phases ms: graph {tm['graph_ms']:.2f} strata {tm['strata_ms']:.2f} loss {tm['loss_ms']:.2f} "
+        f"block {tm['block_ms']:.2f} over {tm['block_launches']} launches", args.quiet)
+
+    # roofline of the dominant kernel (the per-stratum block kernel)
+    J1, J2, J3 = ranks
+    I1, I2, I3 = dims
+    P = args.strata
+    launches = max(tm["block_launches"], 1)
+    avg_launch_s = tm["block_ms"] * 1e-3 / launches
+    nnz_per_launch = nnz / P
+    # algorithmic bytes per launch: 8 B per nonzero record streamed once, and
+    # every factor row of the stratum's blocks read once and written once
+    bytes_per_launch = 8.0 * nnz_per_launch + 2.0 * 4.0 * (I1 * J1 + I2 * J2)
+    flops_per_nnz = 6 * J1 * J2 + 4 * (J1 + J2)
+    achieved_gbs = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    achieved_tf = flops_per_nnz * nnz_per_launch / avg_launch_s / 1e12 if avg_launch_s > 0 else 0.0
+
+    out = {
+        "metric": "nonzero SGD updates/s FP32 vs BF16-MFMA at equal RMSE; fold-in p50/p99 ms",
+        "value": value,
+        "unit": "nonzero updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if precision == sn.PRECISION_FP32 else "bf16",
+        "data": "synthetic",
+        "config": {"workload": "pancan-shaped SGD epoch", "dims": list(dims), "nnz": nnz,
+                   "ranks": list(ranks), "strata_P": P, "tile_T": args.tile,
+                   "graph": "barabasi-albert m=10", "edges": int(eu.shape[0]),
+                   "lambda": 0.01, "lambda_g": 0.1, "lr": 1e-3},
+        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"block_fp32<{J1 if J1 == J2 else max(J1, J2)}>",
+                     "avg_launch_us": avg_launch_s * 1e6, "bytes_per_launch": bytes_per_launch,
+                     "alu_tflops": achieved_tf, "alu_frac": achieved_tf / FP32_VECTOR_PEAK_TFLOPS},
+        "phases_ms_per_step": {"graph": tm["graph_ms"] / args.steps,
+                               "strata": tm["strata_ms"] / args.steps,
+                               "loss": tm["loss_ms"] / args.steps},
+        "train_updates_per_s": nnz * args.steps / ((tm["graph_ms"] + tm["strata_ms"]) * 1e-3),
+        "plan_s": info["plan_seconds"], "upload_s": info["upload_seconds"],
+        "final_rmse": float(rmse[-1]), "final_loss": float(loss[-1]),
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        prob_o = oracle.Problem(dims, ranks, i, j, k, x.astype(np.float64), eu, ev, None, lam=0.01,
+                                lam_g=0.1, lr=1e-3, core_lr_scale=1.0, P=P, T=args.tile,
+                                seed=synth.PLAN_SEED + 1)
+        cores = oracle.num_threads()
+        tc = time.perf_counter()
+        oracle.run(prob_o, A, B, C, G, args.cpu_epochs)
+        tcpu = time.perf_counter() - tc
+        out["cpu_baseline"] = {
+            "value": nnz * args.cpu_epochs / tcpu, "unit": "nonzero updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{args.cpu_epochs} epoch(s) of the same workload in the FP64 oracle, plan and "
+                      f"loss pass included ({tcpu:.1f}s)"}
+        log(f"cpu oracle {tcpu:.1f}s on {cores} threads", args.quiet)
+    prob.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

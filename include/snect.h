@@ -1,0 +1,191 @@
+/*
+ * snect.h -- C ABI of the MI355X (gfx950) SNeCT engine.
+ *
+ * SNeCT (Choi & Sael, arXiv:1711.08095) fits a Tucker model (Eq. 2)
+ *     x(i,j,k) ~ sum_{a,b,c} G[a,b,c] A[i,a] B[j,b] C[k,c]
+ * to the observed cells of a sparse patient x gene x platform tensor, with an
+ * L2 penalty (Eq. 3) and a gene-network Laplacian penalty on B (Eq. 4), by
+ * stochastic gradient descent over the nonzeros (Algorithm 1, gradients of
+ * Eq. 5).  This library runs that SGD on one GPU with a deterministic
+ * stratified schedule in place of the paper's lock-free random order:
+ *
+ *   plan  seeded permutations split patients and genes into P blocks each;
+ *         block (p,q) lists its nonzeros in ascending (k, i, j) and cuts them
+ *         into tiles of at most T entries that never straddle a change of k;
+ *   epoch (a) network step: B <- B - (lr lambda_g / n_sub) L B, n_sub times,
+ *             n_sub = max(1, ceil(2 lr lambda_g d_max)), L = D - W;
+ *         (b) for each of P strata (seeded order), the blocks (p, (p+s) mod P)
+ *             run concurrently; inside a block the tiles run in order and every
+ *             nonzero of a tile reads the factor rows from before the tile:
+ *               e = x - a_i . (H_k b_j),  H_k = G x3 c_k (frozen per stratum)
+ *               a_i += lr * sum_t (e_t H_k b_j - lambda / n1[i] a_i)
+ *               b_j += lr * sum_t (e_t H_k^T a_i - lambda / n2[j] b_j)
+ *             then C and G take one step with the stratum's mean gradient,
+ *             step lr * core_lr_scale;
+ *         (c) f_opt and training RMSE at the end-of-epoch factors.
+ *
+ * Conventions
+ *   - Indices are 0-based (the paper's are 1-based).  All matrices are
+ *     row-major float32: A is I1 x J1, B is I2 x J2, C is I3 x J3, and G is
+ *     J1 x J2 x J3 with flat index (a*J2 + b)*J3 + c.
+ *   - Status codes: 0 on success, a negative SNECT_E_* value on failure.
+ *     No exception or abort crosses this interface.  After a failure,
+ *     snect_last_error() describes it.  Every input is validated before any
+ *     device work starts.
+ *   - Ownership: the caller owns every buffer it passes.  The library only
+ *     borrows them for the duration of the call.  Memory the library
+ *     allocates (the device-resident plan, scratch) belongs to the context
+ *     or problem object and is released by the matching destroy call.
+ *   - Streams: all device work is issued on the stream given to
+ *     snect_create (NULL = the device's default stream).  Every call that
+ *     returns host-visible results synchronises that stream before returning.
+ *   - Threads: one context per host thread; contexts are independent.
+ */
+#ifndef SNECT_H
+#define SNECT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SNECT_OK 0
+#define SNECT_E_ARG -1         /* bad scalar argument or NULL pointer        */
+#define SNECT_E_INDEX -2       /* a coordinate or edge endpoint out of range */
+#define SNECT_E_DUPLICATE -3   /* the same (i,j,k) given twice               */
+#define SNECT_E_RANK -4        /* core size outside what the kernels support */
+#define SNECT_E_OOM -5         /* host or device allocation failed           */
+#define SNECT_E_HIP -6         /* a HIP runtime call failed                  */
+#define SNECT_E_DIVERGED -7    /* the epoch loss became non-finite           */
+#define SNECT_E_BUSY -8        /* the serving pool has no free slot/memory   */
+#define SNECT_E_UNSUPPORTED -9 /* valid input outside this build's limits   */
+
+#define SNECT_PRECISION_FP32 0 /* FP32 contractions                          */
+#define SNECT_PRECISION_BF16 1 /* BF16 MFMA contractions, FP32 masters       */
+
+/* Limits of this build. */
+#define SNECT_MAX_RANK 32      /* J1, J2, J3 <= 32                           */
+#define SNECT_MAX_TILE 64      /* T <= 64: one tile is one wavefront         */
+
+typedef struct snect_ctx snect_ctx;
+typedef struct snect_problem snect_problem;
+
+/* Sparse tensor X over its observed cells Omega_X (Section 2.2, Table 2).
+ * Host memory.  nnz may be 0.  Coordinates must be distinct. */
+typedef struct {
+    int32_t I1, I2, I3;       /* patients, genes, platforms                 */
+    int64_t nnz;              /* number of observed cells, < 2^31           */
+    const int32_t *i, *j, *k; /* [nnz] 0-based coordinates                   */
+    const float *x;           /* [nnz] values, finite                        */
+} snect_tensor;
+
+/* Gene network Y (Section 2.1.2, Eq. 4): undirected edges, each listed once
+ * in either orientation; repeated pairs add their weights.  Host memory. */
+typedef struct {
+    int64_t E;                /* number of edges (may be 0)                  */
+    const int32_t *u, *v;     /* [E] gene endpoints, u != v                  */
+    const float *w;           /* [E] weights >= 0, or NULL for all ones      */
+} snect_graph;
+
+typedef struct {
+    int32_t J1, J2, J3;       /* core size, 1..SNECT_MAX_RANK               */
+    double lambda;            /* L2 weight (Eq. 3), >= 0                     */
+    double lambda_g;          /* network weight (Eq. 4), >= 0                */
+    double lr;                /* learning rate eta of Algorithm 1, > 0       */
+    double core_lr_scale;     /* C and G step = lr * core_lr_scale, >= 0     */
+    int32_t strata_P;         /* blocks per mode, 1 <= P <= min(I1, I2)      */
+    int32_t tile_T;           /* tile size, 1 <= T <= SNECT_MAX_TILE         */
+    int32_t precision;        /* SNECT_PRECISION_*                           */
+    uint64_t seed;            /* plan seed (permutations, stratum orders)    */
+} snect_params;
+
+/* Factor set: device pointers (row-major float32, sizes as above). */
+typedef struct {
+    float *A, *B, *C, *G;
+} snect_factors;
+
+/* Per-problem figures, for reporting and roofline accounting. */
+typedef struct {
+    int64_t nnz, ntiles, edges_csr;
+    int32_t P, T, rows1_max, rows2_max;
+    int32_t n_sub;            /* network sub-steps per epoch                 */
+    double d_max;             /* largest weighted gene degree                */
+    int64_t device_bytes;     /* device memory held by the problem           */
+    double plan_seconds;      /* host planning time                          */
+    double upload_seconds;    /* host-to-device copy time                    */
+} snect_info;
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t, or NULL for the default stream).  *ctx receives the
+ * handle.  Errors: E_ARG, E_HIP. */
+int snect_create(snect_ctx **ctx, int device, void *hip_stream);
+
+/* Release a context.  All problems created on it must be destroyed first;
+ * otherwise the call fails with E_BUSY and the context stays valid. */
+int snect_destroy(snect_ctx *ctx);
+
+/* Message for the last failure on this context ("" if none).  The string is
+ * owned by the context and valid until its next call. */
+const char *snect_last_error(const snect_ctx *ctx);
+
+/* Validate the inputs, build the plan on the host (slice counts, seeded
+ * permutations, block-sorted packed nonzeros, tiles, the symmetric CSR of
+ * the network Laplacian) and upload it.  The tensor and graph arrays are
+ * only read during the call.  Errors: E_ARG, E_INDEX, E_DUPLICATE, E_RANK,
+ * E_UNSUPPORTED (a block's rows do not fit on chip), E_OOM, E_HIP. */
+int snect_problem_create(snect_ctx *ctx, const snect_tensor *X, const snect_graph *Y,
+                         const snect_params *params, snect_problem **prob);
+
+/* Free a problem and its device memory. */
+int snect_problem_destroy(snect_problem *prob);
+
+/* Figures about a problem. */
+int snect_problem_info(const snect_problem *prob, snect_info *info);
+
+/* Run `epochs` epochs numbered start_epoch, start_epoch+1, ... (the epoch
+ * number selects the stratum order, so a run split into pieces reproduces
+ * one long run).  The factors in `f` (device pointers) are read as the
+ * starting point and overwritten in place.  loss[e] and rmse[e] (host
+ * arrays of length `epochs`, either may be NULL) receive f_opt and the
+ * training RMSE after each epoch.  If an epoch's loss is not finite the call
+ * stops, leaves the factors of the last finite epoch in `f` and returns
+ * E_DIVERGED.  Errors: E_ARG, E_HIP, E_DIVERGED. */
+int snect_train(snect_problem *prob, snect_factors *f, int32_t start_epoch, int32_t epochs,
+                double *loss, double *rmse);
+
+/* f_opt (Eq. 3 + lambda_g Eq. 4, L2 over the observed rows) and the RMSE of
+ * the given factors, without changing them.  Errors: E_ARG, E_HIP. */
+int snect_evaluate(snect_problem *prob, const snect_factors *f, double *loss, double *rmse);
+
+/* One-shot form: create the problem, copy `init` into `out` (device
+ * buffers; they may be the same), train `epochs` epochs from start_epoch,
+ * destroy the problem. */
+int snect_decompose(snect_ctx *ctx, const snect_tensor *X, const snect_graph *Y,
+                    const snect_params *params, const snect_factors *init, snect_factors *out,
+                    int32_t start_epoch, int32_t epochs, double *loss, double *rmse);
+
+/* The plan's seeded draws, for cross-checks: perm1[I1] and perm2[I2] (the
+ * row at each position of the patient / gene permutation; block of position
+ * r is floor(r P / I)), strata[P] (stratum order of `epoch`).  Any pointer
+ * may be NULL.  Host memory. */
+int snect_plan_export(const snect_problem *prob, int32_t epoch, int32_t *perm1, int32_t *perm2,
+                      int32_t *strata);
+
+/* Device time of the last snect_train call (milliseconds, summed over its
+ * epochs), measured with HIP events on the library stream: [0] network step,
+ * [1] strata (block kernels and core steps), [2] loss, [3] block kernels
+ * alone and [4] the number of block-kernel launches timed for [3] (both 0
+ * unless per-launch timing is on). */
+int snect_last_timing(const snect_problem *prob, double *ms5);
+
+/* Per-launch timing of the block kernel: when on, snect_train records a pair
+ * of HIP events around every block-kernel launch (no extra host
+ * synchronisation) and reports their sum in snect_last_timing [3].
+ * Errors: E_ARG, E_HIP. */
+int snect_set_profiling(snect_problem *prob, int per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SNECT_H */

@@ -1,0 +1,291 @@
+"""Python binding of libsnect (the C ABI declared in include/snect.h).
+
+Argument marshalling only: every step of the SGD runs in the HIP kernels of
+libsnect.so.  PyTorch supplies device memory (the factor tensors) and the
+stream.  Importing this package does not need a GPU, but every call that does
+device work fails loudly if the library is missing or no GPU is visible.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import sys
+import weakref
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsnect.so")
+
+SNECT_OK = 0
+ERRORS = {
+    -1: "SNECT_E_ARG", -2: "SNECT_E_INDEX", -3: "SNECT_E_DUPLICATE", -4: "SNECT_E_RANK",
+    -5: "SNECT_E_OOM", -6: "SNECT_E_HIP", -7: "SNECT_E_DIVERGED", -8: "SNECT_E_BUSY",
+    -9: "SNECT_E_UNSUPPORTED",
+}
+PRECISION_FP32 = 0
+PRECISION_BF16 = 1
+
+# Every symbol include/snect.h declares.
+EXPORTS = (
+    "snect_create", "snect_destroy", "snect_last_error", "snect_problem_create",
+    "snect_problem_destroy", "snect_problem_info", "snect_train", "snect_evaluate",
+    "snect_decompose", "snect_plan_export", "snect_last_timing", "snect_set_profiling",
+)
+
+
+class SnectError(RuntimeError):
+    def __init__(self, code: int, msg: str = ""):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Tensor(ctypes.Structure):
+    _fields_ = [("I1", ctypes.c_int32), ("I2", ctypes.c_int32), ("I3", ctypes.c_int32),
+                ("nnz", ctypes.c_int64),
+                ("i", ctypes.c_void_p), ("j", ctypes.c_void_p), ("k", ctypes.c_void_p),
+                ("x", ctypes.c_void_p)]
+
+
+class Graph(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_int64), ("u", ctypes.c_void_p), ("v", ctypes.c_void_p),
+                ("w", ctypes.c_void_p)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("J1", ctypes.c_int32), ("J2", ctypes.c_int32), ("J3", ctypes.c_int32),
+                ("lambda_", ctypes.c_double), ("lambda_g", ctypes.c_double), ("lr", ctypes.c_double),
+                ("core_lr_scale", ctypes.c_double),
+                ("strata_P", ctypes.c_int32), ("tile_T", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class Factors(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("G", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("nnz", ctypes.c_int64), ("ntiles", ctypes.c_int64), ("edges_csr", ctypes.c_int64),
+                ("P", ctypes.c_int32), ("T", ctypes.c_int32), ("rows1_max", ctypes.c_int32),
+                ("rows2_max", ctypes.c_int32), ("n_sub", ctypes.c_int32), ("d_max", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
+                ("upload_seconds", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libsnect.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1711_08095_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "snect_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, vp]),
+        "snect_destroy": (ctypes.c_int, [vp]),
+        "snect_last_error": (ctypes.c_char_p, [vp]),
+        "snect_problem_create": (ctypes.c_int, [vp, ctypes.POINTER(Tensor), ctypes.POINTER(Graph),
+                                                ctypes.POINTER(Params), ctypes.POINTER(vp)]),
+        "snect_problem_destroy": (ctypes.c_int, [vp]),
+        "snect_problem_info": (ctypes.c_int, [vp, ctypes.POINTER(Info)]),
+        "snect_train": (ctypes.c_int, [vp, ctypes.POINTER(Factors), i32, i32, vp, vp]),
+        "snect_evaluate": (ctypes.c_int, [vp, ctypes.POINTER(Factors), vp, vp]),
+        "snect_decompose": (ctypes.c_int, [vp, ctypes.POINTER(Tensor), ctypes.POINTER(Graph),
+                                           ctypes.POINTER(Params), ctypes.POINTER(Factors),
+                                           ctypes.POINTER(Factors), i32, i32, vp, vp]),
+        "snect_plan_export": (ctypes.c_int, [vp, i32, vp, vp, vp]),
+        "snect_last_timing": (ctypes.c_int, [vp, vp]),
+        "snect_set_profiling": (ctypes.c_int, [vp, ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _ = (i64, dbl)
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, ctx=None):
+    if rc != SNECT_OK:
+        msg = ""
+        if ctx is not None:
+            m = load().snect_last_error(ctx)
+            msg = m.decode() if m else ""
+        raise SnectError(rc, msg)
+
+
+def _dev_ptr(t, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float32")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+@dataclass
+class Hyper:
+    ranks: tuple
+    lam: float = 0.01
+    lam_g: float = 0.1
+    lr: float = 1e-3
+    core_lr_scale: float = 1.0
+    P: int = 8
+    T: int = 64
+    precision: int = PRECISION_FP32
+    seed: int = 0
+
+    def c(self) -> Params:
+        p = Params()
+        p.J1, p.J2, p.J3 = (int(r) for r in self.ranks)
+        p.lambda_, p.lambda_g, p.lr = float(self.lam), float(self.lam_g), float(self.lr)
+        p.core_lr_scale = float(self.core_lr_scale)
+        p.strata_P, p.tile_T, p.precision = int(self.P), int(self.T), int(self.precision)
+        p.seed = int(self.seed) & 0xFFFFFFFFFFFFFFFF
+        return p
+
+
+class Context:
+    """snect_create / snect_destroy on a device and a stream (default: the
+    current torch stream of that device)."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        lib = load()
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = ctypes.c_void_p()
+        _check(lib.snect_create(ctypes.byref(h), int(device), ctypes.c_void_p(stream)))
+        self.h = h
+        self.device = device
+        self._problems = weakref.WeakSet()
+
+    def close(self):
+        """Destroy the context and every problem still open on it."""
+        if self.h:
+            for p in list(self._problems):
+                p.close()
+            _check(load().snect_destroy(self.h), self.h)
+            self.h = None
+
+    def __del__(self):
+        # at interpreter shutdown the HIP runtime may already be gone; the
+        # process exit releases the memory
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """snect_problem_create on host arrays; the plan lives on the device."""
+
+    def __init__(self, ctx: Context, dims, i, j, k, x, eu=None, ev=None, ew=None, hyper: Hyper = None):
+        lib = load()
+        self.ctx = ctx
+        self.dims = tuple(int(d) for d in dims)
+        self.hyper = hyper
+        self._keep = [np.ascontiguousarray(a, dtype=np.int32) for a in (i, j, k)]
+        self._keep.append(np.ascontiguousarray(x, dtype=np.float32))
+        t = Tensor()
+        t.I1, t.I2, t.I3 = self.dims
+        t.nnz = int(self._keep[0].shape[0])
+        t.i, t.j, t.k, t.x = (a.ctypes.data for a in self._keep)
+        g = Graph()
+        eu = np.zeros(0, np.int32) if eu is None else np.ascontiguousarray(eu, dtype=np.int32)
+        ev = np.zeros(0, np.int32) if ev is None else np.ascontiguousarray(ev, dtype=np.int32)
+        g.E = int(eu.shape[0])
+        g.u, g.v = eu.ctypes.data, ev.ctypes.data
+        ewa = None if ew is None else np.ascontiguousarray(ew, dtype=np.float32)
+        g.w = None if ewa is None else ewa.ctypes.data
+        h = ctypes.c_void_p()
+        p = hyper.c()
+        _check(lib.snect_problem_create(ctx.h, ctypes.byref(t), ctypes.byref(g), ctypes.byref(p),
+                                        ctypes.byref(h)), ctx.h)
+        self.h = h
+        self._keep = None  # the library copied what it needs
+        ctx._problems.add(self)
+
+    def _factors(self, A, B, C, G) -> Factors:
+        I1, I2, I3 = self.dims
+        J1, J2, J3 = self.hyper.ranks
+        f = Factors()
+        f.A = _dev_ptr(A, (I1, J1), "A")
+        f.B = _dev_ptr(B, (I2, J2), "B")
+        f.C = _dev_ptr(C, (I3, J3), "C")
+        f.G = _dev_ptr(G, (J1, J2, J3), "G")
+        return f
+
+    def train(self, A, B, C, G, epochs: int, start_epoch: int = 0):
+        """snect_train: updates the torch tensors in place; returns (loss, rmse)."""
+        f = self._factors(A, B, C, G)
+        loss = np.zeros(max(epochs, 1))
+        rmse = np.zeros(max(epochs, 1))
+        rc = load().snect_train(self.h, ctypes.byref(f), int(start_epoch), int(epochs),
+                                loss.ctypes.data, rmse.ctypes.data)
+        if rc != SNECT_OK:
+            err = SnectError(rc, load().snect_last_error(self.ctx.h).decode())
+            err.loss, err.rmse = loss[:epochs], rmse[:epochs]
+            raise err
+        return loss[:epochs], rmse[:epochs]
+
+    def evaluate(self, A, B, C, G):
+        f = self._factors(A, B, C, G)
+        loss = ctypes.c_double()
+        rmse = ctypes.c_double()
+        _check(load().snect_evaluate(self.h, ctypes.byref(f), ctypes.addressof(loss),
+                                     ctypes.addressof(rmse)), self.ctx.h)
+        return loss.value, rmse.value
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(load().snect_problem_info(self.h, ctypes.byref(inf)), self.ctx.h)
+        return {n: getattr(inf, n) for n, _ in Info._fields_}
+
+    def plan_export(self, epoch: int = 0):
+        I1, I2, _ = self.dims
+        P = self.hyper.P
+        perm1 = np.zeros(I1, np.int32)
+        perm2 = np.zeros(I2, np.int32)
+        strata = np.zeros(P, np.int32)
+        _check(load().snect_plan_export(self.h, int(epoch), perm1.ctypes.data, perm2.ctypes.data,
+                                        strata.ctypes.data), self.ctx.h)
+        return dict(perm1=perm1, perm2=perm2, strata=strata)
+
+    def set_profiling(self, per_launch: bool):
+        _check(load().snect_set_profiling(self.h, 1 if per_launch else 0), self.ctx.h)
+
+    def last_timing(self):
+        ms = np.zeros(5)
+        _check(load().snect_last_timing(self.h, ms.ctypes.data), self.ctx.h)
+        return dict(graph_ms=ms[0], strata_ms=ms[1], loss_ms=ms[2], block_ms=ms[3],
+                    block_launches=int(ms[4]))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().snect_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = ["load", "Context", "Problem", "Hyper", "SnectError", "EXPORTS", "ERRORS",
+           "PRECISION_FP32", "PRECISION_BF16", "LIB_PATH"]

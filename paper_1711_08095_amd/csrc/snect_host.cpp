@@ -1,0 +1,750 @@
+// Host runtime of the SNeCT engine: input validation, the stratified plan,
+// device residency, the epoch launch sequence and the C ABI of snect.h.
+//
+// Plan (Algorithm 1's random order replaced by a seeded, deterministic
+// schedule): SplitMix64 streams (Steele, Lea & Flood 2014) drive Fisher-Yates
+// shuffles of the patient rows (stream 0), the gene rows (stream 1) and, for
+// epoch e, the P strata (stream 2 + e).  Stream t of a seed starts from the
+// t-th output of SplitMix64 seeded with that seed; a shuffle of n items walks
+// r = n-1 .. 1 and swaps item r with item floor(u (r+1) / 2^64) for the next
+// 64-bit draw u.  Position r of a permutation belongs to block
+// floor(r P / I).  Each block's nonzeros are sorted by (k, i, j) and cut into
+// tiles of at most T entries within one platform.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/snect.h"
+#include "snect_internal.h"
+
+using namespace snect;
+
+struct snect_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    size_t max_lds = 65536;
+    int num_cu = 0;
+    int live_problems = 0;  // problems still referring to this context
+};
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+int set_err(snect_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+uint64_t sm64_next(uint64_t& s)
+{
+    uint64_t z = (s += 0x9e3779b97f4a7c15ULL);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t stream_start(uint64_t seed, uint64_t stream)
+{
+    uint64_t s = seed, r = 0;
+    for (uint64_t t = 0; t <= stream; ++t) r = sm64_next(s);
+    return r;
+}
+
+void seeded_shuffle(std::vector<int32_t>& v, uint64_t seed, uint64_t stream)
+{
+    uint64_t s = stream_start(seed, stream);
+    for (int64_t r = (int64_t)v.size() - 1; r >= 1; --r) {
+        const uint64_t u = sm64_next(s);
+        const int64_t j = (int64_t)(((unsigned __int128)u * (unsigned __int128)(uint64_t)(r + 1)) >> 64);
+        std::swap(v[r], v[j]);
+    }
+}
+
+int ceil_log2(int64_t n)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+template <class F>
+void parallel_for(int64_t n, F&& f)
+{
+    unsigned hw = std::thread::hardware_concurrency();
+    int nt = (int)std::min<int64_t>(std::max(1u, std::min(hw, 16u)), std::max<int64_t>(1, n));
+    if (nt <= 1 || n < 64) {
+        for (int64_t t = 0; t < n; ++t) f(t, 0);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    std::vector<std::thread> th;
+    const int64_t chunk = std::max<int64_t>(1, n / (nt * 16));
+    for (int w = 0; w < nt; ++w)
+        th.emplace_back([&, w]() {
+            for (;;) {
+                const int64_t s = next.fetch_add(chunk);
+                if (s >= n) break;
+                const int64_t e = std::min(n, s + chunk);
+                for (int64_t t = s; t < e; ++t) f(t, w);
+            }
+        });
+    for (auto& t : th) t.join();
+}
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct snect_problem {
+    snect_ctx* ctx = nullptr;
+    // shape and parameters
+    int32_t I1 = 0, I2 = 0, I3 = 0, J1 = 0, J2 = 0, J3 = 0, P = 1, T = 1, jp = 0;
+    int64_t nnz = 0, ntiles = 0, ecsr = 0;
+    double lam = 0, lam_g = 0, lr = 0, cls = 1;
+    uint64_t seed = 0;
+    int32_t rows1_max = 0, rows2_max = 0, bits_i = 0, bits_j = 0, n_sub = 0;
+    double dmax = 0;
+    size_t block_lds = 0, loss_lds = 0;
+    double plan_s = 0, upload_s = 0;
+    // host copies kept for export
+    std::vector<int32_t> perm1, perm2;
+    // device buffers
+    std::vector<DevBuf> bufs;
+    uint2* d_nz = nullptr;
+    int32_t *d_tile_off = nullptr, *d_tile_k = nullptr, *d_blk_tile = nullptr;
+    int32_t *d_perm1 = nullptr, *d_start1 = nullptr, *d_perm2 = nullptr, *d_start2 = nullptr;
+    float *d_reg1 = nullptr, *d_reg2 = nullptr;
+    int32_t *d_cnt1 = nullptr, *d_cnt2 = nullptr, *d_cnt3 = nullptr;
+    int32_t *d_adj_start = nullptr, *d_adj_nbr = nullptr;
+    float *d_adj_w = nullptr, *d_deg = nullptr;
+    float* d_Spart = nullptr;
+    int32_t* d_Mpart = nullptr;
+    float* d_Btmp = nullptr;
+    double* d_partial = nullptr;
+    double* d_lossout = nullptr;
+    double* h_lossout = nullptr;  // pinned
+    float *d_bakA = nullptr, *d_bakB = nullptr, *d_bakC = nullptr, *d_bakG = nullptr;
+    // timing
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> evb;  // 2 per stratum when per-launch timing is on
+    bool per_launch = false;
+    double t_ms[5] = {0, 0, 0, 0, 0};
+
+    template <class T_>
+    T_* alloc(size_t count, int& rc)
+    {
+        DevBuf b;
+        b.bytes = std::max<size_t>(count * sizeof(T_), 16);
+        if (hipMalloc(&b.p, b.bytes) != hipSuccess) {
+            rc = SNECT_E_OOM;
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        bufs.push_back(b);
+        return static_cast<T_*>(b.p);
+    }
+    ~snect_problem()
+    {
+        for (auto& b : bufs) (void)hipFree(b.p);
+        if (h_lossout) (void)hipHostFree(h_lossout);
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto& e : evb)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+#define HIP_TRY(call)                                                                          \
+    do {                                                                                       \
+        hipError_t _e = (call);                                                                \
+        if (_e != hipSuccess)                                                                  \
+            return set_err(ctx, SNECT_E_HIP, std::string(#call ": ") + hipGetErrorString(_e)); \
+    } while (0)
+
+extern "C" {
+
+int snect_create(snect_ctx** out, int device, void* stream)
+{
+    if (!out) return SNECT_E_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SNECT_E_ARG;
+    snect_ctx* c = new (std::nothrow) snect_ctx();
+    if (!c) return SNECT_E_OOM;
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return SNECT_E_HIP;
+    }
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && v > 0)
+        c->max_lds = (size_t)v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess) c->num_cu = v;
+    *out = c;
+    return SNECT_OK;
+}
+
+int snect_destroy(snect_ctx* ctx)
+{
+    if (!ctx) return SNECT_E_ARG;
+    if (ctx->live_problems > 0)
+        return set_err(ctx, SNECT_E_BUSY, "destroy the context's problems first");
+    delete ctx;
+    return SNECT_OK;
+}
+
+const char* snect_last_error(const snect_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_graph* Y, const snect_params* pa,
+                         snect_problem** out)
+{
+    if (!ctx) return SNECT_E_ARG;
+    ctx->err.clear();
+    if (!X || !pa || !out) return set_err(ctx, SNECT_E_ARG, "null argument");
+    *out = nullptr;
+    const double t_plan0 = now_s();
+    // ---------------- validation ----------------
+    if (X->I1 <= 0 || X->I2 <= 0 || X->I3 <= 0) return set_err(ctx, SNECT_E_ARG, "tensor dims must be positive");
+    if (X->nnz < 0 || X->nnz >= (int64_t(1) << 31)) return set_err(ctx, SNECT_E_ARG, "nnz out of range");
+    if (X->nnz > 0 && (!X->i || !X->j || !X->k || !X->x)) return set_err(ctx, SNECT_E_ARG, "null tensor array");
+    if (pa->J1 < 1 || pa->J2 < 1 || pa->J3 < 1 || pa->J1 > SNECT_MAX_RANK || pa->J2 > SNECT_MAX_RANK ||
+        pa->J3 > SNECT_MAX_RANK)
+        return set_err(ctx, SNECT_E_RANK, "core size must be in 1..32");
+    if (!(pa->lambda >= 0) || !(pa->lambda_g >= 0) || !(pa->lr > 0) || !(pa->core_lr_scale >= 0) ||
+        !std::isfinite(pa->lambda) || !std::isfinite(pa->lambda_g) || !std::isfinite(pa->lr) ||
+        !std::isfinite(pa->core_lr_scale))
+        return set_err(ctx, SNECT_E_ARG, "lambda, lambda_g, core_lr_scale must be >= 0 and lr > 0");
+    if (pa->strata_P < 1 || pa->strata_P > X->I1 || pa->strata_P > X->I2)
+        return set_err(ctx, SNECT_E_ARG, "strata_P must be in 1..min(I1, I2)");
+    if (pa->tile_T < 1 || pa->tile_T > SNECT_MAX_TILE) return set_err(ctx, SNECT_E_ARG, "tile_T must be in 1..64");
+    if (pa->precision != SNECT_PRECISION_FP32 && pa->precision != SNECT_PRECISION_BF16)
+        return set_err(ctx, SNECT_E_ARG, "unknown precision");
+    if (pa->precision == SNECT_PRECISION_BF16) return set_err(ctx, SNECT_E_UNSUPPORTED, "BF16 path not built");
+    const int64_t E = Y ? Y->E : 0;
+    if (E < 0 || E >= (int64_t(1) << 30)) return set_err(ctx, SNECT_E_ARG, "edge count out of range");
+    if (E > 0 && (!Y->u || !Y->v)) return set_err(ctx, SNECT_E_ARG, "null edge array");
+    const int32_t I1 = X->I1, I2 = X->I2, I3 = X->I3;
+    const int64_t nnz = X->nnz;
+    for (int64_t t = 0; t < nnz; ++t) {
+        if (X->i[t] < 0 || X->i[t] >= I1 || X->j[t] < 0 || X->j[t] >= I2 || X->k[t] < 0 || X->k[t] >= I3)
+            return set_err(ctx, SNECT_E_INDEX, "nonzero " + std::to_string(t) + " has a coordinate out of range");
+        if (!std::isfinite(X->x[t])) return set_err(ctx, SNECT_E_ARG, "non-finite value at nonzero " + std::to_string(t));
+    }
+    for (int64_t e = 0; e < E; ++e) {
+        if (Y->u[e] < 0 || Y->u[e] >= I2 || Y->v[e] < 0 || Y->v[e] >= I2)
+            return set_err(ctx, SNECT_E_INDEX, "edge " + std::to_string(e) + " endpoint out of range");
+        if (Y->u[e] == Y->v[e]) return set_err(ctx, SNECT_E_ARG, "self-loop at edge " + std::to_string(e));
+        if (Y->w && (!(Y->w[e] >= 0) || !std::isfinite(Y->w[e])))
+            return set_err(ctx, SNECT_E_ARG, "edge weights must be finite and >= 0");
+    }
+    const int P = pa->strata_P, T = pa->tile_T;
+    const int jp = jp_for(pa->J1, pa->J2);
+    if (jp < 0) return set_err(ctx, SNECT_E_RANK, "no kernel for this core size");
+    const int rows1_max = (I1 + P - 1) / P, rows2_max = (I2 + P - 1) / P;
+    const int bits_i = std::max(1, ceil_log2(rows1_max)), bits_j = std::max(1, ceil_log2(rows2_max));
+    if (bits_i + bits_j > kMaxLocalBits)
+        return set_err(ctx, SNECT_E_UNSUPPORTED, "blocks too large to pack; raise strata_P");
+    if (I3 > 4096) return set_err(ctx, SNECT_E_UNSUPPORTED, "at most 4096 platforms");
+    const size_t blds = block_lds_bytes(jp, rows1_max, rows2_max, I3, pa->J1, pa->J2);
+    const size_t llds = loss_lds_bytes(jp, rows1_max, rows2_max, I3);
+    if (blds > ctx->max_lds || llds > ctx->max_lds)
+        return set_err(ctx, SNECT_E_UNSUPPORTED,
+                       "a block's rows do not fit in LDS (" + std::to_string(blds) + " bytes); raise strata_P");
+    if ((int64_t)P * P * I3 >= (int64_t(1) << 31)) return set_err(ctx, SNECT_E_UNSUPPORTED, "too many blocks");
+
+    snect_problem* pr = new (std::nothrow) snect_problem();
+    if (!pr) return set_err(ctx, SNECT_E_OOM, "host allocation");
+    pr->ctx = ctx;
+    pr->I1 = I1; pr->I2 = I2; pr->I3 = I3;
+    pr->J1 = pa->J1; pr->J2 = pa->J2; pr->J3 = pa->J3;
+    pr->P = P; pr->T = T; pr->jp = jp; pr->nnz = nnz;
+    pr->lam = pa->lambda; pr->lam_g = pa->lambda_g; pr->lr = pa->lr; pr->cls = pa->core_lr_scale;
+    pr->seed = pa->seed;
+    pr->rows1_max = rows1_max; pr->rows2_max = rows2_max; pr->bits_i = bits_i; pr->bits_j = bits_j;
+    pr->block_lds = blds; pr->loss_lds = llds;
+
+    int rc = SNECT_OK;
+    try {
+        // ---------------- slice counts ----------------
+        std::vector<int32_t> cnt1(I1, 0), cnt2(I2, 0), cnt3(I3, 0);
+        for (int64_t t = 0; t < nnz; ++t) {
+            cnt1[X->i[t]]++;
+            cnt2[X->j[t]]++;
+            cnt3[X->k[t]]++;
+        }
+        std::vector<float> reg1(I1, 0.f), reg2(I2, 0.f);
+        for (int r = 0; r < I1; ++r) reg1[r] = cnt1[r] ? (float)(pa->lambda / cnt1[r]) : 0.f;
+        for (int r = 0; r < I2; ++r) reg2[r] = cnt2[r] ? (float)(pa->lambda / cnt2[r]) : 0.f;
+        // ---------------- permutations and blocks ----------------
+        pr->perm1.resize(I1);
+        pr->perm2.resize(I2);
+        for (int r = 0; r < I1; ++r) pr->perm1[r] = r;
+        for (int r = 0; r < I2; ++r) pr->perm2[r] = r;
+        seeded_shuffle(pr->perm1, pa->seed, 0);
+        seeded_shuffle(pr->perm2, pa->seed, 1);
+        std::vector<int32_t> blk1(I1), loc1(I1), blk2(I2), loc2(I2), start1(P + 1), start2(P + 1);
+        for (int p = 0; p <= P; ++p) {
+            start1[p] = (int32_t)(((int64_t)p * I1 + P - 1) / P);
+            start2[p] = (int32_t)(((int64_t)p * I2 + P - 1) / P);
+        }
+        for (int64_t r = 0; r < I1; ++r) {
+            const int b = (int)(r * P / I1);
+            blk1[pr->perm1[r]] = b;
+            loc1[pr->perm1[r]] = (int32_t)(r - start1[b]);
+        }
+        for (int64_t r = 0; r < I2; ++r) {
+            const int b = (int)(r * P / I2);
+            blk2[pr->perm2[r]] = b;
+            loc2[pr->perm2[r]] = (int32_t)(r - start2[b]);
+        }
+        // ---------------- bucket by (block, k), sort by (i, j) ----------------
+        const int64_t nb = (int64_t)P * P * I3;
+        std::vector<int64_t> bstart(nb + 1, 0);
+        std::vector<int32_t> bucket(nnz);
+        for (int64_t t = 0; t < nnz; ++t) {
+            const int64_t b = ((int64_t)blk1[X->i[t]] * P + blk2[X->j[t]]) * I3 + X->k[t];
+            bucket[t] = (int32_t)b;
+            bstart[b + 1]++;
+        }
+        for (int64_t b = 0; b < nb; ++b) bstart[b + 1] += bstart[b];
+        std::vector<int32_t> ord(nnz);
+        {
+            std::vector<int64_t> fill(bstart.begin(), bstart.end() - 1);
+            for (int64_t t = 0; t < nnz; ++t) ord[fill[bucket[t]]++] = (int32_t)t;
+        }
+        std::vector<int32_t>().swap(bucket);
+        std::atomic<int> dup{0};
+        parallel_for(nb, [&](int64_t b, int) {
+            const int64_t s = bstart[b], e = bstart[b + 1];
+            if (e - s < 2) return;
+            std::vector<std::pair<int64_t, int32_t>> kv(e - s);
+            for (int64_t t = s; t < e; ++t) kv[t - s] = {(int64_t)X->i[ord[t]] * I2 + X->j[ord[t]], ord[t]};
+            std::sort(kv.begin(), kv.end());
+            for (size_t u = 1; u < kv.size(); ++u)
+                if (kv[u].first == kv[u - 1].first) dup.store(1);
+            for (int64_t t = s; t < e; ++t) ord[t] = kv[t - s].second;
+        });
+        if (dup.load()) {
+            delete pr;
+            return set_err(ctx, SNECT_E_DUPLICATE, "duplicate (i,j,k) coordinate");
+        }
+        // ---------------- tiles ----------------
+        std::vector<int64_t> tiles_in_bucket(nb + 1, 0);
+        for (int64_t b = 0; b < nb; ++b) tiles_in_bucket[b + 1] = tiles_in_bucket[b] + (bstart[b + 1] - bstart[b] + T - 1) / T;
+        const int64_t ntiles = tiles_in_bucket[nb];
+        if (ntiles >= (int64_t(1) << 31)) {
+            delete pr;
+            return set_err(ctx, SNECT_E_UNSUPPORTED, "too many tiles");
+        }
+        std::vector<int32_t> tile_off(ntiles + 1), tile_k(ntiles), blk_tile((size_t)P * P + 1);
+        for (int64_t b = 0; b < nb; ++b) {
+            const int k = (int)(b % I3);
+            for (int64_t u = 0; u < tiles_in_bucket[b + 1] - tiles_in_bucket[b]; ++u) {
+                tile_off[tiles_in_bucket[b] + u] = (int32_t)(bstart[b] + u * T);
+                tile_k[tiles_in_bucket[b] + u] = k;
+            }
+        }
+        tile_off[ntiles] = (int32_t)nnz;
+        for (int64_t blk = 0; blk <= (int64_t)P * P; ++blk) blk_tile[blk] = (int32_t)tiles_in_bucket[blk * I3];
+        // ---------------- pack records (with in-tile gene chains) ----------------
+        std::vector<uint2> nz(nnz);
+        const unsigned hw = std::max(1u, std::min(std::thread::hardware_concurrency(), 16u));
+        std::vector<std::vector<int16_t>> lastpos(hw, std::vector<int16_t>(rows2_max, -1));
+        parallel_for(ntiles, [&](int64_t tl, int w) {
+            std::vector<int16_t>& lp = lastpos[w];
+            const int32_t s = tile_off[tl], e = tile_off[tl + 1];
+            for (int32_t z = s; z < e; ++z) {
+                const int32_t t = ord[z];
+                const uint32_t il = (uint32_t)loc1[X->i[t]], jl = (uint32_t)loc2[X->j[t]];
+                const int pos = z - s;
+                const int prev = lp[jl] >= 0 ? lp[jl] : pos;
+                lp[jl] = (int16_t)pos;
+                nz[z].x = il | (jl << bits_i) | ((uint32_t)prev << (bits_i + bits_j));
+                nz[z].y = 0;
+                std::memcpy(&nz[z].y, &X->x[t], 4);
+            }
+            // last occurrence of each gene row in the tile
+            for (int32_t z = e - 1; z >= s; --z) {
+                const uint32_t jl = (nz[z].x >> bits_i) & ((1u << bits_j) - 1u);
+                if (lp[jl] == z - s) {
+                    nz[z].x |= 1u << (bits_i + bits_j + kJprevBits);
+                    lp[jl] = -1;
+                }
+            }
+            for (int32_t z = s; z < e; ++z) lp[(nz[z].x >> bits_i) & ((1u << bits_j) - 1u)] = -1;
+        });
+        // ---------------- network: symmetric CSR, repeated pairs summed ----------------
+        std::vector<std::pair<int64_t, float>> ed;
+        ed.reserve(2 * E);
+        for (int64_t e = 0; e < E; ++e) {
+            const float w = Y->w ? Y->w[e] : 1.f;
+            ed.push_back({(int64_t)Y->u[e] * I2 + Y->v[e], w});
+            ed.push_back({(int64_t)Y->v[e] * I2 + Y->u[e], w});
+        }
+        std::sort(ed.begin(), ed.end(), [](const std::pair<int64_t, float>& a, const std::pair<int64_t, float>& b) {
+            return a.first < b.first;
+        });
+        std::vector<int32_t> adj_start(I2 + 1, 0), adj_nbr;
+        std::vector<float> adj_w;
+        std::vector<double> degd(I2, 0.0);
+        for (size_t e = 0; e < ed.size(); ++e) {
+            if (!adj_nbr.empty() && e > 0 && ed[e].first == ed[e - 1].first) {
+                adj_w.back() += ed[e].second;
+            } else {
+                adj_nbr.push_back((int32_t)(ed[e].first % I2));
+                adj_w.push_back(ed[e].second);
+                adj_start[ed[e].first / I2 + 1]++;
+            }
+        }
+        for (int r = 0; r < I2; ++r) adj_start[r + 1] += adj_start[r];
+        std::vector<float> deg(I2, 0.f);
+        for (int r = 0; r < I2; ++r) {
+            double d = 0.0;
+            for (int e = adj_start[r]; e < adj_start[r + 1]; ++e) d += (double)adj_w[e];
+            degd[r] = d;
+            deg[r] = (float)d;
+        }
+        double dmax = 0.0;
+        for (int r = 0; r < I2; ++r) dmax = std::max(dmax, degd[r]);
+        pr->dmax = dmax;
+        pr->ecsr = (int64_t)adj_nbr.size();
+        pr->n_sub = 0;
+        if (pa->lambda_g > 0 && E > 0) pr->n_sub = std::max(1, (int)std::ceil(2.0 * pa->lr * pa->lambda_g * dmax));
+        pr->ntiles = ntiles;
+        pr->plan_s = now_s() - t_plan0;
+
+        // ---------------- upload ----------------
+        const double t_up0 = now_s();
+        HIP_TRY(hipSetDevice(ctx->device));
+        pr->d_nz = pr->alloc<uint2>(nnz, rc);
+        pr->d_tile_off = pr->alloc<int32_t>(ntiles + 1, rc);
+        pr->d_tile_k = pr->alloc<int32_t>(ntiles, rc);
+        pr->d_blk_tile = pr->alloc<int32_t>((size_t)P * P + 1, rc);
+        pr->d_perm1 = pr->alloc<int32_t>(I1, rc);
+        pr->d_perm2 = pr->alloc<int32_t>(I2, rc);
+        pr->d_start1 = pr->alloc<int32_t>(P + 1, rc);
+        pr->d_start2 = pr->alloc<int32_t>(P + 1, rc);
+        pr->d_reg1 = pr->alloc<float>(I1, rc);
+        pr->d_reg2 = pr->alloc<float>(I2, rc);
+        pr->d_cnt1 = pr->alloc<int32_t>(I1, rc);
+        pr->d_cnt2 = pr->alloc<int32_t>(I2, rc);
+        pr->d_cnt3 = pr->alloc<int32_t>(I3, rc);
+        pr->d_adj_start = pr->alloc<int32_t>(I2 + 1, rc);
+        pr->d_adj_nbr = pr->alloc<int32_t>(adj_nbr.size(), rc);
+        pr->d_adj_w = pr->alloc<float>(adj_w.size(), rc);
+        pr->d_deg = pr->alloc<float>(I2, rc);
+        pr->d_Spart = pr->alloc<float>((size_t)P * I3 * pa->J1 * pa->J2, rc);
+        pr->d_Mpart = pr->alloc<int32_t>((size_t)P * I3, rc);
+        pr->d_Btmp = pr->alloc<float>((size_t)I2 * pa->J2, rc);
+        pr->d_partial = pr->alloc<double>((size_t)P * P, rc);
+        pr->d_lossout = pr->alloc<double>(2, rc);
+        pr->d_bakA = pr->alloc<float>((size_t)I1 * pa->J1, rc);
+        pr->d_bakB = pr->alloc<float>((size_t)I2 * pa->J2, rc);
+        pr->d_bakC = pr->alloc<float>((size_t)I3 * pa->J3, rc);
+        pr->d_bakG = pr->alloc<float>((size_t)pa->J1 * pa->J2 * pa->J3, rc);
+        if (rc) {
+            delete pr;
+            return set_err(ctx, SNECT_E_OOM, "device allocation failed");
+        }
+        if (hipHostMalloc((void**)&pr->h_lossout, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            delete pr;
+            return set_err(ctx, SNECT_E_OOM, "pinned host allocation failed");
+        }
+        hipStream_t st = ctx->stream;
+        auto up = [&](void* d, const void* h, size_t bytes) -> hipError_t {
+            if (bytes == 0) return hipSuccess;
+            return hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st);
+        };
+        hipError_t he = hipSuccess;
+        he = he ? he : up(pr->d_nz, nz.data(), nnz * sizeof(uint2));
+        he = he ? he : up(pr->d_tile_off, tile_off.data(), tile_off.size() * 4);
+        he = he ? he : up(pr->d_tile_k, tile_k.data(), tile_k.size() * 4);
+        he = he ? he : up(pr->d_blk_tile, blk_tile.data(), blk_tile.size() * 4);
+        he = he ? he : up(pr->d_perm1, pr->perm1.data(), I1 * 4);
+        he = he ? he : up(pr->d_perm2, pr->perm2.data(), I2 * 4);
+        he = he ? he : up(pr->d_start1, start1.data(), (P + 1) * 4);
+        he = he ? he : up(pr->d_start2, start2.data(), (P + 1) * 4);
+        he = he ? he : up(pr->d_reg1, reg1.data(), I1 * 4);
+        he = he ? he : up(pr->d_reg2, reg2.data(), I2 * 4);
+        he = he ? he : up(pr->d_cnt1, cnt1.data(), I1 * 4);
+        he = he ? he : up(pr->d_cnt2, cnt2.data(), I2 * 4);
+        he = he ? he : up(pr->d_cnt3, cnt3.data(), I3 * 4);
+        he = he ? he : up(pr->d_adj_start, adj_start.data(), (I2 + 1) * 4);
+        he = he ? he : up(pr->d_adj_nbr, adj_nbr.data(), adj_nbr.size() * 4);
+        he = he ? he : up(pr->d_adj_w, adj_w.data(), adj_w.size() * 4);
+        he = he ? he : up(pr->d_deg, deg.data(), I2 * 4);
+        he = he ? he : hipStreamSynchronize(st);
+        he = he ? he : prepare_kernels(jp, blds, llds);
+        for (int t = 0; t < 4 && he == hipSuccess; ++t) he = hipEventCreate(&pr->ev[t]);
+        if (he != hipSuccess) {
+            delete pr;
+            return set_err(ctx, SNECT_E_HIP, std::string("upload: ") + hipGetErrorString(he));
+        }
+        pr->upload_s = now_s() - t_up0;
+        ctx->live_problems++;
+    } catch (const std::bad_alloc&) {
+        delete pr;
+        return set_err(ctx, SNECT_E_OOM, "host allocation failed while planning");
+    }
+    *out = pr;
+    return SNECT_OK;
+}
+
+int snect_problem_destroy(snect_problem* prob)
+{
+    if (!prob) return SNECT_E_ARG;
+    (void)hipSetDevice(prob->ctx->device);
+    (void)hipStreamSynchronize(prob->ctx->stream);
+    prob->ctx->live_problems--;
+    delete prob;
+    return SNECT_OK;
+}
+
+int snect_problem_info(const snect_problem* pr, snect_info* info)
+{
+    if (!pr || !info) return SNECT_E_ARG;
+    info->nnz = pr->nnz;
+    info->ntiles = pr->ntiles;
+    info->edges_csr = pr->ecsr;
+    info->P = pr->P;
+    info->T = pr->T;
+    info->rows1_max = pr->rows1_max;
+    info->rows2_max = pr->rows2_max;
+    info->n_sub = pr->n_sub;
+    info->d_max = pr->dmax;
+    int64_t b = 0;
+    for (auto& x : pr->bufs) b += (int64_t)x.bytes;
+    info->device_bytes = b;
+    info->plan_seconds = pr->plan_s;
+    info->upload_seconds = pr->upload_s;
+    return SNECT_OK;
+}
+
+static int check_factors(snect_ctx* ctx, const snect_factors* f)
+{
+    if (!f || !f->A || !f->B || !f->C || !f->G) return set_err(ctx, SNECT_E_ARG, "null factor pointer");
+    return SNECT_OK;
+}
+
+// Loss of the current factors into pr->h_lossout (synchronises).
+static int run_loss(snect_problem* pr, const snect_factors* f)
+{
+    snect_ctx* ctx = pr->ctx;
+    LossArgs la;
+    la.nz = pr->d_nz; la.tile_off = pr->d_tile_off; la.tile_k = pr->d_tile_k; la.blk_tile = pr->d_blk_tile;
+    la.perm1 = pr->d_perm1; la.start1 = pr->d_start1; la.perm2 = pr->d_perm2; la.start2 = pr->d_start2;
+    la.cnt1 = pr->d_cnt1; la.cnt2 = pr->d_cnt2; la.cnt3 = pr->d_cnt3;
+    la.A = f->A; la.B = f->B; la.C = f->C; la.G = f->G;
+    la.adj_start = pr->d_adj_start; la.adj_nbr = pr->d_adj_nbr; la.adj_w = pr->d_adj_w;
+    la.partial = pr->d_partial; la.out = pr->d_lossout;
+    la.P = pr->P; la.I1 = pr->I1; la.I2 = pr->I2; la.I3 = pr->I3;
+    la.J1 = pr->J1; la.J2 = pr->J2; la.J3 = pr->J3;
+    la.rows1_max = pr->rows1_max; la.rows2_max = pr->rows2_max; la.bits_i = pr->bits_i; la.bits_j = pr->bits_j;
+    la.lam = pr->lam; la.lam_g = pr->lam_g;
+    HIP_TRY(launch_loss(la, pr->jp, pr->loss_lds, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(pr->h_lossout, pr->d_lossout, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    return SNECT_OK;
+}
+
+int snect_evaluate(snect_problem* pr, const snect_factors* f, double* loss, double* rmse)
+{
+    if (!pr) return SNECT_E_ARG;
+    snect_ctx* ctx = pr->ctx;
+    ctx->err.clear();
+    int rc = check_factors(ctx, f);
+    if (rc) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    rc = run_loss(pr, f);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (loss) *loss = pr->h_lossout[0];
+    if (rmse) *rmse = pr->nnz > 0 ? std::sqrt(pr->h_lossout[1] / (double)pr->nnz) : 0.0;
+    return SNECT_OK;
+}
+
+int snect_train(snect_problem* pr, snect_factors* f, int32_t start_epoch, int32_t epochs, double* loss,
+                double* rmse)
+{
+    if (!pr) return SNECT_E_ARG;
+    snect_ctx* ctx = pr->ctx;
+    ctx->err.clear();
+    int rc = check_factors(ctx, f);
+    if (rc) return rc;
+    if (epochs < 0 || start_epoch < 0) return set_err(ctx, SNECT_E_ARG, "negative epoch count or start");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const int P = pr->P;
+    for (double& t : pr->t_ms) t = 0.0;
+
+    BlockArgs ba;
+    ba.nz = pr->d_nz; ba.tile_off = pr->d_tile_off; ba.tile_k = pr->d_tile_k; ba.blk_tile = pr->d_blk_tile;
+    ba.perm1 = pr->d_perm1; ba.start1 = pr->d_start1; ba.perm2 = pr->d_perm2; ba.start2 = pr->d_start2;
+    ba.reg1 = pr->d_reg1; ba.reg2 = pr->d_reg2;
+    ba.A = f->A; ba.B = f->B; ba.C = f->C; ba.G = f->G;
+    ba.Spart = pr->d_Spart; ba.Mpart = pr->d_Mpart;
+    ba.P = P; ba.s = 0; ba.I3 = pr->I3; ba.J1 = pr->J1; ba.J2 = pr->J2; ba.J3 = pr->J3;
+    ba.rows1_max = pr->rows1_max; ba.rows2_max = pr->rows2_max; ba.bits_i = pr->bits_i; ba.bits_j = pr->bits_j;
+    ba.lr = (float)pr->lr;
+
+    CoreArgs ca;
+    ca.C = f->C; ca.G = f->G; ca.Spart = pr->d_Spart; ca.Mpart = pr->d_Mpart; ca.cnt3 = pr->d_cnt3;
+    ca.P = P; ca.I3 = pr->I3; ca.J1 = pr->J1; ca.J2 = pr->J2; ca.J3 = pr->J3;
+    ca.lam = (float)pr->lam; ca.etac = (float)(pr->lr * pr->cls); ca.nnz = (double)pr->nnz;
+
+    GraphArgs ga;
+    ga.adj_start = pr->d_adj_start; ga.adj_nbr = pr->d_adj_nbr; ga.adj_w = pr->d_adj_w; ga.deg = pr->d_deg;
+    ga.I2 = pr->I2; ga.J2 = pr->J2;
+    ga.alpha = pr->n_sub > 0 ? (float)(pr->lr * pr->lam_g / pr->n_sub) : 0.f;
+
+    const size_t szA = (size_t)pr->I1 * pr->J1 * 4, szB = (size_t)pr->I2 * pr->J2 * 4, szC = (size_t)pr->I3 * pr->J3 * 4,
+                 szG = (size_t)pr->J1 * pr->J2 * pr->J3 * 4;
+    std::vector<int32_t> order(P);
+    for (int32_t ep = start_epoch; ep < start_epoch + epochs; ++ep) {
+        // keep the last finite epoch's factors
+        HIP_TRY(hipMemcpyAsync(pr->d_bakA, f->A, szA, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(pr->d_bakB, f->B, szB, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(pr->d_bakC, f->C, szC, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(pr->d_bakG, f->G, szG, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipEventRecord(pr->ev[0], st));
+        // (a) network step
+        for (int it = 0; it < pr->n_sub; ++it) {
+            const bool even = (it % 2) == 0;
+            ga.Bin = even ? f->B : pr->d_Btmp;
+            ga.Bout = even ? pr->d_Btmp : f->B;
+            HIP_TRY(launch_graph_step(ga, st));
+        }
+        if (pr->n_sub % 2 == 1) HIP_TRY(hipMemcpyAsync(f->B, pr->d_Btmp, szB, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipEventRecord(pr->ev[1], st));
+        // (b) strata
+        for (int s = 0; s < P; ++s) order[s] = s;
+        seeded_shuffle(order, pr->seed, 2 + (uint64_t)ep);
+        for (int si = 0; si < P; ++si) {
+            ba.s = order[si];
+            if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evb[2 * si], st));
+            HIP_TRY(launch_block_fp32(ba, pr->jp, pr->block_lds, st));
+            if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evb[2 * si + 1], st));
+            HIP_TRY(launch_core_step(ca, st));
+        }
+        HIP_TRY(hipEventRecord(pr->ev[2], st));
+        // (c) loss
+        rc = run_loss(pr, f);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(pr->ev[3], st));
+        HIP_TRY(hipStreamSynchronize(st));
+        float m0 = 0, m1 = 0, m2 = 0;
+        HIP_TRY(hipEventElapsedTime(&m0, pr->ev[0], pr->ev[1]));
+        HIP_TRY(hipEventElapsedTime(&m1, pr->ev[1], pr->ev[2]));
+        HIP_TRY(hipEventElapsedTime(&m2, pr->ev[2], pr->ev[3]));
+        pr->t_ms[0] += m0;
+        pr->t_ms[1] += m1;
+        pr->t_ms[2] += m2;
+        if (pr->per_launch)
+            for (int si = 0; si < P; ++si) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, pr->evb[2 * si], pr->evb[2 * si + 1]));
+                pr->t_ms[3] += ms;
+            }
+        pr->t_ms[4] += pr->per_launch ? P : 0;
+        const double fl = pr->h_lossout[0];
+        const double r = pr->nnz > 0 ? std::sqrt(pr->h_lossout[1] / (double)pr->nnz) : 0.0;
+        if (!std::isfinite(fl) || !std::isfinite(r)) {
+            HIP_TRY(hipMemcpyAsync(f->A, pr->d_bakA, szA, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipMemcpyAsync(f->B, pr->d_bakB, szB, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipMemcpyAsync(f->C, pr->d_bakC, szC, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipMemcpyAsync(f->G, pr->d_bakG, szG, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (loss) loss[ep - start_epoch] = fl;
+            if (rmse) rmse[ep - start_epoch] = r;
+            return set_err(ctx, SNECT_E_DIVERGED, "loss not finite at epoch " + std::to_string(ep));
+        }
+        if (loss) loss[ep - start_epoch] = fl;
+        if (rmse) rmse[ep - start_epoch] = r;
+    }
+    return SNECT_OK;
+}
+
+int snect_decompose(snect_ctx* ctx, const snect_tensor* X, const snect_graph* Y, const snect_params* params,
+                    const snect_factors* init, snect_factors* out, int32_t start_epoch, int32_t epochs, double* loss,
+                    double* rmse)
+{
+    if (!ctx) return SNECT_E_ARG;
+    int rc = check_factors(ctx, init);
+    if (rc) return rc;
+    rc = check_factors(ctx, out);
+    if (rc) return rc;
+    snect_problem* pr = nullptr;
+    rc = snect_problem_create(ctx, X, Y, params, &pr);
+    if (rc) return rc;
+    const size_t szA = (size_t)X->I1 * params->J1 * 4, szB = (size_t)X->I2 * params->J2 * 4,
+                 szC = (size_t)X->I3 * params->J3 * 4, szG = (size_t)params->J1 * params->J2 * params->J3 * 4;
+    hipStream_t st = ctx->stream;
+    hipError_t e = hipSuccess;
+    if (init->A != out->A) e = e ? e : hipMemcpyAsync(out->A, init->A, szA, hipMemcpyDeviceToDevice, st);
+    if (init->B != out->B) e = e ? e : hipMemcpyAsync(out->B, init->B, szB, hipMemcpyDeviceToDevice, st);
+    if (init->C != out->C) e = e ? e : hipMemcpyAsync(out->C, init->C, szC, hipMemcpyDeviceToDevice, st);
+    if (init->G != out->G) e = e ? e : hipMemcpyAsync(out->G, init->G, szG, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) {
+        snect_problem_destroy(pr);
+        return set_err(ctx, SNECT_E_HIP, std::string("copy init: ") + hipGetErrorString(e));
+    }
+    rc = snect_train(pr, out, start_epoch, epochs, loss, rmse);
+    std::string msg = ctx->err;
+    snect_problem_destroy(pr);
+    ctx->err = msg;
+    return rc;
+}
+
+int snect_plan_export(const snect_problem* pr, int32_t epoch, int32_t* perm1, int32_t* perm2, int32_t* strata)
+{
+    if (!pr || epoch < 0) return SNECT_E_ARG;
+    if (perm1) std::memcpy(perm1, pr->perm1.data(), pr->perm1.size() * 4);
+    if (perm2) std::memcpy(perm2, pr->perm2.data(), pr->perm2.size() * 4);
+    if (strata) {
+        std::vector<int32_t> o(pr->P);
+        for (int s = 0; s < pr->P; ++s) o[s] = s;
+        seeded_shuffle(o, pr->seed, 2 + (uint64_t)epoch);
+        std::memcpy(strata, o.data(), o.size() * 4);
+    }
+    return SNECT_OK;
+}
+
+int snect_last_timing(const snect_problem* pr, double* ms5)
+{
+    if (!pr || !ms5) return SNECT_E_ARG;
+    for (int t = 0; t < 5; ++t) ms5[t] = pr->t_ms[t];
+    return SNECT_OK;
+}
+
+int snect_set_profiling(snect_problem* pr, int per_launch)
+{
+    if (!pr) return SNECT_E_ARG;
+    snect_ctx* ctx = pr->ctx;
+    if (per_launch && pr->evb.empty()) {
+        HIP_TRY(hipSetDevice(ctx->device));
+        pr->evb.assign(2 * (size_t)pr->P, nullptr);
+        for (auto& e : pr->evb) HIP_TRY(hipEventCreate(&e));
+    }
+    pr->per_launch = per_launch != 0;
+    return SNECT_OK;
+}
+
+}  // extern "C"
