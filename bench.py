@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-epochs", type=int, default=1)
+    ap.add_argument("--path", choices=["auto", "persistent", "multi"], default="auto")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -83,7 +84,9 @@ def main():
     # warmup epochs, then exactly `steps` timed epochs
     if args.warmup > 0:
         prob.train(*f, epochs=args.warmup, start_epoch=0)
-    prob.set_profiling(True)
+    path = {"auto": sn.PATH_AUTO, "persistent": sn.PATH_PERSISTENT, "multi": sn.PATH_MULTI}[args.path]
+    prob.set_exec(per_launch_timing=True, path=path)
+    chosen = prob.exec_path()
     torch.cuda.synchronize()
     ts = time.perf_counter()
     loss, rmse = prob.train(*f, epochs=args.steps, start_epoch=args.warmup)
@@ -95,18 +98,22 @@ def main():
     value = nnz * args.steps / wall
     log(f"loss {loss} rmse {rmse}", args.quiet)
     log(f"phases ms: graph {tm['graph_ms']:.2f} strata {tm['strata_ms']:.2f} loss {tm['loss_ms']:.2f} "
-        f"block {tm['block_ms']:.2f} over {tm['block_launches']} launches", args.quiet)
+        f"kernel {tm['kernel_ms']:.2f} over {tm['kernel_launches']} launches (path {chosen})", args.quiet)
 
-    # roofline of the dominant kernel (the per-stratum block kernel)
+    # roofline of the dominant kernel: the stratum kernel (one launch per
+    # epoch when persistent, one per stratum otherwise)
     J1, J2, J3 = ranks
     I1, I2, I3 = dims
     P = args.strata
-    launches = max(tm["block_launches"], 1)
-    avg_launch_s = tm["block_ms"] * 1e-3 / launches
-    nnz_per_launch = nnz / P
-    # algorithmic bytes per launch: 8 B per nonzero record streamed once, and
-    # every factor row of the stratum's blocks read once and written once
-    bytes_per_launch = 8.0 * nnz_per_launch + 2.0 * 4.0 * (I1 * J1 + I2 * J2)
+    launches = max(tm["kernel_launches"], 1)
+    avg_launch_s = tm["kernel_ms"] * 1e-3 / launches
+    persistent = chosen == sn.PATH_PERSISTENT
+    strata_per_launch = P if persistent else 1
+    nnz_per_launch = nnz * strata_per_launch / P
+    # algorithmic bytes per stratum: 8 B per nonzero record streamed once; the
+    # moving (patient) rows read and written once per stratum; the stationary
+    # (gene) rows read and written once per launch
+    bytes_per_launch = (8.0 * nnz_per_launch + strata_per_launch * 8.0 * I1 * J1 + 8.0 * I2 * J2)
     flops_per_nnz = 6 * J1 * J2 + 4 * (J1 + J2)
     achieved_gbs = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
     achieved_tf = flops_per_nnz * nnz_per_launch / avg_launch_s / 1e12 if avg_launch_s > 0 else 0.0
@@ -130,7 +137,7 @@ def main():
                    "lambda": 0.01, "lambda_g": 0.1, "lr": 1e-3},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"block_fp32<{J1 if J1 == J2 else max(J1, J2)}>",
+                     "kernel": ("strata_persistent" if persistent else "block_step") + f"<JP={max(J1, J2)}>",
                      "avg_launch_us": avg_launch_s * 1e6, "bytes_per_launch": bytes_per_launch,
                      "alu_tflops": achieved_tf, "alu_frac": achieved_tf / FP32_VECTOR_PEAK_TFLOPS},
         "phases_ms_per_step": {"graph": tm["graph_ms"] / args.steps,

@@ -174,16 +174,30 @@ int snect_plan_export(const snect_problem *prob, int32_t epoch, int32_t *perm1, 
 
 /* Device time of the last snect_train call (milliseconds, summed over its
  * epochs), measured with HIP events on the library stream: [0] network step,
- * [1] strata (block kernels and core steps), [2] loss, [3] block kernels
- * alone and [4] the number of block-kernel launches timed for [3] (both 0
- * unless per-launch timing is on). */
+ * [1] strata (all stratum work), [2] loss, [3] the stratum kernels alone
+ * (per-launch events, only with per-launch timing on) and [4] the number of
+ * stratum-kernel launches timed for [3]. */
 int snect_last_timing(const snect_problem *prob, double *ms5);
 
-/* Per-launch timing of the block kernel: when on, snect_train records a pair
- * of HIP events around every block-kernel launch (no extra host
- * synchronisation) and reports their sum in snect_last_timing [3].
- * Errors: E_ARG, E_HIP. */
-int snect_set_profiling(snect_problem *prob, int per_launch);
+#define SNECT_PATH_AUTO 0       /* persistent kernel when it can be resident */
+#define SNECT_PATH_PERSISTENT 1 /* one cooperative launch per epoch           */
+#define SNECT_PATH_MULTI 2      /* one launch per stratum + a core-step launch */
+
+/* Execution choices; they never change results (both paths are
+ * bit-identical).  per_launch_timing records a pair of HIP events around
+ * every stratum-kernel launch (no extra host synchronisation); path selects
+ * the stratum driver.  SNECT_PATH_PERSISTENT fails with E_UNSUPPORTED at
+ * snect_train if the P workgroups cannot all be resident.  Errors: E_ARG,
+ * E_HIP. */
+typedef struct {
+    int32_t per_launch_timing;
+    int32_t path;
+} snect_exec;
+
+int snect_set_exec(snect_problem *prob, const snect_exec *exec);
+
+/* The stratum driver the next snect_train call will use (SNECT_PATH_*). */
+int snect_exec_path(const snect_problem *prob);
 
 #ifdef __cplusplus
 }

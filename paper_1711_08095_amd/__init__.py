@@ -32,8 +32,10 @@ PRECISION_BF16 = 1
 EXPORTS = (
     "snect_create", "snect_destroy", "snect_last_error", "snect_problem_create",
     "snect_problem_destroy", "snect_problem_info", "snect_train", "snect_evaluate",
-    "snect_decompose", "snect_plan_export", "snect_last_timing", "snect_set_profiling",
+    "snect_decompose", "snect_plan_export", "snect_last_timing", "snect_set_exec",
+    "snect_exec_path",
 )
+PATH_AUTO, PATH_PERSISTENT, PATH_MULTI = 0, 1, 2
 
 
 class SnectError(RuntimeError):
@@ -65,6 +67,10 @@ class Params(ctypes.Structure):
 class Factors(ctypes.Structure):
     _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
                 ("G", ctypes.c_void_p)]
+
+
+class Exec(ctypes.Structure):
+    _fields_ = [("per_launch_timing", ctypes.c_int32), ("path", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -102,7 +108,8 @@ def load(path: str = LIB_PATH):
                                            ctypes.POINTER(Factors), i32, i32, vp, vp]),
         "snect_plan_export": (ctypes.c_int, [vp, i32, vp, vp, vp]),
         "snect_last_timing": (ctypes.c_int, [vp, vp]),
-        "snect_set_profiling": (ctypes.c_int, [vp, ctypes.c_int]),
+        "snect_set_exec": (ctypes.c_int, [vp, ctypes.POINTER(Exec)]),
+        "snect_exec_path": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -264,14 +271,21 @@ class Problem:
                                         strata.ctypes.data), self.ctx.h)
         return dict(perm1=perm1, perm2=perm2, strata=strata)
 
-    def set_profiling(self, per_launch: bool):
-        _check(load().snect_set_profiling(self.h, 1 if per_launch else 0), self.ctx.h)
+    def set_exec(self, per_launch_timing: bool = False, path: int = PATH_AUTO):
+        """snect_set_exec: per-launch timing events and the stratum driver."""
+        e = Exec()
+        e.per_launch_timing = 1 if per_launch_timing else 0
+        e.path = int(path)
+        _check(load().snect_set_exec(self.h, ctypes.byref(e)), self.ctx.h)
+
+    def exec_path(self) -> int:
+        return int(load().snect_exec_path(self.h))
 
     def last_timing(self):
         ms = np.zeros(5)
         _check(load().snect_last_timing(self.h, ms.ctypes.data), self.ctx.h)
-        return dict(graph_ms=ms[0], strata_ms=ms[1], loss_ms=ms[2], block_ms=ms[3],
-                    block_launches=int(ms[4]))
+        return dict(graph_ms=ms[0], strata_ms=ms[1], loss_ms=ms[2], kernel_ms=ms[3],
+                    kernel_launches=int(ms[4]))
 
     def close(self):
         if getattr(self, "h", None):
@@ -288,4 +302,5 @@ class Problem:
 
 
 __all__ = ["load", "Context", "Problem", "Hyper", "SnectError", "EXPORTS", "ERRORS",
-           "PRECISION_FP32", "PRECISION_BF16", "LIB_PATH"]
+           "PRECISION_FP32", "PRECISION_BF16", "LIB_PATH", "PATH_AUTO", "PATH_PERSISTENT",
+           "PATH_MULTI"]

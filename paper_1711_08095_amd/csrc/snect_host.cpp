@@ -10,6 +10,11 @@
 // 64-bit draw u.  Position r of a permutation belongs to block
 // floor(r P / I).  Each block's nonzeros are sorted by (k, i, j) and cut into
 // tiles of at most T entries within one platform.
+//
+// On the device the factor rows live in plan (position) order for the whole
+// of a training call, so every block's rows are one contiguous range; they
+// are gathered from and scattered back to the caller's row order at the
+// start and the end of the call.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +39,7 @@ struct snect_ctx {
     std::string err;
     size_t max_lds = 65536;
     int num_cu = 0;
+    int coop = 0;
     int live_problems = 0;  // problems still referring to this context
 };
 
@@ -73,6 +79,14 @@ void seeded_shuffle(std::vector<int32_t>& v, uint64_t seed, uint64_t stream)
         const int64_t j = (int64_t)(((unsigned __int128)u * (unsigned __int128)(uint64_t)(r + 1)) >> 64);
         std::swap(v[r], v[j]);
     }
+}
+
+std::vector<int32_t> stratum_order(int P, uint64_t seed, int64_t epoch)
+{
+    std::vector<int32_t> o(P);
+    for (int s = 0; s < P; ++s) o[s] = s;
+    seeded_shuffle(o, seed, 2 + (uint64_t)epoch);
+    return o;
 }
 
 int ceil_log2(int64_t n)
@@ -120,12 +134,12 @@ struct snect_problem {
     int64_t nnz = 0, ntiles = 0, ecsr = 0;
     double lam = 0, lam_g = 0, lr = 0, cls = 1;
     uint64_t seed = 0;
-    int32_t rows1_max = 0, rows2_max = 0, bits_i = 0, bits_j = 0, n_sub = 0;
+    int32_t rows1_max = 0, rows2_max = 0, bits_i = 0, bits_j = 0, n_sub = 0, n_reg_wg = 0;
     double dmax = 0;
-    size_t block_lds = 0, loss_lds = 0;
+    size_t strata_lds = 0, block_lds = 0, loss_lds = 0, core_lds = 0;
+    int capacity = 0;
     double plan_s = 0, upload_s = 0;
-    // host copies kept for export
-    std::vector<int32_t> perm1, perm2;
+    std::vector<int32_t> perm1, perm2;  // host copies kept for export
     // device buffers
     std::vector<DevBuf> bufs;
     uint2* d_nz = nullptr;
@@ -135,17 +149,20 @@ struct snect_problem {
     int32_t *d_cnt1 = nullptr, *d_cnt2 = nullptr, *d_cnt3 = nullptr;
     int32_t *d_adj_start = nullptr, *d_adj_nbr = nullptr;
     float *d_adj_w = nullptr, *d_deg = nullptr;
-    float* d_Spart = nullptr;
+    float *d_Ap = nullptr, *d_Bp = nullptr, *d_Btmp = nullptr;
+    float *d_Spart = nullptr, *d_Ssum = nullptr;
     int32_t* d_Mpart = nullptr;
-    float* d_Btmp = nullptr;
-    double* d_partial = nullptr;
-    double* d_lossout = nullptr;
+    int32_t* d_order = nullptr;  // [P]
+    GridBar* d_bar = nullptr;
+    double *d_sse = nullptr, *d_regp = nullptr, *d_net = nullptr, *d_lossout = nullptr;
     double* h_lossout = nullptr;  // pinned
+    int32_t* h_order = nullptr;   // pinned [P]
     float *d_bakA = nullptr, *d_bakB = nullptr, *d_bakC = nullptr, *d_bakG = nullptr;
-    // timing
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    std::vector<hipEvent_t> evb;  // 2 per stratum when per-launch timing is on
+    // execution
+    int path = SNECT_PATH_AUTO;
     bool per_launch = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> evl;  // per-launch timing events
     double t_ms[5] = {0, 0, 0, 0, 0};
 
     template <class T_>
@@ -165,10 +182,18 @@ struct snect_problem {
     {
         for (auto& b : bufs) (void)hipFree(b.p);
         if (h_lossout) (void)hipHostFree(h_lossout);
+        if (h_order) (void)hipHostFree(h_order);
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
-        for (auto& e : evb)
+        for (auto& e : evl)
             if (e) (void)hipEventDestroy(e);
+    }
+    bool persistent_ok() const { return ctx->coop && capacity >= P && strata_lds <= ctx->max_lds; }
+    int chosen_path() const
+    {
+        if (path == SNECT_PATH_MULTI) return SNECT_PATH_MULTI;
+        if (path == SNECT_PATH_PERSISTENT) return SNECT_PATH_PERSISTENT;
+        return persistent_ok() ? SNECT_PATH_PERSISTENT : SNECT_PATH_MULTI;
     }
 };
 
@@ -186,7 +211,10 @@ int snect_create(snect_ctx** out, int device, void* stream)
     if (!out) return SNECT_E_ARG;
     *out = nullptr;
     int n = 0;
-    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SNECT_E_ARG;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        (void)hipGetLastError();
+        return SNECT_E_ARG;
+    }
     snect_ctx* c = new (std::nothrow) snect_ctx();
     if (!c) return SNECT_E_OOM;
     c->device = device;
@@ -199,6 +227,7 @@ int snect_create(snect_ctx** out, int device, void* stream)
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && v > 0)
         c->max_lds = (size_t)v;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess) c->num_cu = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, device) == hipSuccess) c->coop = v;
     *out = c;
     return SNECT_OK;
 }
@@ -206,8 +235,7 @@ int snect_create(snect_ctx** out, int device, void* stream)
 int snect_destroy(snect_ctx* ctx)
 {
     if (!ctx) return SNECT_E_ARG;
-    if (ctx->live_problems > 0)
-        return set_err(ctx, SNECT_E_BUSY, "destroy the context's problems first");
+    if (ctx->live_problems > 0) return set_err(ctx, SNECT_E_BUSY, "destroy the context's problems first");
     delete ctx;
     return SNECT_OK;
 }
@@ -257,30 +285,35 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
             return set_err(ctx, SNECT_E_ARG, "edge weights must be finite and >= 0");
     }
     const int P = pa->strata_P, T = pa->tile_T;
-    const int jp = jp_for(pa->J1, pa->J2);
+    const int J1 = pa->J1, J2 = pa->J2, J3 = pa->J3;
+    const int jp = jp_for(J1, J2);
     if (jp < 0) return set_err(ctx, SNECT_E_RANK, "no kernel for this core size");
     const int rows1_max = (I1 + P - 1) / P, rows2_max = (I2 + P - 1) / P;
     const int bits_i = std::max(1, ceil_log2(rows1_max)), bits_j = std::max(1, ceil_log2(rows2_max));
     if (bits_i + bits_j > kMaxLocalBits)
         return set_err(ctx, SNECT_E_UNSUPPORTED, "blocks too large to pack; raise strata_P");
     if (I3 > 4096) return set_err(ctx, SNECT_E_UNSUPPORTED, "at most 4096 platforms");
-    const size_t blds = block_lds_bytes(jp, rows1_max, rows2_max, I3, pa->J1, pa->J2);
-    const size_t llds = loss_lds_bytes(jp, rows1_max, rows2_max, I3);
-    if (blds > ctx->max_lds || llds > ctx->max_lds)
-        return set_err(ctx, SNECT_E_UNSUPPORTED,
-                       "a block's rows do not fit in LDS (" + std::to_string(blds) + " bytes); raise strata_P");
     if ((int64_t)P * P * I3 >= (int64_t(1) << 31)) return set_err(ctx, SNECT_E_UNSUPPORTED, "too many blocks");
+    const size_t slds = strata_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3);
+    const size_t blds = slds;
+    const size_t llds = loss_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3);
+    const size_t clds = core_lds_bytes(I3, J1, J2, J3, kCoreThreads);
+    if (blds > ctx->max_lds || llds > ctx->max_lds || clds > ctx->max_lds)
+        return set_err(ctx, SNECT_E_UNSUPPORTED,
+                       "a block's rows and the core do not fit in LDS (" + std::to_string(blds) +
+                           " bytes); raise strata_P");
 
     snect_problem* pr = new (std::nothrow) snect_problem();
     if (!pr) return set_err(ctx, SNECT_E_OOM, "host allocation");
     pr->ctx = ctx;
     pr->I1 = I1; pr->I2 = I2; pr->I3 = I3;
-    pr->J1 = pa->J1; pr->J2 = pa->J2; pr->J3 = pa->J3;
+    pr->J1 = J1; pr->J2 = J2; pr->J3 = J3;
     pr->P = P; pr->T = T; pr->jp = jp; pr->nnz = nnz;
     pr->lam = pa->lambda; pr->lam_g = pa->lambda_g; pr->lr = pa->lr; pr->cls = pa->core_lr_scale;
     pr->seed = pa->seed;
     pr->rows1_max = rows1_max; pr->rows2_max = rows2_max; pr->bits_i = bits_i; pr->bits_j = bits_j;
-    pr->block_lds = blds; pr->loss_lds = llds;
+    pr->strata_lds = slds; pr->block_lds = blds; pr->loss_lds = llds; pr->core_lds = clds;
+    pr->n_reg_wg = (I1 + 255) / 256 + (I2 + 255) / 256 + 1;
 
     int rc = SNECT_OK;
     try {
@@ -291,9 +324,6 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
             cnt2[X->j[t]]++;
             cnt3[X->k[t]]++;
         }
-        std::vector<float> reg1(I1, 0.f), reg2(I2, 0.f);
-        for (int r = 0; r < I1; ++r) reg1[r] = cnt1[r] ? (float)(pa->lambda / cnt1[r]) : 0.f;
-        for (int r = 0; r < I2; ++r) reg2[r] = cnt2[r] ? (float)(pa->lambda / cnt2[r]) : 0.f;
         // ---------------- permutations and blocks ----------------
         pr->perm1.resize(I1);
         pr->perm2.resize(I2);
@@ -301,37 +331,47 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         for (int r = 0; r < I2; ++r) pr->perm2[r] = r;
         seeded_shuffle(pr->perm1, pa->seed, 0);
         seeded_shuffle(pr->perm2, pa->seed, 1);
-        std::vector<int32_t> blk1(I1), loc1(I1), blk2(I2), loc2(I2), start1(P + 1), start2(P + 1);
+        std::vector<int32_t> pos1(I1), pos2(I2), blk1(I1), blk2(I2), start1(P + 1), start2(P + 1);
         for (int p = 0; p <= P; ++p) {
             start1[p] = (int32_t)(((int64_t)p * I1 + P - 1) / P);
             start2[p] = (int32_t)(((int64_t)p * I2 + P - 1) / P);
         }
         for (int64_t r = 0; r < I1; ++r) {
-            const int b = (int)(r * P / I1);
-            blk1[pr->perm1[r]] = b;
-            loc1[pr->perm1[r]] = (int32_t)(r - start1[b]);
+            pos1[pr->perm1[r]] = (int32_t)r;
+            blk1[pr->perm1[r]] = (int32_t)(r * P / I1);
         }
         for (int64_t r = 0; r < I2; ++r) {
-            const int b = (int)(r * P / I2);
-            blk2[pr->perm2[r]] = b;
-            loc2[pr->perm2[r]] = (int32_t)(r - start2[b]);
+            pos2[pr->perm2[r]] = (int32_t)r;
+            blk2[pr->perm2[r]] = (int32_t)(r * P / I2);
+        }
+        // per-row data in position order
+        std::vector<float> reg1p(I1), reg2p(I2);
+        std::vector<int32_t> cnt1p(I1), cnt2p(I2);
+        for (int r = 0; r < I1; ++r) {
+            const int32_t row = pr->perm1[r];
+            cnt1p[r] = cnt1[row];
+            reg1p[r] = cnt1[row] ? (float)(pa->lambda / cnt1[row]) : 0.f;
+        }
+        for (int r = 0; r < I2; ++r) {
+            const int32_t row = pr->perm2[r];
+            cnt2p[r] = cnt2[row];
+            reg2p[r] = cnt2[row] ? (float)(pa->lambda / cnt2[row]) : 0.f;
         }
         // ---------------- bucket by (block, k), sort by (i, j) ----------------
         const int64_t nb = (int64_t)P * P * I3;
         std::vector<int64_t> bstart(nb + 1, 0);
-        std::vector<int32_t> bucket(nnz);
-        for (int64_t t = 0; t < nnz; ++t) {
-            const int64_t b = ((int64_t)blk1[X->i[t]] * P + blk2[X->j[t]]) * I3 + X->k[t];
-            bucket[t] = (int32_t)b;
-            bstart[b + 1]++;
-        }
-        for (int64_t b = 0; b < nb; ++b) bstart[b + 1] += bstart[b];
         std::vector<int32_t> ord(nnz);
         {
+            std::vector<int32_t> bucket(nnz);
+            for (int64_t t = 0; t < nnz; ++t) {
+                const int64_t b = ((int64_t)blk1[X->i[t]] * P + blk2[X->j[t]]) * I3 + X->k[t];
+                bucket[t] = (int32_t)b;
+                bstart[b + 1]++;
+            }
+            for (int64_t b = 0; b < nb; ++b) bstart[b + 1] += bstart[b];
             std::vector<int64_t> fill(bstart.begin(), bstart.end() - 1);
             for (int64_t t = 0; t < nnz; ++t) ord[fill[bucket[t]]++] = (int32_t)t;
         }
-        std::vector<int32_t>().swap(bucket);
         std::atomic<int> dup{0};
         parallel_for(nb, [&](int64_t b, int) {
             const int64_t s = bstart[b], e = bstart[b + 1];
@@ -349,7 +389,8 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         }
         // ---------------- tiles ----------------
         std::vector<int64_t> tiles_in_bucket(nb + 1, 0);
-        for (int64_t b = 0; b < nb; ++b) tiles_in_bucket[b + 1] = tiles_in_bucket[b] + (bstart[b + 1] - bstart[b] + T - 1) / T;
+        for (int64_t b = 0; b < nb; ++b)
+            tiles_in_bucket[b + 1] = tiles_in_bucket[b] + (bstart[b + 1] - bstart[b] + T - 1) / T;
         const int64_t ntiles = tiles_in_bucket[nb];
         if (ntiles >= (int64_t(1) << 31)) {
             delete pr;
@@ -365,49 +406,43 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         }
         tile_off[ntiles] = (int32_t)nnz;
         for (int64_t blk = 0; blk <= (int64_t)P * P; ++blk) blk_tile[blk] = (int32_t)tiles_in_bucket[blk * I3];
-        // ---------------- pack records (with in-tile gene chains) ----------------
+        // ---------------- pack records with the tile's gene-slot order ----------------
         std::vector<uint2> nz(nnz);
-        const unsigned hw = std::max(1u, std::min(std::thread::hardware_concurrency(), 16u));
-        std::vector<std::vector<int16_t>> lastpos(hw, std::vector<int16_t>(rows2_max, -1));
-        parallel_for(ntiles, [&](int64_t tl, int w) {
-            std::vector<int16_t>& lp = lastpos[w];
-            const int32_t s = tile_off[tl], e = tile_off[tl + 1];
-            for (int32_t z = s; z < e; ++z) {
-                const int32_t t = ord[z];
-                const uint32_t il = (uint32_t)loc1[X->i[t]], jl = (uint32_t)loc2[X->j[t]];
-                const int pos = z - s;
-                const int prev = lp[jl] >= 0 ? lp[jl] : pos;
-                lp[jl] = (int16_t)pos;
-                nz[z].x = il | (jl << bits_i) | ((uint32_t)prev << (bits_i + bits_j));
-                nz[z].y = 0;
-                std::memcpy(&nz[z].y, &X->x[t], 4);
+        const int sh_f = bits_i + bits_j;
+        parallel_for(ntiles, [&](int64_t tl, int) {
+            const int32_t s = tile_off[tl], e = tile_off[tl + 1], n = e - s;
+            int32_t jl[kTileMax], slot_of[kTileMax], at_slot[kTileMax];
+            for (int t = 0; t < n; ++t) {
+                const int32_t id = ord[s + t];
+                jl[t] = pos2[X->j[id]] - start2[blk2[X->j[id]]];
+                at_slot[t] = t;
             }
-            // last occurrence of each gene row in the tile
-            for (int32_t z = e - 1; z >= s; --z) {
-                const uint32_t jl = (nz[z].x >> bits_i) & ((1u << bits_j) - 1u);
-                if (lp[jl] == z - s) {
-                    nz[z].x |= 1u << (bits_i + bits_j + kJprevBits);
-                    lp[jl] = -1;
-                }
+            // stable order by gene row: slot -> position
+            std::stable_sort(at_slot, at_slot + n, [&](int32_t u, int32_t v) { return jl[u] < jl[v]; });
+            for (int sl = 0; sl < n; ++sl) slot_of[at_slot[sl]] = sl;
+            for (int t = 0; t < n; ++t) {
+                const int32_t id = ord[s + t];
+                const uint32_t il = (uint32_t)(pos1[X->i[id]] - start1[blk1[X->i[id]]]);
+                nz[s + t].x = il | ((uint32_t)jl[t] << bits_i) | ((uint32_t)slot_of[t] << sh_f);
+                std::memcpy(&nz[s + t].y, &X->x[id], 4);
             }
-            for (int32_t z = s; z < e; ++z) lp[(nz[z].x >> bits_i) & ((1u << bits_j) - 1u)] = -1;
         });
-        // ---------------- network: symmetric CSR, repeated pairs summed ----------------
+        // ---------------- network: symmetric CSR over gene positions ----------------
         std::vector<std::pair<int64_t, float>> ed;
         ed.reserve(2 * E);
         for (int64_t e = 0; e < E; ++e) {
             const float w = Y->w ? Y->w[e] : 1.f;
-            ed.push_back({(int64_t)Y->u[e] * I2 + Y->v[e], w});
-            ed.push_back({(int64_t)Y->v[e] * I2 + Y->u[e], w});
+            const int64_t a = pos2[Y->u[e]], b = pos2[Y->v[e]];
+            ed.push_back({a * I2 + b, w});
+            ed.push_back({b * I2 + a, w});
         }
         std::sort(ed.begin(), ed.end(), [](const std::pair<int64_t, float>& a, const std::pair<int64_t, float>& b) {
             return a.first < b.first;
         });
         std::vector<int32_t> adj_start(I2 + 1, 0), adj_nbr;
         std::vector<float> adj_w;
-        std::vector<double> degd(I2, 0.0);
         for (size_t e = 0; e < ed.size(); ++e) {
-            if (!adj_nbr.empty() && e > 0 && ed[e].first == ed[e - 1].first) {
+            if (e > 0 && ed[e].first == ed[e - 1].first) {
                 adj_w.back() += ed[e].second;
             } else {
                 adj_nbr.push_back((int32_t)(ed[e].first % I2));
@@ -417,14 +452,13 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         }
         for (int r = 0; r < I2; ++r) adj_start[r + 1] += adj_start[r];
         std::vector<float> deg(I2, 0.f);
+        double dmax = 0.0;
         for (int r = 0; r < I2; ++r) {
             double d = 0.0;
             for (int e = adj_start[r]; e < adj_start[r + 1]; ++e) d += (double)adj_w[e];
-            degd[r] = d;
             deg[r] = (float)d;
+            dmax = std::max(dmax, d);
         }
-        double dmax = 0.0;
-        for (int r = 0; r < I2; ++r) dmax = std::max(dmax, degd[r]);
         pr->dmax = dmax;
         pr->ecsr = (int64_t)adj_nbr.size();
         pr->n_sub = 0;
@@ -435,6 +469,7 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         // ---------------- upload ----------------
         const double t_up0 = now_s();
         HIP_TRY(hipSetDevice(ctx->device));
+        const size_t ni = (size_t)I3 * J1 * J2, ng = (size_t)J1 * J2 * J3;
         pr->d_nz = pr->alloc<uint2>(nnz, rc);
         pr->d_tile_off = pr->alloc<int32_t>(ntiles + 1, rc);
         pr->d_tile_k = pr->alloc<int32_t>(ntiles, rc);
@@ -452,20 +487,28 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         pr->d_adj_nbr = pr->alloc<int32_t>(adj_nbr.size(), rc);
         pr->d_adj_w = pr->alloc<float>(adj_w.size(), rc);
         pr->d_deg = pr->alloc<float>(I2, rc);
-        pr->d_Spart = pr->alloc<float>((size_t)P * I3 * pa->J1 * pa->J2, rc);
+        pr->d_Ap = pr->alloc<float>((size_t)I1 * J1, rc);
+        pr->d_Bp = pr->alloc<float>((size_t)I2 * J2, rc);
+        pr->d_Btmp = pr->alloc<float>((size_t)I2 * J2, rc);
+        pr->d_Spart = pr->alloc<float>((size_t)P * ni, rc);
+        pr->d_Ssum = pr->alloc<float>(std::max(ni, ng), rc);
         pr->d_Mpart = pr->alloc<int32_t>((size_t)P * I3, rc);
-        pr->d_Btmp = pr->alloc<float>((size_t)I2 * pa->J2, rc);
-        pr->d_partial = pr->alloc<double>((size_t)P * P, rc);
+        pr->d_order = pr->alloc<int32_t>(P, rc);
+        pr->d_bar = pr->alloc<GridBar>(1, rc);
+        pr->d_sse = pr->alloc<double>((size_t)P * P, rc);
+        pr->d_regp = pr->alloc<double>(pr->n_reg_wg, rc);
+        pr->d_net = pr->alloc<double>(I2, rc);
         pr->d_lossout = pr->alloc<double>(2, rc);
-        pr->d_bakA = pr->alloc<float>((size_t)I1 * pa->J1, rc);
-        pr->d_bakB = pr->alloc<float>((size_t)I2 * pa->J2, rc);
-        pr->d_bakC = pr->alloc<float>((size_t)I3 * pa->J3, rc);
-        pr->d_bakG = pr->alloc<float>((size_t)pa->J1 * pa->J2 * pa->J3, rc);
+        pr->d_bakA = pr->alloc<float>((size_t)I1 * J1, rc);
+        pr->d_bakB = pr->alloc<float>((size_t)I2 * J2, rc);
+        pr->d_bakC = pr->alloc<float>((size_t)I3 * J3, rc);
+        pr->d_bakG = pr->alloc<float>(ng, rc);
         if (rc) {
             delete pr;
             return set_err(ctx, SNECT_E_OOM, "device allocation failed");
         }
-        if (hipHostMalloc((void**)&pr->h_lossout, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc((void**)&pr->h_lossout, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&pr->h_order, (size_t)P * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
             delete pr;
             return set_err(ctx, SNECT_E_OOM, "pinned host allocation failed");
         }
@@ -479,26 +522,27 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         he = he ? he : up(pr->d_tile_off, tile_off.data(), tile_off.size() * 4);
         he = he ? he : up(pr->d_tile_k, tile_k.data(), tile_k.size() * 4);
         he = he ? he : up(pr->d_blk_tile, blk_tile.data(), blk_tile.size() * 4);
-        he = he ? he : up(pr->d_perm1, pr->perm1.data(), I1 * 4);
-        he = he ? he : up(pr->d_perm2, pr->perm2.data(), I2 * 4);
-        he = he ? he : up(pr->d_start1, start1.data(), (P + 1) * 4);
-        he = he ? he : up(pr->d_start2, start2.data(), (P + 1) * 4);
-        he = he ? he : up(pr->d_reg1, reg1.data(), I1 * 4);
-        he = he ? he : up(pr->d_reg2, reg2.data(), I2 * 4);
-        he = he ? he : up(pr->d_cnt1, cnt1.data(), I1 * 4);
-        he = he ? he : up(pr->d_cnt2, cnt2.data(), I2 * 4);
-        he = he ? he : up(pr->d_cnt3, cnt3.data(), I3 * 4);
-        he = he ? he : up(pr->d_adj_start, adj_start.data(), (I2 + 1) * 4);
+        he = he ? he : up(pr->d_perm1, pr->perm1.data(), (size_t)I1 * 4);
+        he = he ? he : up(pr->d_perm2, pr->perm2.data(), (size_t)I2 * 4);
+        he = he ? he : up(pr->d_start1, start1.data(), (size_t)(P + 1) * 4);
+        he = he ? he : up(pr->d_start2, start2.data(), (size_t)(P + 1) * 4);
+        he = he ? he : up(pr->d_reg1, reg1p.data(), (size_t)I1 * 4);
+        he = he ? he : up(pr->d_reg2, reg2p.data(), (size_t)I2 * 4);
+        he = he ? he : up(pr->d_cnt1, cnt1p.data(), (size_t)I1 * 4);
+        he = he ? he : up(pr->d_cnt2, cnt2p.data(), (size_t)I2 * 4);
+        he = he ? he : up(pr->d_cnt3, cnt3.data(), (size_t)I3 * 4);
+        he = he ? he : up(pr->d_adj_start, adj_start.data(), (size_t)(I2 + 1) * 4);
         he = he ? he : up(pr->d_adj_nbr, adj_nbr.data(), adj_nbr.size() * 4);
         he = he ? he : up(pr->d_adj_w, adj_w.data(), adj_w.size() * 4);
-        he = he ? he : up(pr->d_deg, deg.data(), I2 * 4);
+        he = he ? he : up(pr->d_deg, deg.data(), (size_t)I2 * 4);
         he = he ? he : hipStreamSynchronize(st);
-        he = he ? he : prepare_kernels(jp, blds, llds);
+        he = he ? he : prepare_kernels(jp, slds, llds, clds);
         for (int t = 0; t < 4 && he == hipSuccess; ++t) he = hipEventCreate(&pr->ev[t]);
         if (he != hipSuccess) {
             delete pr;
             return set_err(ctx, SNECT_E_HIP, std::string("upload: ") + hipGetErrorString(he));
         }
+        pr->capacity = (ctx->coop && slds <= ctx->max_lds) ? persistent_capacity(jp, slds) : 0;
         pr->upload_s = now_s() - t_up0;
         ctx->live_problems++;
     } catch (const std::bad_alloc&) {
@@ -545,23 +589,58 @@ static int check_factors(snect_ctx* ctx, const snect_factors* f)
     return SNECT_OK;
 }
 
-// Loss of the current factors into pr->h_lossout (synchronises).
-static int run_loss(snect_problem* pr, const snect_factors* f)
+static GraphArgs graph_args(const snect_problem* pr)
+{
+    GraphArgs ga;
+    ga.Bin = pr->d_Bp;
+    ga.Bout = pr->d_Btmp;
+    ga.adj_start = pr->d_adj_start;
+    ga.adj_nbr = pr->d_adj_nbr;
+    ga.adj_w = pr->d_adj_w;
+    ga.deg = pr->d_deg;
+    ga.net_part = pr->d_net;
+    ga.I2 = pr->I2;
+    ga.J2 = pr->J2;
+    ga.alpha = pr->n_sub > 0 ? (float)(pr->lr * pr->lam_g / pr->n_sub) : 0.f;
+    return ga;
+}
+
+// Loss of the factors held in position order (d_Ap, d_Bp, C, G) into
+// pr->h_lossout (asynchronous; the caller synchronises).
+static int run_loss(snect_problem* pr, const float* C, const float* G)
 {
     snect_ctx* ctx = pr->ctx;
     LossArgs la;
     la.nz = pr->d_nz; la.tile_off = pr->d_tile_off; la.tile_k = pr->d_tile_k; la.blk_tile = pr->d_blk_tile;
-    la.perm1 = pr->d_perm1; la.start1 = pr->d_start1; la.perm2 = pr->d_perm2; la.start2 = pr->d_start2;
+    la.start1 = pr->d_start1; la.start2 = pr->d_start2;
     la.cnt1 = pr->d_cnt1; la.cnt2 = pr->d_cnt2; la.cnt3 = pr->d_cnt3;
-    la.A = f->A; la.B = f->B; la.C = f->C; la.G = f->G;
+    la.Ap = pr->d_Ap; la.Bp = pr->d_Bp; la.C = C; la.G = G;
     la.adj_start = pr->d_adj_start; la.adj_nbr = pr->d_adj_nbr; la.adj_w = pr->d_adj_w;
-    la.partial = pr->d_partial; la.out = pr->d_lossout;
+    la.sse_part = pr->d_sse; la.reg_part = pr->d_regp; la.net_part = pr->d_net; la.out = pr->d_lossout;
     la.P = pr->P; la.I1 = pr->I1; la.I2 = pr->I2; la.I3 = pr->I3;
     la.J1 = pr->J1; la.J2 = pr->J2; la.J3 = pr->J3;
     la.rows1_max = pr->rows1_max; la.rows2_max = pr->rows2_max; la.bits_i = pr->bits_i; la.bits_j = pr->bits_j;
+    la.n_reg_wg = pr->n_reg_wg;
     la.lam = pr->lam; la.lam_g = pr->lam_g;
-    HIP_TRY(launch_loss(la, pr->jp, pr->loss_lds, ctx->stream));
+    GraphArgs ga = graph_args(pr);
+    HIP_TRY(launch_loss(la, ga, pr->jp, pr->loss_lds, ctx->stream));
     HIP_TRY(hipMemcpyAsync(pr->h_lossout, pr->d_lossout, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    return SNECT_OK;
+}
+
+static int to_positions(snect_problem* pr, const snect_factors* f)
+{
+    snect_ctx* ctx = pr->ctx;
+    HIP_TRY(launch_permute(f->A, pr->d_Ap, pr->d_perm1, pr->I1, pr->J1, 1, ctx->stream));
+    HIP_TRY(launch_permute(f->B, pr->d_Bp, pr->d_perm2, pr->I2, pr->J2, 1, ctx->stream));
+    return SNECT_OK;
+}
+
+static int from_positions(snect_problem* pr, snect_factors* f)
+{
+    snect_ctx* ctx = pr->ctx;
+    HIP_TRY(launch_permute(pr->d_Ap, f->A, pr->d_perm1, pr->I1, pr->J1, 0, ctx->stream));
+    HIP_TRY(launch_permute(pr->d_Bp, f->B, pr->d_perm2, pr->I2, pr->J2, 0, ctx->stream));
     return SNECT_OK;
 }
 
@@ -573,8 +652,8 @@ int snect_evaluate(snect_problem* pr, const snect_factors* f, double* loss, doub
     int rc = check_factors(ctx, f);
     if (rc) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
-    rc = run_loss(pr, f);
-    if (rc) return rc;
+    if ((rc = to_positions(pr, f))) return rc;
+    if ((rc = run_loss(pr, f->C, f->G))) return rc;
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     if (loss) *loss = pr->h_lossout[0];
     if (rmse) *rmse = pr->nnz > 0 ? std::sqrt(pr->h_lossout[1] / (double)pr->nnz) : 0.0;
@@ -593,63 +672,79 @@ int snect_train(snect_problem* pr, snect_factors* f, int32_t start_epoch, int32_
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     const int P = pr->P;
+    const int path = pr->chosen_path();
+    if (path == SNECT_PATH_PERSISTENT && !pr->persistent_ok())
+        return set_err(ctx, SNECT_E_UNSUPPORTED, "the persistent stratum kernel cannot be resident for this P");
     for (double& t : pr->t_ms) t = 0.0;
+    const int nlaunch = path == SNECT_PATH_PERSISTENT ? 1 : P;
+    if (pr->per_launch && (int)pr->evl.size() < 2 * nlaunch) {
+        const size_t have = pr->evl.size();
+        pr->evl.resize(2 * (size_t)nlaunch, nullptr);
+        for (size_t t = have; t < pr->evl.size(); ++t) HIP_TRY(hipEventCreate(&pr->evl[t]));
+    }
 
-    BlockArgs ba;
-    ba.nz = pr->d_nz; ba.tile_off = pr->d_tile_off; ba.tile_k = pr->d_tile_k; ba.blk_tile = pr->d_blk_tile;
-    ba.perm1 = pr->d_perm1; ba.start1 = pr->d_start1; ba.perm2 = pr->d_perm2; ba.start2 = pr->d_start2;
-    ba.reg1 = pr->d_reg1; ba.reg2 = pr->d_reg2;
-    ba.A = f->A; ba.B = f->B; ba.C = f->C; ba.G = f->G;
-    ba.Spart = pr->d_Spart; ba.Mpart = pr->d_Mpart;
-    ba.P = P; ba.s = 0; ba.I3 = pr->I3; ba.J1 = pr->J1; ba.J2 = pr->J2; ba.J3 = pr->J3;
-    ba.rows1_max = pr->rows1_max; ba.rows2_max = pr->rows2_max; ba.bits_i = pr->bits_i; ba.bits_j = pr->bits_j;
-    ba.lr = (float)pr->lr;
+    StratArgs sa;
+    sa.nz = pr->d_nz; sa.tile_off = pr->d_tile_off; sa.tile_k = pr->d_tile_k; sa.blk_tile = pr->d_blk_tile;
+    sa.start1 = pr->d_start1; sa.start2 = pr->d_start2;
+    sa.reg1 = pr->d_reg1; sa.reg2 = pr->d_reg2; sa.cnt3 = pr->d_cnt3;
+    sa.Ap = pr->d_Ap; sa.Bp = pr->d_Bp; sa.C = f->C; sa.G = f->G;
+    sa.Spart = pr->d_Spart; sa.Mpart = pr->d_Mpart; sa.Ssum = pr->d_Ssum;
+    sa.order = pr->d_order; sa.bar = pr->d_bar;
+    sa.P = P; sa.s = 0; sa.I3 = pr->I3; sa.J1 = pr->J1; sa.J2 = pr->J2; sa.J3 = pr->J3;
+    sa.rows1_max = pr->rows1_max; sa.rows2_max = pr->rows2_max; sa.bits_i = pr->bits_i; sa.bits_j = pr->bits_j;
+    sa.lr = (float)pr->lr; sa.lam = (float)pr->lam; sa.etac = (float)(pr->lr * pr->cls);
+    sa.nnz = (double)pr->nnz;
+    GraphArgs ga = graph_args(pr);
 
-    CoreArgs ca;
-    ca.C = f->C; ca.G = f->G; ca.Spart = pr->d_Spart; ca.Mpart = pr->d_Mpart; ca.cnt3 = pr->d_cnt3;
-    ca.P = P; ca.I3 = pr->I3; ca.J1 = pr->J1; ca.J2 = pr->J2; ca.J3 = pr->J3;
-    ca.lam = (float)pr->lam; ca.etac = (float)(pr->lr * pr->cls); ca.nnz = (double)pr->nnz;
-
-    GraphArgs ga;
-    ga.adj_start = pr->d_adj_start; ga.adj_nbr = pr->d_adj_nbr; ga.adj_w = pr->d_adj_w; ga.deg = pr->d_deg;
-    ga.I2 = pr->I2; ga.J2 = pr->J2;
-    ga.alpha = pr->n_sub > 0 ? (float)(pr->lr * pr->lam_g / pr->n_sub) : 0.f;
-
-    const size_t szA = (size_t)pr->I1 * pr->J1 * 4, szB = (size_t)pr->I2 * pr->J2 * 4, szC = (size_t)pr->I3 * pr->J3 * 4,
-                 szG = (size_t)pr->J1 * pr->J2 * pr->J3 * 4;
-    std::vector<int32_t> order(P);
+    const size_t szA = (size_t)pr->I1 * pr->J1 * 4, szB = (size_t)pr->I2 * pr->J2 * 4,
+                 szC = (size_t)pr->I3 * pr->J3 * 4, szG = (size_t)pr->J1 * pr->J2 * pr->J3 * 4;
+    if ((rc = to_positions(pr, f))) return rc;
     for (int32_t ep = start_epoch; ep < start_epoch + epochs; ++ep) {
         // keep the last finite epoch's factors
-        HIP_TRY(hipMemcpyAsync(pr->d_bakA, f->A, szA, hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipMemcpyAsync(pr->d_bakB, f->B, szB, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(pr->d_bakA, pr->d_Ap, szA, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(pr->d_bakB, pr->d_Bp, szB, hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipMemcpyAsync(pr->d_bakC, f->C, szC, hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipMemcpyAsync(pr->d_bakG, f->G, szG, hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipEventRecord(pr->ev[0], st));
-        // (a) network step
+        // (a) network step, Jacobi sub-steps ping-ponging through Btmp
         for (int it = 0; it < pr->n_sub; ++it) {
             const bool even = (it % 2) == 0;
-            ga.Bin = even ? f->B : pr->d_Btmp;
-            ga.Bout = even ? pr->d_Btmp : f->B;
-            HIP_TRY(launch_graph_step(ga, st));
+            ga.Bin = even ? pr->d_Bp : pr->d_Btmp;
+            ga.Bout = even ? pr->d_Btmp : pr->d_Bp;
+            HIP_TRY(launch_graph_step(ga, pr->jp, st));
         }
-        if (pr->n_sub % 2 == 1) HIP_TRY(hipMemcpyAsync(f->B, pr->d_Btmp, szB, hipMemcpyDeviceToDevice, st));
+        if (pr->n_sub % 2 == 1) HIP_TRY(hipMemcpyAsync(pr->d_Bp, pr->d_Btmp, szB, hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipEventRecord(pr->ev[1], st));
         // (b) strata
-        for (int s = 0; s < P; ++s) order[s] = s;
-        seeded_shuffle(order, pr->seed, 2 + (uint64_t)ep);
-        for (int si = 0; si < P; ++si) {
-            ba.s = order[si];
-            if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evb[2 * si], st));
-            HIP_TRY(launch_block_fp32(ba, pr->jp, pr->block_lds, st));
-            if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evb[2 * si + 1], st));
-            HIP_TRY(launch_core_step(ca, st));
+        const std::vector<int32_t> order = stratum_order(P, pr->seed, ep);
+        if (path == SNECT_PATH_PERSISTENT) {
+            // the pinned order buffer is free: the previous epoch ended with a
+            // stream synchronisation
+            std::memcpy(pr->h_order, order.data(), (size_t)P * 4);
+            HIP_TRY(hipMemcpyAsync(pr->d_order, pr->h_order, (size_t)P * 4, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemsetAsync(pr->d_bar, 0, sizeof(GridBar), st));
+            if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[0], st));
+            HIP_TRY(launch_strata_persistent(sa, pr->jp, pr->strata_lds, st));
+            if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[1], st));
+        } else {
+            for (int si = 0; si < P; ++si) {
+                sa.s = order[si];
+                if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[2 * si], st));
+                HIP_TRY(launch_block(sa, pr->jp, pr->block_lds, st));
+                if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[2 * si + 1], st));
+                HIP_TRY(launch_core_step(sa, pr->core_lds, st));
+            }
         }
         HIP_TRY(hipEventRecord(pr->ev[2], st));
         // (c) loss
-        rc = run_loss(pr, f);
-        if (rc) return rc;
+        if ((rc = run_loss(pr, f->C, f->G))) return rc;
         HIP_TRY(hipEventRecord(pr->ev[3], st));
         HIP_TRY(hipStreamSynchronize(st));
+        if (path == SNECT_PATH_PERSISTENT) {
+            GridBar hb;
+            HIP_TRY(hipMemcpy(&hb, pr->d_bar, sizeof(GridBar), hipMemcpyDeviceToHost));
+            if (hb.err) return set_err(ctx, SNECT_E_HIP, "grid barrier timed out in the stratum kernel");
+        }
         float m0 = 0, m1 = 0, m2 = 0;
         HIP_TRY(hipEventElapsedTime(&m0, pr->ev[0], pr->ev[1]));
         HIP_TRY(hipEventElapsedTime(&m1, pr->ev[1], pr->ev[2]));
@@ -657,28 +752,30 @@ int snect_train(snect_problem* pr, snect_factors* f, int32_t start_epoch, int32_
         pr->t_ms[0] += m0;
         pr->t_ms[1] += m1;
         pr->t_ms[2] += m2;
-        if (pr->per_launch)
-            for (int si = 0; si < P; ++si) {
+        if (pr->per_launch) {
+            for (int l = 0; l < nlaunch; ++l) {
                 float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, pr->evb[2 * si], pr->evb[2 * si + 1]));
+                HIP_TRY(hipEventElapsedTime(&ms, pr->evl[2 * l], pr->evl[2 * l + 1]));
                 pr->t_ms[3] += ms;
             }
-        pr->t_ms[4] += pr->per_launch ? P : 0;
+            pr->t_ms[4] += nlaunch;
+        }
         const double fl = pr->h_lossout[0];
         const double r = pr->nnz > 0 ? std::sqrt(pr->h_lossout[1] / (double)pr->nnz) : 0.0;
-        if (!std::isfinite(fl) || !std::isfinite(r)) {
-            HIP_TRY(hipMemcpyAsync(f->A, pr->d_bakA, szA, hipMemcpyDeviceToDevice, st));
-            HIP_TRY(hipMemcpyAsync(f->B, pr->d_bakB, szB, hipMemcpyDeviceToDevice, st));
-            HIP_TRY(hipMemcpyAsync(f->C, pr->d_bakC, szC, hipMemcpyDeviceToDevice, st));
-            HIP_TRY(hipMemcpyAsync(f->G, pr->d_bakG, szG, hipMemcpyDeviceToDevice, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            if (loss) loss[ep - start_epoch] = fl;
-            if (rmse) rmse[ep - start_epoch] = r;
-            return set_err(ctx, SNECT_E_DIVERGED, "loss not finite at epoch " + std::to_string(ep));
-        }
         if (loss) loss[ep - start_epoch] = fl;
         if (rmse) rmse[ep - start_epoch] = r;
+        if (!std::isfinite(fl) || !std::isfinite(r)) {
+            HIP_TRY(hipMemcpyAsync(pr->d_Ap, pr->d_bakA, szA, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipMemcpyAsync(pr->d_Bp, pr->d_bakB, szB, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipMemcpyAsync(f->C, pr->d_bakC, szC, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipMemcpyAsync(f->G, pr->d_bakG, szG, hipMemcpyDeviceToDevice, st));
+            if ((rc = from_positions(pr, f))) return rc;
+            HIP_TRY(hipStreamSynchronize(st));
+            return set_err(ctx, SNECT_E_DIVERGED, "loss not finite at epoch " + std::to_string(ep));
+        }
     }
+    if ((rc = from_positions(pr, f))) return rc;
+    HIP_TRY(hipStreamSynchronize(st));
     return SNECT_OK;
 }
 
@@ -719,9 +816,7 @@ int snect_plan_export(const snect_problem* pr, int32_t epoch, int32_t* perm1, in
     if (perm1) std::memcpy(perm1, pr->perm1.data(), pr->perm1.size() * 4);
     if (perm2) std::memcpy(perm2, pr->perm2.data(), pr->perm2.size() * 4);
     if (strata) {
-        std::vector<int32_t> o(pr->P);
-        for (int s = 0; s < pr->P; ++s) o[s] = s;
-        seeded_shuffle(o, pr->seed, 2 + (uint64_t)epoch);
+        const std::vector<int32_t> o = stratum_order(pr->P, pr->seed, epoch);
         std::memcpy(strata, o.data(), o.size() * 4);
     }
     return SNECT_OK;
@@ -734,17 +829,20 @@ int snect_last_timing(const snect_problem* pr, double* ms5)
     return SNECT_OK;
 }
 
-int snect_set_profiling(snect_problem* pr, int per_launch)
+int snect_set_exec(snect_problem* pr, const snect_exec* ex)
+{
+    if (!pr || !ex) return SNECT_E_ARG;
+    if (ex->path < SNECT_PATH_AUTO || ex->path > SNECT_PATH_MULTI)
+        return set_err(pr->ctx, SNECT_E_ARG, "unknown path");
+    pr->per_launch = ex->per_launch_timing != 0;
+    pr->path = ex->path;
+    return SNECT_OK;
+}
+
+int snect_exec_path(const snect_problem* pr)
 {
     if (!pr) return SNECT_E_ARG;
-    snect_ctx* ctx = pr->ctx;
-    if (per_launch && pr->evb.empty()) {
-        HIP_TRY(hipSetDevice(ctx->device));
-        pr->evb.assign(2 * (size_t)pr->P, nullptr);
-        for (auto& e : pr->evb) HIP_TRY(hipEventCreate(&e));
-    }
-    pr->per_launch = per_launch != 0;
-    return SNECT_OK;
+    return pr->chosen_path();
 }
 
 }  // extern "C"

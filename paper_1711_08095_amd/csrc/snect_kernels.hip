@@ -1,17 +1,39 @@
-// gfx950 kernels of the SNeCT stratified SGD (arXiv:1711.08095, Algorithm 1
+// gfx950 kernels of the SNeCT stratified SGD (arXiv:1711.08095: Algorithm 1
 // with the gradients of Eq. 5, the network term of Eq. 4, the objective of
 // Eq. 3).
 //
-// Block kernel: one wavefront per block (p, q) of a stratum.  The block's
-// patient rows and gene rows live in LDS for the whole stratum; H_k = G x3 c_k
-// for every platform k is built in LDS from the stratum's frozen C and G.
-// Each tile (<= 64 nonzeros of one platform) is one wavefront step: lane t
-// takes nonzero t, reads its rows from before the tile, forms
-// w1 = H_k b_j, w2 = H_k^T a_i, e = x - a_i . w1, stages e*w1 and e*w2, and
-// the last lane of each patient run / gene chain sums its row's terms in a
-// fixed order and writes the updated row.  The block's sum of e a (x) b per
-// platform, needed by the core step, accumulates on the matrix cores
-// (v_mfma_f32_16x16x4f32 / 32x32x2f32) from staged pre-tile rows.
+// Factor rows are kept in plan (position) order, so the rows of a block are
+// one contiguous range.  A block (p, q) is processed by one workgroup of four
+// wavefronts: its patient rows and gene rows sit in LDS, H_k = G x3 c_k for
+// every platform k is built in LDS from the stratum's frozen C and G, and
+// each tile (<= 64 nonzeros of one platform) is one step in which lane t of
+// every wavefront stands for nonzero t and wavefront w owns the factor
+// columns c = w, w+4, ...:
+//   1. every wavefront reads the tile's rows as they were before the tile;
+//      wavefront w forms w1[x] = (H_k b_j)[x] and w2[y] = (H_k^T a_i)[y] for
+//      its columns and its share of x~ = a_i . w1;
+//   2. after a barrier all wavefronts know e = x - x~; each stages e*w1 (in
+//      tile order), e*w2 (in the tile's gene-sorted slot order) and the
+//      matrix-core operands for its columns;
+//   3. after a barrier a segmented wavefront scan sums the terms of every
+//      patient run (contiguous: tiles are sorted by i) and every gene run
+//      (contiguous in slot order) in a fixed tree order; the last lane of a
+//      run writes the row's owned columns; wavefront w also accumulates the
+//      block's sum of e a (x) b over nonzeros 16w..16w+15 on the matrix cores;
+//   4. a barrier ends the tile.
+// Staging arrays are column-major with a pitch of 66 words, which keeps the
+// column writes and the matrix-core operand reads free of bank conflicts.
+//
+// Two drivers share that block step and all of the arithmetic:
+//   strata_persistent: one cooperative launch per epoch; P workgroups stay
+//     resident, workgroup q keeps gene block q in LDS for the whole epoch and
+//     visits patient block (q - s) mod P in stratum s; two grid barriers per
+//     stratum bracket a distributed reduction of the blocks' sums, after
+//     which every workgroup applies the same core step to its LDS copy of C
+//     and G;
+//   block_step + core_step: one launch per stratum plus one for the core step
+//     (used when the persistent kernel cannot be co-resident).
+// Both give bit-identical results.
 #include <hip/hip_runtime.h>
 
 #include "snect_internal.h"
@@ -21,41 +43,61 @@ namespace snect {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+constexpr int kTS = 66;  // pitch (words) of a staged column
+constexpr int kWaves = kStratThreads / 64;
+
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
-// LDS carve-up of the block kernel (floats unless noted).
-struct BlockLds {
-    int a_off, b_off, ra_off, rb_off, h_off, sta_off, stb_off, as_off, es_off, sk_off, mk_off, jp_off;
+// Compiler-only ordering point: memory accesses are not moved across it
+// (bounds how many LDS values the scheduler keeps in flight).
+__device__ inline void lds_order_fence() { asm volatile("" ::: "memory"); }
+
+// ---------------------------------------------------------------------------
+// LDS carve-up of the stratum kernels (in 4-byte words).
+// ---------------------------------------------------------------------------
+struct StratLds {
+    int a, b, ra, rb, c, g, h, sa, sb, as, es, xtp, slotj, skw, sk, mk, tco, tck, red, msum, cgt, flag;
     int total;
 };
 
-__host__ __device__ inline BlockLds block_lds_layout(int jp, int rows1_max, int rows2_max, int I3,
-                                                     int J1, int J2)
+__host__ __device__ inline int up4(int o) { return (o + 3) & ~3; }
+
+__host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2,
+                                                     int J3)
 {
-    const int rs = row_stride(jp), mp = mfma_dim(jp);
-    BlockLds L;
+    const int rs = row_stride(jp), mp = mfma_dim(jp), j12 = J1 * J2;
+    const int nch = (j12 + kCoreChunk - 1) / kCoreChunk;
+    StratLds L;
     int o = 0;
-    L.a_off = o;  o += rows1_max * rs;
-    L.b_off = o;  o += rows2_max * rs;
-    L.ra_off = o; o += rows1_max;
-    L.rb_off = o; o += rows2_max;
-    o = (o + 3) & ~3;
-    L.h_off = o;  o += I3 * jp * jp;
-    o = (o + 3) & ~3;
-    L.sta_off = o; o += kTileMax * rs;
-    L.stb_off = o; o += kTileMax * rs;
-    L.as_off = o;  o += kTileMax * mp;
-    L.es_off = o;  o += kTileMax * mp;
-    L.sk_off = o;  o += I3 * J1 * J2;
-    L.mk_off = o;  o += I3;          // int32 counts
-    L.jp_off = o;  o += kTileMax;    // int32 chain links
+    L.a = o;     o = up4(o + rows1_max * rs);
+    L.b = o;     o = up4(o + rows2_max * rs);
+    L.ra = o;    o = up4(o + rows1_max);
+    L.rb = o;    o = up4(o + rows2_max);
+    L.c = o;     o = up4(o + I3 * J3);
+    L.g = o;     o = up4(o + j12 * J3);
+    L.h = o;     o = up4(o + I3 * jp * jp);
+    L.sa = o;    o = up4(o + jp * kTS);
+    L.sb = o;    o = up4(o + jp * kTS);
+    L.as = o;    o = up4(o + mp * kTS);
+    L.es = o;    o = up4(o + mp * kTS);
+    L.xtp = o;   o = up4(o + kWaves * 64);
+    L.slotj = o; o = up4(o + kTileMax);
+    L.skw = o;   o = up4(o + kWaves * I3 * j12);
+    L.sk = o;    o = up4(o + I3 * j12);
+    L.mk = o;    o = up4(o + I3);
+    L.tco = o;   o = up4(o + kTileCache + 2);
+    L.tck = o;   o = up4(o + kTileCache);
+    L.red = o;   o = up4(o + (kStratThreads > I3 * J3 * nch ? kStratThreads : I3 * J3 * nch));
+    L.msum = o;  o = up4(o + 2 * I3);          // doubles
+    L.cgt = o;   o = up4(o + I3 * J3 + j12 * J3);
+    L.flag = o;  o = up4(o + 1);
     L.total = o;
     return L;
 }
 
-size_t block_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2)
+size_t strata_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3)
 {
-    return align16(sizeof(float) * (size_t)block_lds_layout(jp, rows1_max, rows2_max, I3, J1, J2).total);
+    return align16(4 * (size_t)strat_lds_layout(jp, rows1_max, rows2_max, I3, J1, J2, J3).total);
 }
 
 int jp_for(int J1, int J2)
@@ -66,20 +108,141 @@ int jp_for(int J1, int J2)
     return -1;
 }
 
-// MFMA accumulator of the per-platform S = sum_t e_t a_t (x) b_t.
+// ---------------------------------------------------------------------------
+// Shared arithmetic (identical instruction sequence in every driver)
+// ---------------------------------------------------------------------------
+
+// H_k[x][y] = sum_c G[x,y,c] C[k,c], zero padded to JP x JP.
+template <int JP>
+__device__ void build_h(float* Hs, const float* Cs, const float* Gs, int I3, int J1, int J2, int J3, int tid,
+                        int nthr)
+{
+    for (int idx = tid; idx < I3 * JP * JP; idx += nthr) {
+        const int k = idx / (JP * JP), xy = idx - k * JP * JP, x = xy / JP, y = xy - x * JP;
+        float h = 0.f;
+        if (x < J1 && y < J2)
+            for (int c = 0; c < J3; ++c) h = fmaf(Gs[(x * J2 + y) * J3 + c], Cs[k * J3 + c], h);
+        Hs[idx] = h;
+    }
+}
+
+// Stratum sum of one item of S over the blocks: chunks of kRedChunk
+// consecutive blocks are summed in ascending order, then the chunk sums in
+// ascending order.
+__device__ inline float chunk_sum(const float* Spart, int ni, int item, int p0, int p1)
+{
+    float v[kRedChunk];
+#pragma unroll
+    for (int u = 0; u < kRedChunk; ++u) v[u] = p0 + u < p1 ? Spart[(size_t)(p0 + u) * ni + item] : 0.f;
+    float s = 0.f;
+#pragma unroll
+    for (int u = 0; u < kRedChunk; ++u) s += v[u];
+    return s;
+}
+
+// Sums items [i0, i1) of the stratum into dst[item - i0] using the whole
+// workgroup (red: nthr floats of LDS).
+__device__ void reduce_items(const float* Spart, int P, int ni, int i0, int i1, float* dst, float* red, int tid,
+                             int nthr)
+{
+    const int nch = (P + kRedChunk - 1) / kRedChunk;
+    const int per_pass = nthr / nch > 0 ? nthr / nch : 1;
+    for (int base = i0; base < i1; base += per_pass) {
+        const int items = (i1 - base) < per_pass ? (i1 - base) : per_pass;
+        __syncthreads();
+        if (tid < items * nch) {
+            const int it = tid / nch, ch = tid - it * nch;
+            const int p0 = ch * kRedChunk, p1 = (p0 + kRedChunk) < P ? (p0 + kRedChunk) : P;
+            red[tid] = chunk_sum(Spart, ni, base + it, p0, p1);
+        }
+        __syncthreads();
+        if (tid < items) {
+            float s = 0.f;
+            for (int ch = 0; ch < nch; ++ch) s += red[tid * nch + ch];
+            dst[base + tid - i0] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// m_k = sum over blocks of the per-block counts (integer adds: exact in any
+// order).  cnt is I3 ints of LDS scratch; msum receives doubles.
+__device__ void stratum_counts(const int32_t* Mpart, int P, int I3, int* cnt, double* msum, int tid, int nthr)
+{
+    for (int k = tid; k < I3; k += nthr) cnt[k] = 0;
+    __syncthreads();
+    for (int idx = tid; idx < P * I3; idx += nthr) atomicAdd(&cnt[idx % I3], Mpart[idx]);
+    __syncthreads();
+    for (int k = tid; k < I3; k += nthr) msum[k] = (double)cnt[k];
+    __syncthreads();
+}
+
+// Core / platform-factor step from the stratum sums S (I3 x J1J2) and the
+// counts m_k: one mean-gradient step of size etac,
+//   C[k][c] -= etac/m (-sum_ab G0[ab][c] S_k[ab] + lam m_k/n3[k] C0[k][c])
+//   G[ab][c] -= etac/m (-sum_k S_k[ab] C0[k][c] + lam m/nnz G0[ab][c]).
+// The C sums over ab run in chunks of kCoreChunk (red: I3*J3*nch floats),
+// then the chunks in ascending order.  New C goes to newC, new G to newG
+// (neither may alias C0 / G0); the caller synchronises afterwards.
+__device__ void core_update(const float* C0, const float* G0, const float* S, const double* mk,
+                            const int32_t* cnt3, int I3, int J12, int J3, float lam, float etac, double nnz,
+                            float* red, float* newC, float* newG, int tid, int nthr)
+{
+    double m = 0.0;
+    for (int k = 0; k < I3; ++k) m += mk[k];
+    if (m <= 0.0) {
+        for (int idx = tid; idx < I3 * J3; idx += nthr) newC[idx] = C0[idx];
+        for (int idx = tid; idx < J12 * J3; idx += nthr) newG[idx] = G0[idx];
+        return;
+    }
+    const float inv_m = (float)(1.0 / m);
+    const int nch = (J12 + kCoreChunk - 1) / kCoreChunk;
+    const int nc = I3 * J3;
+    for (int u = tid; u < nc * nch; u += nthr) {
+        const int item = u / nch, ch = u - item * nch;
+        const int k = item / J3, c = item - k * J3;
+        const int ab1 = (ch + 1) * kCoreChunk < J12 ? (ch + 1) * kCoreChunk : J12;
+        float g = 0.f;
+        for (int ab = ch * kCoreChunk; ab < ab1; ++ab) g = fmaf(-G0[ab * J3 + c], S[k * J12 + ab], g);
+        red[u] = g;
+    }
+    const float greg = lam * (float)(m / nnz);
+    for (int idx = tid; idx < J12 * J3; idx += nthr) {
+        const int ab = idx / J3, c = idx - ab * J3;
+        float g = 0.f;
+        for (int k = 0; k < I3; ++k) g = fmaf(-S[k * J12 + ab], C0[k * J3 + c], g);
+        g = fmaf(greg, G0[idx], g);
+        newG[idx] = fmaf(-etac, g * inv_m, G0[idx]);
+    }
+    __syncthreads();
+    for (int item = tid; item < nc; item += nthr) {
+        const int k = item / J3;
+        float g = 0.f;
+        for (int ch = 0; ch < nch; ++ch) g += red[item * nch + ch];
+        if (mk[k] > 0.0) g = fmaf(lam * (float)(mk[k] / (double)cnt3[k]), C0[item], g);
+        newC[item] = fmaf(-etac, g * inv_m, C0[item]);
+    }
+}
+
+// MFMA accumulator of the per-platform S = sum_t e_t a_t (x) b_t.  Staged
+// operands are column-major, element (t, c) at c*kTS + t.
 template <int MP> struct SAcc;
 
 template <> struct SAcc<16> {
     floatx4 v;
     __device__ void zero() { v = floatx4{0.f, 0.f, 0.f, 0.f}; }
-    // staged operands are [64][16]: step s covers nonzeros 4s..4s+3 and lane l
-    // supplies A[l%16][l/16] = a_{4s+l/16}[l%16] and B[l/16][l%16] likewise,
-    // which is element 64 s + l of the staging arrays
-    __device__ void accumulate(const float* As, const float* Es, int n, int lane)
+    // v_mfma_f32_16x16x4f32: step s covers nonzeros 4s..4s+3; lane l supplies
+    // A[l%16][l/16] = a_{4s+l/16}[l%16] and B[l/16][l%16] = (e b)_{4s+l/16}[l%16].
+    // Wavefront w takes nonzeros 16w..16w+15, i.e. steps 4w..4w+3.
+    __device__ void accumulate(const float* As, const float* Es, int n, int w, int lane)
     {
-        const int steps = (n + 3) >> 2;
-        for (int s = 0; s < steps; ++s)
-            v = __builtin_amdgcn_mfma_f32_16x16x4f32(As[s * 64 + lane], Es[s * 64 + lane], v, 0, 0, 0);
+        const int s_end = (n + 3) >> 2;
+        const int col = (lane & 15) * kTS + (lane >> 4);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int s = 4 * w + u;
+            if (s < s_end) v = __builtin_amdgcn_mfma_f32_16x16x4f32(As[col + 4 * s], Es[col + 4 * s], v, 0, 0, 0);
+        }
     }
     // output element (row 4*(l/16)+r, column l%16) sits in register r of lane l
     __device__ void flush(float* Sk, int J1, int J2, int lane)
@@ -100,13 +263,18 @@ template <> struct SAcc<32> {
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r] = 0.f;
     }
-    // staged operands are [64][32]: step s covers nonzeros 2s, 2s+1 and lane l
-    // supplies a_{2s+l/32}[l%32], i.e. element 64 s + l
-    __device__ void accumulate(const float* As, const float* Es, int n, int lane)
+    // v_mfma_f32_32x32x2f32: step s covers nonzeros 2s, 2s+1; lane l supplies
+    // a_{2s+l/32}[l%32] and (e b)_{2s+l/32}[l%32].  Wavefront w takes steps
+    // 8w..8w+7.
+    __device__ void accumulate(const float* As, const float* Es, int n, int w, int lane)
     {
-        const int steps = (n + 1) >> 1;
-        for (int s = 0; s < steps; ++s)
-            v = __builtin_amdgcn_mfma_f32_32x32x2f32(As[s * 64 + lane], Es[s * 64 + lane], v, 0, 0, 0);
+        const int s_end = (n + 1) >> 1;
+        const int col = (lane & 31) * kTS + (lane >> 5);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int s = 8 * w + u;
+            if (s < s_end) v = __builtin_amdgcn_mfma_f32_32x32x2f32(As[col + 2 * s], Es[col + 2 * s], v, 0, 0, 0);
+        }
     }
     // output element (row 8*(r/4) + 4*(l/32) + r%4, column l%32) in register r
     __device__ void flush(float* Sk, int J1, int J2, int lane)
@@ -120,277 +288,577 @@ template <> struct SAcc<32> {
     }
 };
 
-// ---------------------------------------------------------------------------
-// Block kernel (FP32)
-// ---------------------------------------------------------------------------
+// Contiguous rows [row0, row0+nrows) of a position-ordered factor into LDS
+// rows of stride RS (padding columns are left as they are: zero).
+__device__ inline void load_rows(float* dst, const float* src, int row0, int nrows, int J, int RS, int tid,
+                                 int nthr)
+{
+    constexpr int U = 8;  // loads in flight per thread
+    const float* s = src + (size_t)row0 * J;
+    const int total = nrows * J;
+    for (int base = tid; base < total; base += U * nthr) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * nthr;
+            v[u] = idx < total ? s[idx] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * nthr;
+            if (idx < total) {
+                const int l = idx / J, c = idx - l * J;
+                dst[l * RS + c] = v[u];
+            }
+        }
+    }
+}
+
+__device__ inline void store_rows(float* dst, const float* src, int row0, int nrows, int J, int RS, int tid,
+                                  int nthr)
+{
+    float* d = dst + (size_t)row0 * J;
+    for (int idx = tid; idx < nrows * J; idx += nthr) {
+        const int l = idx / J, c = idx - l * J;
+        d[idx] = src[l * RS + c];
+    }
+}
+
+// Tile metadata of tiles [base, base + kTileCache] (offsets one further).
+__device__ inline void load_tile_cache(const StratArgs& a, int* tco, int* tck, int base, int t1, int tid,
+                                       int nthr)
+{
+    for (int u = tid; u < kTileCache + 2; u += nthr) {
+        const int t = base + u;
+        tco[u] = t <= t1 ? a.tile_off[t] : 0;
+        if (u < kTileCache) tck[u] = t < t1 ? a.tile_k[t] : 0;
+    }
+}
+
+// Inclusive segmented scan over the lanes of a wavefront: lane l returns the
+// sum of v over lanes head..l (head <= l), added in a fixed tree order.
+__device__ inline float seg_scan(float v, int lane, int head)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const float t = __shfl_up(v, d);
+        if (lane - d >= head) v += t;
+    }
+    return v;
+}
+
+// Position of the highest set bit of `heads` at or below `lane`.
+__device__ inline int run_head(unsigned long long heads, int lane)
+{
+    const unsigned long long m = lane == 63 ? heads : (heads & ((2ull << lane) - 1ull));
+    return m ? 63 - __clzll(m) : 0;
+}
+
+struct TileLds {
+    float *Ab, *Bb;
+    const float *rA, *rB, *Hs;
+    float *sA, *sB, *As, *Es, *xtp;
+    int* slotJ;
+    float* Skw;   // [kWaves][I3*J1*J2]
+    int* Mk;
+    int *tco, *tck;
+};
+
+// The tiles of block (p, q), run by the whole workgroup (kStratThreads
+// threads).  L.Ab/L.Bb hold the block's rows; L.Skw receives each
+// wavefront's per-platform sums, L.Mk the block's counts.
 template <int JP>
-__global__ __launch_bounds__(64) void block_fp32(BlockArgs a)
+__device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, int tid)
 {
     constexpr int RS = row_stride(JP);
     constexpr int MP = mfma_dim(JP);
-    extern __shared__ float lds[];
-    const int lane = threadIdx.x;
-    const int p = blockIdx.x;
-    const int q = (p + a.s) % a.P;
-    const BlockLds L = block_lds_layout(JP, a.rows1_max, a.rows2_max, a.I3, a.J1, a.J2);
-    float* Ab = lds + L.a_off;
-    float* Bb = lds + L.b_off;
-    float* rA = lds + L.ra_off;
-    float* rB = lds + L.rb_off;
-    float* Hs = lds + L.h_off;
-    float* stA = lds + L.sta_off;
-    float* stB = lds + L.stb_off;
-    float* As = lds + L.as_off;
-    float* Es = lds + L.es_off;
-    float* Sk = lds + L.sk_off;
-    int* Mk = reinterpret_cast<int*>(lds + L.mk_off);
-    int* Jl = reinterpret_cast<int*>(lds + L.jp_off);
-
-    const int J1 = a.J1, J2 = a.J2, J3 = a.J3, I3 = a.I3;
-    const int s1 = a.start1[p], r1 = a.start1[p + 1] - s1;
-    const int s2 = a.start2[q], r2 = a.start2[q + 1] - s2;
-
-    // gather the block's rows (zero-padded to the row stride)
-    for (int idx = lane; idx < r1 * RS; idx += 64) {
-        const int l = idx / RS, c = idx - l * RS;
-        Ab[idx] = c < J1 ? a.A[(size_t)a.perm1[s1 + l] * J1 + c] : 0.f;
-    }
-    for (int idx = lane; idx < r2 * RS; idx += 64) {
-        const int l = idx / RS, c = idx - l * RS;
-        Bb[idx] = c < J2 ? a.B[(size_t)a.perm2[s2 + l] * J2 + c] : 0.f;
-    }
-    for (int l = lane; l < r1; l += 64) rA[l] = a.reg1[a.perm1[s1 + l]];
-    for (int l = lane; l < r2; l += 64) rB[l] = a.reg2[a.perm2[s2 + l]];
-    // H_k[x][y] = sum_c G[x,y,c] C[k,c] for every platform (zero padded)
-    for (int idx = lane; idx < I3 * JP * JP; idx += 64) {
-        const int k = idx / (JP * JP), xy = idx - k * JP * JP, x = xy / JP, y = xy - x * JP;
-        float h = 0.f;
-        if (x < J1 && y < J2)
-            for (int c = 0; c < J3; ++c) h += a.G[(x * J2 + y) * J3 + c] * a.C[k * J3 + c];
-        Hs[idx] = h;
-    }
-    for (int idx = lane; idx < I3 * J1 * J2; idx += 64) Sk[idx] = 0.f;
-    for (int k = lane; k < I3; k += 64) Mk[k] = 0;
-    __syncthreads();
-
+    constexpr int QN = (JP + kWaves - 1) / kWaves;  // owned factor columns per wavefront
+    constexpr int QM = MP / kWaves;                  // owned operand columns per wavefront
+    const int lane = tid & 63, w = tid >> 6;
+    const int J1 = a.J1, J2 = a.J2, J12 = J1 * J2;
     const uint32_t mask_i = (1u << a.bits_i) - 1u, mask_j = (1u << a.bits_j) - 1u;
-    const int sh_j = a.bits_i, sh_f = a.bits_i + a.bits_j;
+    const int sh_j = a.bits_i, sh_r = a.bits_i + a.bits_j;
     const int blk = p * a.P + q;
     const int t0 = a.blk_tile[blk], t1 = a.blk_tile[blk + 1];
+    if (t0 >= t1) return;
+    int base = t0;
+    load_tile_cache(a, L.tco, L.tck, base, t1, tid, kStratThreads);
+    __syncthreads();
 
     SAcc<MP> acc;
     acc.zero();
+    float* Skmine = L.Skw + w * a.I3 * J12;
     int curk = -1;
     uint2 wnext = make_uint2(0u, 0u);
-    if (t0 < t1) {
-        const int off = a.tile_off[t0], n = a.tile_off[t0 + 1] - off;
+    {
+        const int off = L.tco[0], n = L.tco[1] - off;
         if (lane < n) wnext = a.nz[off + lane];
     }
     for (int tl = t0; tl < t1; ++tl) {
-        const int off = a.tile_off[tl];
-        const int n = a.tile_off[tl + 1] - off;
-        const int k = a.tile_k[tl];
+        if (tl - base == kTileCache) {
+            base = tl;
+            load_tile_cache(a, L.tco, L.tck, base, t1, tid, kStratThreads);
+            __syncthreads();
+        }
+        const int u = tl - base;
+        const int off = L.tco[u];
+        const int n = L.tco[u + 1] - off;
+        const int k = L.tck[u];
         const uint2 wv = wnext;
         if (tl + 1 < t1) {  // prefetch the next tile's records
-            const int o2 = a.tile_off[tl + 1], n2 = a.tile_off[tl + 2] - o2;
+            const int o2 = L.tco[u + 1], n2 = L.tco[u + 2] - o2;
             wnext = lane < n2 ? a.nz[o2 + lane] : make_uint2(0u, 0u);
         }
         if (k != curk) {
-            if (curk >= 0) acc.flush(Sk + curk * J1 * J2, J1, J2, lane);
+            if (curk >= 0) acc.flush(Skmine + curk * J12, J1, J2, lane);
             acc.zero();
             curk = k;
         }
         const bool act = lane < n;
-        const uint32_t w = wv.x;
+        const uint32_t wd = wv.x;
         const float x = __uint_as_float(wv.y);
-        const int il = act ? (int)(w & mask_i) : -1;
-        const int jl = act ? (int)((w >> sh_j) & mask_j) : 0;
-        const int jprev = (int)((w >> sh_f) & 63u);
-        const bool jlast = act && ((w >> (sh_f + kJprevBits)) & 1u);
+        const int il = act ? (int)(wd & mask_i) : -1;
+        const int jl = act ? (int)((wd >> sh_j) & mask_j) : 0;
+        const int jrank = (int)(wd >> sh_r);
 
+        // 1. rows before the tile; owned columns of w1 and w2; share of x~
         float av[JP], bv[JP];
 #pragma unroll
         for (int c = 0; c < JP; ++c) {
-            av[c] = act ? Ab[il * RS + c] : 0.f;
-            bv[c] = act ? Bb[jl * RS + c] : 0.f;
+            av[c] = act ? L.Ab[il * RS + c] : 0.f;
+            bv[c] = act ? L.Bb[jl * RS + c] : 0.f;
         }
-        const float* H = Hs + k * JP * JP;
-        float w1[JP], w2[JP];
+        const float* H = L.Hs + k * JP * JP;
+        float w1q[QN], w2q[QN], aq[QN];
+        float xw = 0.f;
 #pragma unroll
-        for (int c = 0; c < JP; ++c) { w1[c] = 0.f; w2[c] = 0.f; }
+        for (int qq = 0; qq < QN; ++qq) {
+            const int c = w + kWaves * qq;
+            float t1v = 0.f, t2v = 0.f, ac = 0.f;
+            if (c < JP) {
 #pragma unroll
-        for (int x_ = 0; x_ < JP; ++x_)
+                for (int y = 0; y < JP; ++y) t1v = fmaf(H[c * JP + y], bv[y], t1v);
 #pragma unroll
-            for (int y = 0; y < JP; ++y) {
-                const float h = H[x_ * JP + y];
-                w1[x_] = fmaf(h, bv[y], w1[x_]);
-                w2[y] = fmaf(av[x_], h, w2[y]);
+                for (int x_ = 0; x_ < JP; ++x_) t2v = fmaf(av[x_], H[x_ * JP + c], t2v);
+                ac = act ? L.Ab[il * RS + c] : 0.f;
+                xw = fmaf(ac, t1v, xw);
             }
-        float xt = 0.f;
+            w1q[qq] = t1v;
+            w2q[qq] = t2v;
+            aq[qq] = ac;
+            if constexpr (JP > 16) lds_order_fence();
+        }
+        L.xtp[w * 64 + lane] = xw;
+        __syncthreads();
+
+        // 2. residual; stage row terms and matrix-core operands
+        float xt = L.xtp[lane];
 #pragma unroll
-        for (int c = 0; c < JP; ++c) xt = fmaf(av[c], w1[c], xt);
+        for (int ww = 1; ww < kWaves; ++ww) xt += L.xtp[ww * 64 + lane];
         const float e = act ? x - xt : 0.f;
-
-        // stage row terms, MFMA operands and gene-chain links
 #pragma unroll
-        for (int c = 0; c < JP; ++c) {
-            stA[lane * RS + c] = e * w1[c];
-            stB[lane * RS + c] = e * w2[c];
-        }
-#pragma unroll
-        for (int c = 0; c < MP; ++c) {
-            As[lane * MP + c] = c < JP ? av[c] : 0.f;
-            Es[lane * MP + c] = c < JP ? e * bv[c] : 0.f;
-        }
-        Jl[lane] = jprev;
-        __syncthreads();
-
-        acc.accumulate(As, Es, n, lane);
-
-        // patient runs are contiguous (tiles are sorted by i): the last lane
-        // of a run sums the run in ascending order
-        const int il_up = __shfl_up(il, 1);
-        const int il_dn = __shfl_down(il, 1);
-        const bool ifirst = act && (lane == 0 || il_up != il);
-        const bool ilast = act && (lane == 63 || il_dn != il);
-        const unsigned long long heads = __ballot(ifirst);
-        if (ilast) {
-            const unsigned long long m = lane == 63 ? heads : (heads & ((2ull << lane) - 1ull));
-            const int head = 63 - __clzll(m);
-            float sum[JP];
-#pragma unroll
-            for (int c = 0; c < JP; ++c) sum[c] = 0.f;
-            for (int u = head; u <= lane; ++u)
-#pragma unroll
-                for (int c = 0; c < JP; ++c) sum[c] += stA[u * RS + c];
-            const float cr = (float)(lane - head + 1) * rA[il];
-#pragma unroll
-            for (int c = 0; c < JP; ++c) Ab[il * RS + c] = av[c] + a.lr * (sum[c] - cr * av[c]);
-        }
-        // gene rows: follow the chain of earlier occurrences in the tile
-        if (jlast) {
-            float sum[JP];
-#pragma unroll
-            for (int c = 0; c < JP; ++c) sum[c] = stB[lane * RS + c];
-            int u = lane, pv = jprev, cnt = 1;
-            while (pv != u && cnt < kTileMax) {
-#pragma unroll
-                for (int c = 0; c < JP; ++c) sum[c] += stB[pv * RS + c];
-                u = pv;
-                pv = Jl[u];
-                ++cnt;
+        for (int qq = 0; qq < QN; ++qq) {
+            const int c = w + kWaves * qq;
+            if (c < JP) {
+                L.sA[c * kTS + lane] = e * w1q[qq];
+                if (act) L.sB[c * kTS + jrank] = e * w2q[qq];
             }
-            const float cr = (float)cnt * rB[jl];
-#pragma unroll
-            for (int c = 0; c < JP; ++c) Bb[jl * RS + c] = bv[c] + a.lr * (sum[c] - cr * bv[c]);
         }
-        if (lane == 0) Mk[k] += n;
+#pragma unroll
+        for (int qm = 0; qm < QM; ++qm) {
+            const int c = w + kWaves * qm;
+            float av_c = 0.f, eb_c = 0.f;
+            if (c < JP && act) {
+                av_c = qm < QN ? aq[qm < QN ? qm : 0] : L.Ab[il * RS + c];
+                eb_c = e * L.Bb[jl * RS + c];
+            }
+            L.As[c * kTS + lane] = av_c;
+            L.Es[c * kTS + lane] = eb_c;
+        }
+        if (w == 0 && act) L.slotJ[jrank] = jl;
+        __syncthreads();
+
+        // 3. matrix-core sums; fixed-order run sums; owned columns of the rows
+        acc.accumulate(L.As, L.Es, n, w, lane);
+        {
+            const int il_up = __shfl_up(il, 1), il_dn = __shfl_down(il, 1);
+            const bool ifirst = act && (lane == 0 || il_up != il);
+            const bool ilast = act && (lane == 63 || il_dn != il);
+            const int head = run_head(__ballot(ifirst), lane);
+            const float cr = act ? (float)(lane - head + 1) * L.rA[il] : 0.f;
+#pragma unroll
+            for (int qq = 0; qq < QN; ++qq) {
+                const int c = w + kWaves * qq;
+                if (c < JP) {
+                    const float v = seg_scan(L.sA[c * kTS + lane], lane, head);
+                    if (ilast) L.Ab[il * RS + c] = fmaf(a.lr, v - cr * aq[qq], aq[qq]);
+                }
+            }
+        }
+        {
+            const int sj = lane < n ? L.slotJ[lane] : -1;
+            const int sj_up = __shfl_up(sj, 1), sj_dn = __shfl_down(sj, 1);
+            const bool jfirst = lane < n && (lane == 0 || sj_up != sj);
+            const bool jlast = lane < n && (lane == 63 || sj_dn != sj);
+            const int head = run_head(__ballot(jfirst), lane);
+            const float cr = lane < n ? (float)(lane - head + 1) * L.rB[sj] : 0.f;
+#pragma unroll
+            for (int qq = 0; qq < QN; ++qq) {
+                const int c = w + kWaves * qq;
+                if (c < JP) {
+                    const float v = seg_scan(L.sB[c * kTS + lane], lane, head);
+                    if (jlast) {
+                        const float bp = L.Bb[sj * RS + c];
+                        L.Bb[sj * RS + c] = fmaf(a.lr, v - cr * bp, bp);
+                    }
+                }
+            }
+        }
+        if (tid == 0) L.Mk[k] += n;
         __syncthreads();
     }
-    if (curk >= 0) acc.flush(Sk + curk * J1 * J2, J1, J2, lane);
+    acc.flush(Skmine + curk * J12, J1, J2, lane);
     __syncthreads();
+}
 
-    // write the rows back and publish the block's core-gradient sums
-    for (int idx = lane; idx < r1 * J1; idx += 64) {
-        const int l = idx / J1, c = idx - l * J1;
-        a.A[(size_t)a.perm1[s1 + l] * J1 + c] = Ab[l * RS + c];
+// The block's S = sum over wavefronts (ascending) of their partial sums.
+__device__ inline void combine_waves(float* Sk, const float* Skw, int ni, int tid)
+{
+    for (int idx = tid; idx < ni; idx += kStratThreads) {
+        float s = Skw[idx];
+#pragma unroll
+        for (int ww = 1; ww < kWaves; ++ww) s += Skw[ww * ni + idx];
+        Sk[idx] = s;
     }
-    for (int idx = lane; idx < r2 * J2; idx += 64) {
-        const int l = idx / J2, c = idx - l * J2;
-        a.B[(size_t)a.perm2[s2 + l] * J2 + c] = Bb[l * RS + c];
-    }
-    float* Sp = a.Spart + (size_t)p * I3 * J1 * J2;
-    for (int idx = lane; idx < I3 * J1 * J2; idx += 64) Sp[idx] = Sk[idx];
-    for (int k = lane; k < I3; k += 64) a.Mpart[p * I3 + k] = Mk[k];
 }
 
 // ---------------------------------------------------------------------------
-// Core / platform step after a stratum: blocks' sums reduced in ascending p,
-// then one mean-gradient step on C and G.
+// Grid barrier for the persistent kernel.  Returns false (for every thread
+// of the workgroup) if the barrier gave up: another workgroup timed out or
+// this one waited far longer than any stratum can take.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void core_step(CoreArgs a)
+constexpr unsigned kSpinLimit = 1u << 25;
+
+__device__ bool grid_sync(GridBar* bar, unsigned nblocks, unsigned& gen, int* flag)
 {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned g = gen;
+        __threadfence();
+        const unsigned arrived = atomicAdd(&bar->count, 1u);
+        if (arrived == nblocks - 1) {
+            atomicExch(&bar->count, 0u);
+            __threadfence();
+            atomicAdd(&bar->gen, 1u);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (__hip_atomic_load(&bar->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > kSpinLimit) {
+                    atomicOr(&bar->err, 1u);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        gen = g + 1;
+        *flag = ok;
+    }
+    __syncthreads();
+    return *flag != 0;
+}
+
+template <int JP>
+__device__ inline TileLds tile_lds(float* lds, const StratLds& S)
+{
+    TileLds L;
+    L.Ab = lds + S.a;
+    L.Bb = lds + S.b;
+    L.rA = lds + S.ra;
+    L.rB = lds + S.rb;
+    L.Hs = lds + S.h;
+    L.sA = lds + S.sa;
+    L.sB = lds + S.sb;
+    L.As = lds + S.as;
+    L.Es = lds + S.es;
+    L.xtp = lds + S.xtp;
+    L.slotJ = reinterpret_cast<int*>(lds + S.slotj);
+    L.Skw = lds + S.skw;
+    L.Mk = reinterpret_cast<int*>(lds + S.mk);
+    L.tco = reinterpret_cast<int*>(lds + S.tco);
+    L.tck = reinterpret_cast<int*>(lds + S.tck);
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent driver: every stratum of one epoch in one launch.
+// ---------------------------------------------------------------------------
+template <int JP>
+__global__ __launch_bounds__(kStratThreads) void strata_persistent(StratArgs a)
+{
+    constexpr int RS = row_stride(JP);
+    constexpr int NT = kStratThreads;
     extern __shared__ float lds[];
-    const int J12 = a.J1 * a.J2, I3 = a.I3, J3 = a.J3;
-    float* S = lds;                        // [I3][J12]
-    float* C0 = S + I3 * J12;              // [I3][J3]
-    float* G0 = C0 + I3 * J3;              // [J12][J3]
-    double* mk = reinterpret_cast<double*>(lds + ((I3 * J12 + I3 * J3 + J12 * J3 + 1) & ~1));
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < I3 * J12; idx += blockDim.x) {
-        float s = 0.f;
-        for (int p = 0; p < a.P; ++p) s += a.Spart[(size_t)p * I3 * J12 + idx];
-        S[idx] = s;
-    }
-    for (int k = tid; k < I3; k += blockDim.x) {
-        long long m = 0;
-        for (int p = 0; p < a.P; ++p) m += a.Mpart[p * I3 + k];
-        mk[k] = (double)m;
-    }
-    for (int idx = tid; idx < I3 * J3; idx += blockDim.x) C0[idx] = a.C[idx];
-    for (int idx = tid; idx < J12 * J3; idx += blockDim.x) G0[idx] = a.G[idx];
+    const int q = blockIdx.x;
+    const int P = a.P, I3 = a.I3, J1 = a.J1, J2 = a.J2, J3 = a.J3, J12 = J1 * J2;
+    const int ni = I3 * J12;
+    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3);
+    const TileLds L = tile_lds<JP>(lds, S);
+    float* Cs = lds + S.c;
+    float* Gs = lds + S.g;
+    float* Hs = lds + S.h;
+    float* Sk = lds + S.sk;
+    float* red = lds + S.red;
+    double* msum = reinterpret_cast<double*>(lds + S.msum);
+    float* cgt = lds + S.cgt;
+    int* flag = reinterpret_cast<int*>(lds + S.flag);
+
+    for (int idx = tid; idx < (a.rows1_max + a.rows2_max) * RS; idx += NT) lds[S.a + idx] = 0.f;
     __syncthreads();
-    double m = 0.0;
-    for (int k = 0; k < I3; ++k) m += mk[k];
-    if (m <= 0.0) return;
-    const float inv_m = (float)(1.0 / m);
-    for (int idx = tid; idx < I3 * J3; idx += blockDim.x) {
-        const int k = idx / J3, c = idx - k * J3;
-        float g = 0.f;
-        for (int ab = 0; ab < J12; ++ab) g -= G0[ab * J3 + c] * S[k * J12 + ab];
-        if (mk[k] > 0.0) g += a.lam * (float)(mk[k] / (double)a.cnt3[k]) * C0[idx];
-        a.C[idx] = C0[idx] - a.etac * g * inv_m;
+    const int s2 = a.start2[q], r2 = a.start2[q + 1] - s2;
+    load_rows(L.Bb, a.Bp, s2, r2, J2, RS, tid, NT);
+    for (int l = tid; l < r2; l += NT) lds[S.rb + l] = a.reg2[s2 + l];
+    for (int idx = tid; idx < I3 * J3; idx += NT) Cs[idx] = a.C[idx];
+    for (int idx = tid; idx < J12 * J3; idx += NT) Gs[idx] = a.G[idx];
+    unsigned gen = 0;
+    if (tid == 0) gen = __hip_atomic_load(&a.bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+
+    // this workgroup's share of the stratum reduction
+    const int i0 = (int)(((long long)ni * q) / P), i1 = (int)(((long long)ni * (q + 1)) / P);
+
+    for (int si = 0; si < P; ++si) {
+        const int s = a.order[si];
+        const int p = (q - s + P) % P;
+        const int s1 = a.start1[p], r1 = a.start1[p + 1] - s1;
+        load_rows(L.Ab, a.Ap, s1, r1, J1, RS, tid, NT);
+        for (int l = tid; l < r1; l += NT) lds[S.ra + l] = a.reg1[s1 + l];
+        build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
+        for (int idx = tid; idx < kWaves * ni; idx += NT) L.Skw[idx] = 0.f;
+        for (int k = tid; k < I3; k += NT) L.Mk[k] = 0;
+        __syncthreads();
+        block_tiles<JP>(a, p, q, L, tid);
+        combine_waves(Sk, L.Skw, ni, tid);
+        store_rows(a.Ap, L.Ab, s1, r1, J1, RS, tid, NT);
+        __syncthreads();
+        float* Sp = a.Spart + (size_t)p * ni;
+        for (int idx = tid; idx < ni; idx += NT) Sp[idx] = Sk[idx];
+        for (int k = tid; k < I3; k += NT) a.Mpart[p * I3 + k] = L.Mk[k];
+        if (!grid_sync(a.bar, P, gen, flag)) return;
+
+        stratum_counts(a.Mpart, P, I3, L.Mk, msum, tid, NT);
+        reduce_items(a.Spart, P, ni, i0, i1, a.Ssum + i0, red, tid, NT);
+        if (!grid_sync(a.bar, P, gen, flag)) return;
+
+        for (int idx = tid; idx < ni; idx += NT) Sk[idx] = a.Ssum[idx];
+        __syncthreads();
+        core_update(Cs, Gs, Sk, msum, a.cnt3, I3, J12, J3, a.lam, a.etac, a.nnz, red, cgt, cgt + I3 * J3, tid,
+                    NT);
+        __syncthreads();
+        for (int idx = tid; idx < I3 * J3; idx += NT) Cs[idx] = cgt[idx];
+        for (int idx = tid; idx < J12 * J3; idx += NT) Gs[idx] = cgt[I3 * J3 + idx];
+        __syncthreads();
     }
-    const float greg = a.lam * (float)(m / a.nnz);
-    for (int idx = tid; idx < J12 * J3; idx += blockDim.x) {
-        const int ab = idx / J3, c = idx - ab * J3;
-        float g = 0.f;
-        for (int k = 0; k < I3; ++k) g -= S[k * J12 + ab] * C0[k * J3 + c];
-        g += greg * G0[idx];
-        a.G[idx] = G0[idx] - a.etac * g * inv_m;
+    store_rows(a.Bp, L.Bb, s2, r2, J2, RS, tid, NT);
+    if (q == 0) {
+        for (int idx = tid; idx < I3 * J3; idx += NT) a.C[idx] = Cs[idx];
+        for (int idx = tid; idx < J12 * J3; idx += NT) a.G[idx] = Gs[idx];
     }
 }
 
 // ---------------------------------------------------------------------------
-// Network step: one Jacobi application of B <- B - alpha L B.
+// Multi-launch driver: one block step per stratum, then one core step.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void graph_step(GraphArgs a)
+template <int JP>
+__global__ __launch_bounds__(kStratThreads) void block_step(StratArgs a)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= a.I2 * a.J2) return;
-    const int r = idx / a.J2, c = idx - r * a.J2;
-    float lb = a.deg[r] * a.Bin[idx];
-    for (int e = a.adj_start[r]; e < a.adj_start[r + 1]; ++e)
-        lb -= a.adj_w[e] * a.Bin[(size_t)a.adj_nbr[e] * a.J2 + c];
-    a.Bout[idx] = a.Bin[idx] - a.alpha * lb;
+    constexpr int RS = row_stride(JP);
+    constexpr int NT = kStratThreads;
+    extern __shared__ float lds[];
+    const int tid = threadIdx.x;
+    const int p = blockIdx.x, P = a.P;
+    const int q = (p + a.s) % P;
+    const int I3 = a.I3, J1 = a.J1, J2 = a.J2, J3 = a.J3, J12 = J1 * J2, ni = I3 * J12;
+    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3);
+    const TileLds L = tile_lds<JP>(lds, S);
+    float* Cs = lds + S.c;
+    float* Gs = lds + S.g;
+    float* Hs = lds + S.h;
+    float* Sk = lds + S.sk;
+    for (int idx = tid; idx < (a.rows1_max + a.rows2_max) * RS; idx += NT) lds[S.a + idx] = 0.f;
+    __syncthreads();
+    const int s1 = a.start1[p], r1 = a.start1[p + 1] - s1;
+    const int s2 = a.start2[q], r2 = a.start2[q + 1] - s2;
+    load_rows(L.Ab, a.Ap, s1, r1, J1, RS, tid, NT);
+    load_rows(L.Bb, a.Bp, s2, r2, J2, RS, tid, NT);
+    for (int l = tid; l < r1; l += NT) lds[S.ra + l] = a.reg1[s1 + l];
+    for (int l = tid; l < r2; l += NT) lds[S.rb + l] = a.reg2[s2 + l];
+    for (int idx = tid; idx < I3 * J3; idx += NT) Cs[idx] = a.C[idx];
+    for (int idx = tid; idx < J12 * J3; idx += NT) Gs[idx] = a.G[idx];
+    for (int idx = tid; idx < kWaves * ni; idx += NT) L.Skw[idx] = 0.f;
+    for (int k = tid; k < I3; k += NT) L.Mk[k] = 0;
+    __syncthreads();
+    build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
+    __syncthreads();
+    block_tiles<JP>(a, p, q, L, tid);
+    combine_waves(Sk, L.Skw, ni, tid);
+    store_rows(a.Ap, L.Ab, s1, r1, J1, RS, tid, NT);
+    store_rows(a.Bp, L.Bb, s2, r2, J2, RS, tid, NT);
+    __syncthreads();
+    float* Sp = a.Spart + (size_t)p * ni;
+    for (int idx = tid; idx < ni; idx += NT) Sp[idx] = Sk[idx];
+    for (int k = tid; k < I3; k += NT) a.Mpart[p * I3 + k] = L.Mk[k];
 }
 
-// ---------------------------------------------------------------------------
-// Loss: per-block squared errors (FP32 model value, FP64 sums), then one
-// workgroup adds the blocks in order with the L2 and network terms.
-// ---------------------------------------------------------------------------
-struct LossLds {
-    int a_off, b_off, h_off, red_off, total;
+struct CoreLds {
+    int s, c, cgt, red, msum, total;
 };
 
-__host__ __device__ inline LossLds loss_lds_layout(int jp, int rows1_max, int rows2_max, int I3)
+__host__ __device__ inline CoreLds core_lds_layout(int I3, int J1, int J2, int J3, int threads)
 {
-    const int rs = row_stride(jp);
-    LossLds L;
+    const int nch = (J1 * J2 + kCoreChunk - 1) / kCoreChunk;
+    CoreLds L;
     int o = 0;
-    L.a_off = o; o += rows1_max * rs;
-    L.b_off = o; o += rows2_max * rs;
-    o = (o + 3) & ~3;
-    L.h_off = o; o += I3 * jp * jp;
-    o = (o + 1) & ~1;
-    L.red_off = o; o += 2 * 256;  // 256 doubles
+    L.s = o;    o = up4(o + I3 * J1 * J2);
+    L.c = o;    o = up4(o + I3 * J3);
+    L.cgt = o;  o = up4(o + I3 * J3);
+    L.red = o;  o = up4(o + (threads > I3 * J3 * nch ? threads : I3 * J3 * nch));
+    L.msum = o; o = up4(o + 2 * I3);
     L.total = o;
     return L;
 }
 
-size_t loss_lds_bytes(int jp, int rows1_max, int rows2_max, int I3)
+size_t core_lds_bytes(int I3, int J1, int J2, int J3, int threads)
 {
-    return align16(sizeof(float) * (size_t)loss_lds_layout(jp, rows1_max, rows2_max, I3).total);
+    return align16(4 * (size_t)core_lds_layout(I3, J1, J2, J3, threads).total);
+}
+
+// One workgroup: the stratum reduction and the core step on C, G in HBM.
+// New G values go to Gtmp first so that every C item still reads the old G.
+__global__ __launch_bounds__(kCoreThreads) void core_step(StratArgs a, float* Gtmp)
+{
+    extern __shared__ float lds[];
+    constexpr int NT = kCoreThreads;
+    const int tid = threadIdx.x;
+    const int P = a.P, I3 = a.I3, J1 = a.J1, J2 = a.J2, J3 = a.J3, J12 = J1 * J2, ni = I3 * J12;
+    const CoreLds L = core_lds_layout(I3, J1, J2, J3, NT);
+    float* S = lds + L.s;
+    float* C0 = lds + L.c;
+    float* cgt = lds + L.cgt;
+    float* red = lds + L.red;
+    double* msum = reinterpret_cast<double*>(lds + L.msum);
+    stratum_counts(a.Mpart, P, I3, reinterpret_cast<int*>(cgt), msum, tid, NT);
+    for (int idx = tid; idx < I3 * J3; idx += NT) C0[idx] = a.C[idx];
+    reduce_items(a.Spart, P, ni, 0, ni, S, red, tid, NT);
+    core_update(C0, a.G, S, msum, a.cnt3, I3, J12, J3, a.lam, a.etac, a.nnz, red, cgt, Gtmp, tid, NT);
+    __syncthreads();
+    for (int idx = tid; idx < I3 * J3; idx += NT) a.C[idx] = cgt[idx];
+    for (int idx = tid; idx < J12 * J3; idx += NT) a.G[idx] = Gtmp[idx];
+}
+
+// ---------------------------------------------------------------------------
+// Network: one wavefront per gene row (position order).
+//   mode 0: Bout[r] = Bin[r] - alpha (deg[r] Bin[r] - sum_nbr w Bin[nbr])
+//   mode 1: net_part[r] = sum_nbr w |Bin[r] - Bin[nbr]|^2   (FP64)
+// Lanes stride over the neighbours; a butterfly reduction (fixed order)
+// combines the lanes.
+// ---------------------------------------------------------------------------
+template <int JP>
+__global__ __launch_bounds__(256) void graph_rows(GraphArgs g, int mode)
+{
+    const int lane = threadIdx.x & 63;
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= g.I2) return;
+    const int J2 = g.J2;
+    const int e0 = g.adj_start[r], e1 = g.adj_start[r + 1];
+    if (mode == 0) {
+        float acc[JP];
+#pragma unroll
+        for (int c = 0; c < JP; ++c) acc[c] = 0.f;
+        for (int e = e0 + lane; e < e1; e += 64) {
+            const float w = g.adj_w[e];
+            const float* bn = g.Bin + (size_t)g.adj_nbr[e] * J2;
+#pragma unroll
+            for (int c = 0; c < JP; ++c)
+                if (c < J2) acc[c] = fmaf(w, bn[c], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < JP; ++c)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_xor(acc[c], o);
+        float mine = 0.f;
+#pragma unroll
+        for (int c = 0; c < JP; ++c)
+            if (c == lane) mine = acc[c];
+        if (lane < J2) {
+            const float b = g.Bin[(size_t)r * J2 + lane];
+            g.Bout[(size_t)r * J2 + lane] = fmaf(-g.alpha, fmaf(g.deg[r], b, -mine), b);
+        }
+    } else {
+        double d = 0.0;
+        const float* br = g.Bin + (size_t)r * J2;
+        for (int e = e0 + lane; e < e1; e += 64) {
+            const float* bn = g.Bin + (size_t)g.adj_nbr[e] * J2;
+            double s = 0.0;
+            for (int c = 0; c < J2; ++c) {
+                const double t = (double)br[c] - (double)bn[c];
+                s += t * t;
+            }
+            d += (double)g.adj_w[e] * s;
+        }
+        for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
+        if (lane == 0) g.net_part[r] = d;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Loss: squared errors per block (FP32 model value, FP64 sums), L2 terms per
+// row group, network term per gene row, then one workgroup adds each list in
+// a fixed order.
+// ---------------------------------------------------------------------------
+struct LossLds {
+    int a, b, c, g, h, red, total;
+};
+
+__host__ __device__ inline LossLds loss_lds_layout(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2,
+                                                   int J3)
+{
+    const int rs = row_stride(jp);
+    LossLds L;
+    int o = 0;
+    L.a = o;   o = up4(o + rows1_max * rs);
+    L.b = o;   o = up4(o + rows2_max * rs);
+    L.c = o;   o = up4(o + I3 * J3);
+    L.g = o;   o = up4(o + J1 * J2 * J3);
+    L.h = o;   o = up4(o + I3 * jp * jp);
+    L.red = o; o = up4(o + 2 * 256);
+    L.total = o;
+    return L;
+}
+
+size_t loss_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3)
+{
+    return align16(4 * (size_t)loss_lds_layout(jp, rows1_max, rows2_max, I3, J1, J2, J3).total);
+}
+
+__device__ inline double block_sum_256(double v, double* red, int tid)
+{
+    red[tid] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
 }
 
 template <int JP>
@@ -398,214 +866,280 @@ __global__ __launch_bounds__(256) void loss_blocks(LossArgs a)
 {
     constexpr int RS = row_stride(JP);
     extern __shared__ float lds[];
-    const LossLds L = loss_lds_layout(JP, a.rows1_max, a.rows2_max, a.I3);
-    float* Ab = lds + L.a_off;
-    float* Bb = lds + L.b_off;
-    float* Hs = lds + L.h_off;
-    double* red = reinterpret_cast<double*>(lds + L.red_off);
     const int tid = threadIdx.x;
     const int blk = blockIdx.x, p = blk / a.P, q = blk - p * a.P;
+    const int t0 = a.blk_tile[blk], t1 = a.blk_tile[blk + 1];
+    if (t0 >= t1) {
+        if (tid == 0) a.sse_part[blk] = 0.0;
+        return;
+    }
     const int J1 = a.J1, J2 = a.J2, J3 = a.J3;
+    const LossLds L = loss_lds_layout(JP, a.rows1_max, a.rows2_max, a.I3, J1, J2, J3);
+    float* Ab = lds + L.a;
+    float* Bb = lds + L.b;
+    float* Cs = lds + L.c;
+    float* Gs = lds + L.g;
+    float* Hs = lds + L.h;
+    double* red = reinterpret_cast<double*>(lds + L.red);
+    for (int idx = tid; idx < (a.rows1_max + a.rows2_max) * RS; idx += 256) lds[L.a + idx] = 0.f;
+    for (int idx = tid; idx < a.I3 * J3; idx += 256) Cs[idx] = a.C[idx];
+    for (int idx = tid; idx < J1 * J2 * J3; idx += 256) Gs[idx] = a.G[idx];
+    __syncthreads();
     const int s1 = a.start1[p], r1 = a.start1[p + 1] - s1;
     const int s2 = a.start2[q], r2 = a.start2[q + 1] - s2;
-    const int t0 = a.blk_tile[blk], t1 = a.blk_tile[blk + 1];
+    load_rows(Ab, a.Ap, s1, r1, J1, RS, tid, 256);
+    load_rows(Bb, a.Bp, s2, r2, J2, RS, tid, 256);
+    build_h<JP>(Hs, Cs, Gs, a.I3, J1, J2, J3, tid, 256);
+    __syncthreads();
+    const uint32_t mask_i = (1u << a.bits_i) - 1u, mask_j = (1u << a.bits_j) - 1u;
+    // one wavefront per tile: the tile's platform is uniform
+    const int wave = tid >> 6, lane = tid & 63;
     double acc = 0.0;
-    if (t0 < t1) {
-        for (int idx = tid; idx < r1 * RS; idx += 256) {
-            const int l = idx / RS, c = idx - l * RS;
-            Ab[idx] = c < J1 ? a.A[(size_t)a.perm1[s1 + l] * J1 + c] : 0.f;
-        }
-        for (int idx = tid; idx < r2 * RS; idx += 256) {
-            const int l = idx / RS, c = idx - l * RS;
-            Bb[idx] = c < J2 ? a.B[(size_t)a.perm2[s2 + l] * J2 + c] : 0.f;
-        }
-        for (int idx = tid; idx < a.I3 * JP * JP; idx += 256) {
-            const int k = idx / (JP * JP), xy = idx - k * JP * JP, x = xy / JP, y = xy - x * JP;
-            float h = 0.f;
-            if (x < J1 && y < J2)
-                for (int c = 0; c < J3; ++c) h += a.G[(x * J2 + y) * J3 + c] * a.C[k * J3 + c];
-            Hs[idx] = h;
-        }
-        __syncthreads();
-        const uint32_t mask_i = (1u << a.bits_i) - 1u, mask_j = (1u << a.bits_j) - 1u;
-        const int z0 = a.tile_off[t0], z1 = a.tile_off[t1];
-        // tiles are platform-uniform; find each nonzero's platform by its tile
-        int tl = t0;
-        for (int z = z0 + tid; z < z1; z += 256) {
-            while (a.tile_off[tl + 1] <= z) ++tl;
-            const int k = a.tile_k[tl];
-            const uint2 wv = a.nz[z];
+    for (int tl = t0 + wave; tl < t1; tl += 4) {
+        const int off = a.tile_off[tl], n = a.tile_off[tl + 1] - off, k = a.tile_k[tl];
+        if (lane < n) {
+            const uint2 wv = a.nz[off + lane];
             const int il = (int)(wv.x & mask_i), jl = (int)((wv.x >> a.bits_i) & mask_j);
             const float* H = Hs + k * JP * JP;
+            float bv[JP];
+#pragma unroll
+            for (int y = 0; y < JP; ++y) bv[y] = Bb[jl * RS + y];
             float xt = 0.f;
 #pragma unroll
             for (int x_ = 0; x_ < JP; ++x_) {
                 float w1 = 0.f;
 #pragma unroll
-                for (int y = 0; y < JP; ++y) w1 = fmaf(H[x_ * JP + y], Bb[jl * RS + y], w1);
+                for (int y = 0; y < JP; ++y) w1 = fmaf(H[x_ * JP + y], bv[y], w1);
                 xt = fmaf(Ab[il * RS + x_], w1, xt);
             }
             const float e = __uint_as_float(wv.y) - xt;
             acc += (double)e * (double)e;
         }
     }
-    red[tid] = acc;
+    const double s = block_sum_256(acc, red, tid);
+    if (tid == 0) a.sse_part[blk] = s;
+}
+
+// L2 terms: workgroups [0, nA) take patient rows, [nA, nA+nB) gene rows, the
+// last one the platform rows and the core.
+__global__ __launch_bounds__(256) void loss_reg(LossArgs a)
+{
+    __shared__ double red[256];
+    const int tid = threadIdx.x, wg = blockIdx.x;
+    const int nA = (a.I1 + 255) / 256, nB = (a.I2 + 255) / 256;
+    double v = 0.0;
+    if (wg < nA) {
+        const int r = wg * 256 + tid;
+        if (r < a.I1 && a.cnt1[r] > 0)
+            for (int c = 0; c < a.J1; ++c) v += (double)a.Ap[(size_t)r * a.J1 + c] * a.Ap[(size_t)r * a.J1 + c];
+    } else if (wg < nA + nB) {
+        const int r = (wg - nA) * 256 + tid;
+        if (r < a.I2 && a.cnt2[r] > 0)
+            for (int c = 0; c < a.J2; ++c) v += (double)a.Bp[(size_t)r * a.J2 + c] * a.Bp[(size_t)r * a.J2 + c];
+    } else {
+        const int ng = a.J1 * a.J2 * a.J3;
+        for (int t = tid; t < ng; t += 256) v += (double)a.G[t] * a.G[t];
+        for (int r = tid; r < a.I3; r += 256)
+            if (a.cnt3[r] > 0)
+                for (int c = 0; c < a.J3; ++c) v += (double)a.C[(size_t)r * a.J3 + c] * a.C[(size_t)r * a.J3 + c];
+    }
+    const double s = block_sum_256(v, red, tid);
+    if (tid == 0) a.reg_part[wg] = s;
+}
+
+__device__ double ordered_sum(const double* x, int n, double* red, int tid)
+{
+    double v = 0.0;
+    for (int t = tid; t < n; t += 1024) v += x[t];
+    red[tid] = v;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = 512; w > 0; w >>= 1) {
         if (tid < w) red[tid] += red[tid + w];
         __syncthreads();
     }
-    if (tid == 0) a.partial[blk] = red[0];
+    const double r = red[0];
+    __syncthreads();
+    return r;
 }
 
 __global__ __launch_bounds__(1024) void loss_final(LossArgs a)
 {
     __shared__ double red[1024];
     const int tid = threadIdx.x;
-    const int nb = a.P * a.P;
-    double sse = 0.0;
-    for (int b = tid; b < nb; b += 1024) sse += a.partial[b];
-    red[tid] = sse;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
-        __syncthreads();
-    }
-    sse = red[0];
-    __syncthreads();
-    // L2 term over the core and the observed rows
-    double reg = 0.0;
-    const int ng = a.J1 * a.J2 * a.J3;
-    for (int q = tid; q < ng; q += 1024) reg += (double)a.G[q] * a.G[q];
-    for (int r = tid; r < a.I1; r += 1024)
-        if (a.cnt1[r] > 0)
-            for (int c = 0; c < a.J1; ++c) reg += (double)a.A[(size_t)r * a.J1 + c] * a.A[(size_t)r * a.J1 + c];
-    for (int r = tid; r < a.I2; r += 1024)
-        if (a.cnt2[r] > 0)
-            for (int c = 0; c < a.J2; ++c) reg += (double)a.B[(size_t)r * a.J2 + c] * a.B[(size_t)r * a.J2 + c];
-    for (int r = tid; r < a.I3; r += 1024)
-        if (a.cnt3[r] > 0)
-            for (int c = 0; c < a.J3; ++c) reg += (double)a.C[(size_t)r * a.J3 + c] * a.C[(size_t)r * a.J3 + c];
-    red[tid] = reg;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
-        __syncthreads();
-    }
-    reg = red[0];
-    __syncthreads();
-    // network term: each undirected pair appears twice in the symmetric CSR
-    double net = 0.0;
-    if (a.lam_g > 0.0) {
-        for (int r = tid; r < a.I2; r += 1024)
-            for (int e = a.adj_start[r]; e < a.adj_start[r + 1]; ++e) {
-                const int v = a.adj_nbr[e];
-                double d2 = 0.0;
-                for (int c = 0; c < a.J2; ++c) {
-                    const double d = (double)a.B[(size_t)r * a.J2 + c] - (double)a.B[(size_t)v * a.J2 + c];
-                    d2 += d * d;
-                }
-                net += (double)a.adj_w[e] * d2;
-            }
-    }
-    red[tid] = net;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
-        __syncthreads();
-    }
-    net = 0.5 * red[0];
+    const double sse = ordered_sum(a.sse_part, a.P * a.P, red, tid);
+    const double reg = ordered_sum(a.reg_part, a.n_reg_wg, red, tid);
+    const double net = a.lam_g > 0.0 ? 0.5 * ordered_sum(a.net_part, a.I2, red, tid) : 0.0;
     if (tid == 0) {
         a.out[0] = 0.5 * sse + 0.5 * a.lam * reg + 0.5 * a.lam_g * net;
         a.out[1] = sse;
     }
 }
 
+// Row permutation: gather dst[r] = src[perm[r]] or scatter dst[perm[r]] = src[r].
+__global__ __launch_bounds__(256) void permute_rows(const float* src, float* dst, const int32_t* perm, int rows,
+                                                    int cols, int gather)
+{
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (long long)rows * cols) return;
+    const int r = (int)(idx / cols), c = (int)(idx - (long long)r * cols);
+    const size_t pr = (size_t)perm[r] * cols + c;
+    if (gather)
+        dst[idx] = src[pr];
+    else
+        dst[pr] = src[idx];
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int JP>
-static hipError_t launch_block_t(const BlockArgs& a, size_t lds, hipStream_t st)
-{
-    hipLaunchKernelGGL(block_fp32<JP>, dim3(a.P), dim3(64), lds, st, a);
-    return hipGetLastError();
-}
-
-template <int JP>
-static hipError_t launch_loss_t(const LossArgs& a, size_t lds, hipStream_t st)
-{
-    hipLaunchKernelGGL(loss_blocks<JP>, dim3(a.P * a.P), dim3(256), lds, st, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(loss_final, dim3(1), dim3(1024), 0, st, a);
-    return hipGetLastError();
-}
-
-#define SNECT_JP_SWITCH(JPV, CALL) \
-    switch (JPV) {                 \
-    case 2: return CALL(2);        \
-    case 4: return CALL(4);        \
-    case 5: return CALL(5);        \
-    case 8: return CALL(8);        \
-    case 10: return CALL(10);      \
-    case 12: return CALL(12);      \
-    case 16: return CALL(16);      \
-    case 20: return CALL(20);      \
-    case 24: return CALL(24);      \
-    case 32: return CALL(32);      \
-    default: return hipErrorInvalidValue; \
+#define SNECT_JP_SWITCH(JPV, CALL)            \
+    switch (JPV) {                            \
+    case 2: return CALL(2);                   \
+    case 4: return CALL(4);                   \
+    case 5: return CALL(5);                   \
+    case 8: return CALL(8);                   \
+    case 10: return CALL(10);                 \
+    case 12: return CALL(12);                 \
+    case 16: return CALL(16);                 \
+    case 20: return CALL(20);                 \
+    case 24: return CALL(24);                 \
+    case 32: return CALL(32);                 \
+    default: return hipErrorInvalidValue;     \
     }
 
-hipError_t launch_block_fp32(const BlockArgs& a, int jp, size_t lds, hipStream_t st)
+template <int JP>
+static hipError_t launch_persistent_t(const StratArgs& a, size_t lds, hipStream_t st)
+{
+    StratArgs copy = a;
+    void* args[] = {&copy};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&strata_persistent<JP>), dim3(a.P),
+                                      dim3(kStratThreads), args, (unsigned)lds, st);
+}
+
+hipError_t launch_strata_persistent(const StratArgs& a, int jp, size_t lds, hipStream_t st)
+{
+#define CALL_P(J) launch_persistent_t<J>(a, lds, st)
+    SNECT_JP_SWITCH(jp, CALL_P)
+#undef CALL_P
+}
+
+template <int JP>
+static hipError_t launch_block_t(const StratArgs& a, size_t lds, hipStream_t st)
+{
+    hipLaunchKernelGGL(block_step<JP>, dim3(a.P), dim3(kStratThreads), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_block(const StratArgs& a, int jp, size_t lds, hipStream_t st)
 {
 #define CALL_B(J) launch_block_t<J>(a, lds, st)
     SNECT_JP_SWITCH(jp, CALL_B)
 #undef CALL_B
 }
 
-hipError_t launch_loss(const LossArgs& a, int jp, size_t lds, hipStream_t st)
+hipError_t launch_core_step(const StratArgs& a, size_t lds, hipStream_t st)
 {
-#define CALL_L(J) launch_loss_t<J>(a, lds, st)
-    SNECT_JP_SWITCH(jp, CALL_L)
-#undef CALL_L
-}
-
-hipError_t launch_core_step(const CoreArgs& a, hipStream_t st)
-{
-    const int J12 = a.J1 * a.J2;
-    const size_t lds = align16(sizeof(float) * (size_t)(((a.I3 * J12 + a.I3 * a.J3 + J12 * a.J3 + 1) & ~1) +
-                                                      2 * a.I3));
-    hipLaunchKernelGGL(core_step, dim3(1), dim3(1024), lds, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_graph_step(const GraphArgs& a, hipStream_t st)
-{
-    const int n = a.I2 * a.J2;
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(graph_step, dim3((n + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(core_step, dim3(1), dim3(kCoreThreads), lds, st, a, a.Ssum);
     return hipGetLastError();
 }
 
 template <int JP>
-static hipError_t prepare_t(size_t block_lds, size_t loss_lds)
+static hipError_t launch_graph_t(const GraphArgs& g, int mode, hipStream_t st)
+{
+    if (g.I2 == 0) return hipSuccess;
+    hipLaunchKernelGGL(graph_rows<JP>, dim3((g.I2 + 3) / 4), dim3(256), 0, st, g, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_graph_step(const GraphArgs& g, int jp, hipStream_t st)
+{
+#define CALL_G(J) launch_graph_t<J>(g, 0, st)
+    SNECT_JP_SWITCH(jp, CALL_G)
+#undef CALL_G
+}
+
+template <int JP>
+static hipError_t launch_loss_t(const LossArgs& a, const GraphArgs& g, size_t lds, hipStream_t st)
+{
+    hipLaunchKernelGGL(loss_blocks<JP>, dim3(a.P * a.P), dim3(256), lds, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(loss_reg, dim3(a.n_reg_wg), dim3(256), 0, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (a.lam_g > 0.0) {
+        e = launch_graph_t<JP>(g, 1, st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(loss_final, dim3(1), dim3(1024), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss(const LossArgs& a, const GraphArgs& g, int jp, size_t lds, hipStream_t st)
+{
+#define CALL_L(J) launch_loss_t<J>(a, g, lds, st)
+    SNECT_JP_SWITCH(jp, CALL_L)
+#undef CALL_L
+}
+
+hipError_t launch_permute(const float* src, float* dst, const int32_t* perm, int rows, int cols, int gather,
+                          hipStream_t st)
+{
+    const long long n = (long long)rows * cols;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(permute_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, perm, rows,
+                       cols, gather);
+    return hipGetLastError();
+}
+
+template <int JP>
+static hipError_t prepare_t(size_t slds, size_t llds, size_t clds)
 {
     hipError_t e = hipSuccess;
-    if (block_lds > 65536)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&block_fp32<JP>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)block_lds);
-    if (e != hipSuccess) return e;
-    if (loss_lds > 65536)
+    const int limit = 65536;
+    if (slds > (size_t)limit) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&strata_persistent<JP>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&block_step<JP>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds);
+    }
+    if (e == hipSuccess && llds > (size_t)limit)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&loss_blocks<JP>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)loss_lds);
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)llds);
+    if (e == hipSuccess && clds > (size_t)limit)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&core_step), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)clds);
     return e;
 }
 
-hipError_t prepare_kernels(int jp, size_t block_lds, size_t loss_lds)
+hipError_t prepare_kernels(int jp, size_t slds, size_t llds, size_t clds)
 {
-#define CALL_P(J) prepare_t<J>(block_lds, loss_lds)
-    SNECT_JP_SWITCH(jp, CALL_P)
-#undef CALL_P
+#define CALL_R(J) prepare_t<J>(slds, llds, clds)
+    SNECT_JP_SWITCH(jp, CALL_R)
+#undef CALL_R
+}
+
+template <int JP>
+static int capacity_t(size_t lds)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&strata_persistent<JP>),
+                                                     kStratThreads, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return per_cu * cus;
+}
+
+int persistent_capacity(int jp, size_t lds)
+{
+#define CALL_C(J) capacity_t<J>(lds)
+    SNECT_JP_SWITCH(jp, CALL_C)
+#undef CALL_C
 }
 
 }  // namespace snect

@@ -35,14 +35,33 @@ def _check_factors(gpu, orc, tol=FACTOR_TOL):
         assert r <= tol, f"{name}: relative Frobenius error {r:.3e} > {tol}"
 
 
+@pytest.mark.parametrize("path", [1, 2])
 @pytest.mark.parametrize("P,T", [(8, 64), (1, 1), (4, 16), (3, 37)])
-def test_planted_one_epoch_factors(ctx, P, T):
+def test_planted_one_epoch_factors(ctx, P, T, path):
     case = planted_case(P=P, T=T)
-    print(f"planted P={P} T={T}", flush=True)
+    print(f"planted P={P} T={T} path={path}", flush=True)
     orc = run_oracle(case, 1)
-    gpu, loss, rmse, _ = run_gpu(ctx, case, 1)
+    prob = gpu_problem(ctx, case)
+    prob.set_exec(path=path)
+    gpu, loss, rmse, _ = run_gpu(ctx, case, 1, prob=prob)
     _check_factors(gpu, orc[:4])
     assert abs(loss[0] - orc[4][0]) <= LOSS_TOL * abs(orc[4][0])
+
+
+@pytest.mark.parametrize("P,T,ranks", [(8, 64, (5, 5, 2)), (5, 29, (20, 20, 5)), (3, 7, (16, 12, 3))])
+def test_paths_are_bit_identical(ctx, P, T, ranks):
+    import paper_1711_08095_amd as sn
+    case = planted_case(seed=21, dims=(61, 83, 6), ranks=ranks, nnz=5000, edges=300, P=P, T=T, sigma=0.5,
+                        lr=2e-4)
+    prob = gpu_problem(ctx, case)
+    assert prob.exec_path() == sn.PATH_PERSISTENT
+    out = []
+    for path in (sn.PATH_PERSISTENT, sn.PATH_MULTI):
+        prob.set_exec(path=path)
+        out.append(run_gpu(ctx, case, 3, prob=prob))
+    for a, b in zip(out[0][0], out[1][0]):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(out[0][1], out[1][1])
 
 
 def test_planted_ten_epochs_loss(ctx):
