@@ -138,6 +138,7 @@ struct snect_problem {
     double dmax = 0;
     size_t strata_lds = 0, block_lds = 0, loss_lds = 0, core_lds = 0;
     int capacity = 0;
+    int rec_cap = 2048;
     double plan_s = 0, upload_s = 0;
     std::vector<int32_t> perm1, perm2;  // host copies kept for export
     // device buffers
@@ -294,7 +295,11 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         return set_err(ctx, SNECT_E_UNSUPPORTED, "blocks too large to pack; raise strata_P");
     if (I3 > 4096) return set_err(ctx, SNECT_E_UNSUPPORTED, "at most 4096 platforms");
     if ((int64_t)P * P * I3 >= (int64_t(1) << 31)) return set_err(ctx, SNECT_E_UNSUPPORTED, "too many blocks");
-    const size_t slds = strata_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3);
+    // the largest record chunk that still fits in LDS
+    int rec_cap = 2048;
+    while (rec_cap > kTileMax && strata_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap) > ctx->max_lds)
+        rec_cap /= 2;
+    const size_t slds = strata_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap);
     const size_t blds = slds;
     const size_t llds = loss_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3);
     const size_t clds = core_lds_bytes(I3, J1, J2, J3, kCoreThreads);
@@ -313,6 +318,7 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
     pr->seed = pa->seed;
     pr->rows1_max = rows1_max; pr->rows2_max = rows2_max; pr->bits_i = bits_i; pr->bits_j = bits_j;
     pr->strata_lds = slds; pr->block_lds = blds; pr->loss_lds = llds; pr->core_lds = clds;
+    pr->rec_cap = rec_cap;
     pr->n_reg_wg = (I1 + 255) / 256 + (I2 + 255) / 256 + 1;
 
     int rc = SNECT_OK;
@@ -692,6 +698,7 @@ int snect_train(snect_problem* pr, snect_factors* f, int32_t start_epoch, int32_
     sa.order = pr->d_order; sa.bar = pr->d_bar;
     sa.P = P; sa.s = 0; sa.I3 = pr->I3; sa.J1 = pr->J1; sa.J2 = pr->J2; sa.J3 = pr->J3;
     sa.rows1_max = pr->rows1_max; sa.rows2_max = pr->rows2_max; sa.bits_i = pr->bits_i; sa.bits_j = pr->bits_j;
+    sa.rec_cap = pr->rec_cap;
     sa.lr = (float)pr->lr; sa.lam = (float)pr->lam; sa.etac = (float)(pr->lr * pr->cls);
     sa.nnz = (double)pr->nnz;
     GraphArgs ga = graph_args(pr);

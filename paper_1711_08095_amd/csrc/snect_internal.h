@@ -60,6 +60,7 @@ struct StratArgs {
     int32_t P, s, I3, J1, J2, J3;
     int32_t rows1_max, rows2_max;
     int32_t bits_i, bits_j;
+    int32_t rec_cap;           // records staged in LDS per chunk (>= kTileMax)
     float lr, lam, etac;
     double nnz;
 };
@@ -104,7 +105,7 @@ struct GraphArgs {
     float alpha;
 };
 
-size_t strata_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3);
+size_t strata_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3, int rec_cap);
 size_t loss_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3);
 size_t core_lds_bytes(int I3, int J1, int J2, int J3, int threads);
 int jp_for(int J1, int J2);

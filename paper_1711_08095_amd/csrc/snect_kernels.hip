@@ -56,14 +56,14 @@ __device__ inline void lds_order_fence() { asm volatile("" ::: "memory"); }
 // LDS carve-up of the stratum kernels (in 4-byte words).
 // ---------------------------------------------------------------------------
 struct StratLds {
-    int a, b, ra, rb, c, g, h, sa, sb, as, es, xtp, slotj, skw, sk, mk, tco, tck, red, msum, cgt, flag;
+    int a, b, ra, rb, c, g, h, sa, sb, as, es, xtp, slotj, skw, sk, mk, tco, tck, red, msum, cgt, flag, rec;
     int total;
 };
 
 __host__ __device__ inline int up4(int o) { return (o + 3) & ~3; }
 
 __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2,
-                                                     int J3)
+                                                     int J3, int rec_cap)
 {
     const int rs = row_stride(jp), mp = mfma_dim(jp), j12 = J1 * J2;
     const int nch = (j12 + kCoreChunk - 1) / kCoreChunk;
@@ -85,19 +85,20 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     L.skw = o;   o = up4(o + kWaves * I3 * j12);
     L.sk = o;    o = up4(o + I3 * j12);
     L.mk = o;    o = up4(o + I3);
-    L.tco = o;   o = up4(o + kTileCache + 2);
+    L.tco = o;   o = up4(o + kTileCache + 1);
     L.tck = o;   o = up4(o + kTileCache);
     L.red = o;   o = up4(o + (kStratThreads > I3 * J3 * nch ? kStratThreads : I3 * J3 * nch));
     L.msum = o;  o = up4(o + 2 * I3);          // doubles
     L.cgt = o;   o = up4(o + I3 * J3 + j12 * J3);
     L.flag = o;  o = up4(o + 1);
+    L.rec = o;   o = up4(o + 2 * rec_cap);
     L.total = o;
     return L;
 }
 
-size_t strata_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3)
+size_t strata_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3, int rec_cap)
 {
-    return align16(4 * (size_t)strat_lds_layout(jp, rows1_max, rows2_max, I3, J1, J2, J3).total);
+    return align16(4 * (size_t)strat_lds_layout(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap).total);
 }
 
 int jp_for(int J1, int J2)
@@ -324,26 +325,73 @@ __device__ inline void store_rows(float* dst, const float* src, int row0, int nr
     }
 }
 
-// Tile metadata of tiles [base, base + kTileCache] (offsets one further).
+// Tile metadata of tiles [base, base + kTileCache) (offsets one further).
 __device__ inline void load_tile_cache(const StratArgs& a, int* tco, int* tck, int base, int t1, int tid,
                                        int nthr)
 {
-    for (int u = tid; u < kTileCache + 2; u += nthr) {
+    for (int u = tid; u < kTileCache + 1; u += nthr) {
         const int t = base + u;
         tco[u] = t <= t1 ? a.tile_off[t] : 0;
         if (u < kTileCache) tck[u] = t < t1 ? a.tile_k[t] : 0;
     }
 }
 
+// n consecutive records into LDS, eight loads in flight per thread.
+__device__ inline void load_records(uint2* dst, const uint2* src, int n, int tid)
+{
+    constexpr int U = 8;
+    for (int b = tid; b < n; b += U * kStratThreads) {
+        uint2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = b + u * kStratThreads;
+            v[u] = src[i < n ? i : n - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = b + u * kStratThreads;
+            if (i < n) dst[i] = v[u];
+        }
+    }
+}
+
+// Cross-lane moves on the VALU (DPP), no LDS round trip.
+template <int CTRL, int ROWS>
+__device__ inline float dpp_move(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, true));
+}
+template <int CTRL>
+__device__ inline int dpp_move_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, true);
+}
+constexpr int kDppRowShr = 0x110;   // + n: lane l of a 16-lane row reads lane l-n of the row
+constexpr int kDppRowBcast15 = 0x142;  // lane 15 of each row to the next row
+constexpr int kDppRowBcast31 = 0x143;  // lane 31 to rows 2 and 3
+constexpr int kDppWaveShr1 = 0x138;    // lane l reads lane l-1
+constexpr int kDppWaveShl1 = 0x130;    // lane l reads lane l+1
+
 // Inclusive segmented scan over the lanes of a wavefront: lane l returns the
-// sum of v over lanes head..l (head <= l), added in a fixed tree order.
+// sum of v over lanes head..l (head <= l), added in a fixed tree order:
+// Hillis-Steele steps of 1, 2, 4, 8 inside each 16-lane row, then the row
+// totals carried across rows.
 __device__ inline float seg_scan(float v, int lane, int head)
 {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const float t = __shfl_up(v, d);
-        if (lane - d >= head) v += t;
-    }
+    const int r = lane & 15, row = lane >> 4;
+    float t;
+    t = dpp_move<kDppRowShr + 1, 0xf>(v);
+    if (r >= 1 && lane - 1 >= head) v += t;
+    t = dpp_move<kDppRowShr + 2, 0xf>(v);
+    if (r >= 2 && lane - 2 >= head) v += t;
+    t = dpp_move<kDppRowShr + 4, 0xf>(v);
+    if (r >= 4 && lane - 4 >= head) v += t;
+    t = dpp_move<kDppRowShr + 8, 0xf>(v);
+    if (r >= 8 && lane - 8 >= head) v += t;
+    t = dpp_move<kDppRowBcast15, 0xa>(v);
+    if ((row & 1) && head <= 16 * row - 1) v += t;
+    t = dpp_move<kDppRowBcast31, 0xc>(v);
+    if (row >= 2 && head <= 31) v += t;
     return v;
 }
 
@@ -362,6 +410,7 @@ struct TileLds {
     float* Skw;   // [kWaves][I3*J1*J2]
     int* Mk;
     int *tco, *tck;
+    uint2* rec;   // [rec_cap] staged records
 };
 
 // The tiles of block (p, q), run by the whole workgroup (kStratThreads
@@ -381,38 +430,48 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
     const int blk = p * a.P + q;
     const int t0 = a.blk_tile[blk], t1 = a.blk_tile[blk + 1];
     if (t0 >= t1) return;
-    int base = t0;
-    load_tile_cache(a, L.tco, L.tck, base, t1, tid, kStratThreads);
-    __syncthreads();
 
     SAcc<MP> acc;
     acc.zero();
     float* Skmine = L.Skw + w * a.I3 * J12;
     int curk = -1;
-    uint2 wnext = make_uint2(0u, 0u);
-    {
-        const int off = L.tco[0], n = L.tco[1] - off;
-        if (lane < n) wnext = a.nz[off + lane];
-    }
-    for (int tl = t0; tl < t1; ++tl) {
-        if (tl - base == kTileCache) {
-            base = tl;
-            load_tile_cache(a, L.tco, L.tck, base, t1, tid, kStratThreads);
-            __syncthreads();
-        }
-        const int u = tl - base;
+    // for small cores the owned rows and columns of H_k stay in registers
+    // while consecutive tiles share the platform k
+    constexpr bool kHreg = JP <= 12;
+    float hr[kHreg ? QN : 1][kHreg ? JP : 1], hc[kHreg ? QN : 1][kHreg ? JP : 1];
+    int tl = t0;
+    while (tl < t1) {
+        // a chunk: up to kTileCache tiles whose records fit in rec_cap,
+        // metadata and records brought into LDS with many loads in flight
+        const int base = tl;
+        load_tile_cache(a, L.tco, L.tck, base, t1, tid, kStratThreads);
+        __syncthreads();
+        const int ntc = (t1 - base) < kTileCache ? (t1 - base) : kTileCache;
+        const int cend = __syncthreads_count(tid < ntc && L.tco[tid + 1] - L.tco[0] <= a.rec_cap);
+        const int z0 = L.tco[0], nrec = L.tco[cend] - z0;
+        load_records(L.rec, a.nz + z0, nrec, tid);
+        __syncthreads();
+        for (int u = 0; u < cend; ++u, ++tl) {
         const int off = L.tco[u];
         const int n = L.tco[u + 1] - off;
         const int k = L.tck[u];
-        const uint2 wv = wnext;
-        if (tl + 1 < t1) {  // prefetch the next tile's records
-            const int o2 = L.tco[u + 1], n2 = L.tco[u + 2] - o2;
-            wnext = lane < n2 ? a.nz[o2 + lane] : make_uint2(0u, 0u);
-        }
+        const uint2 wv = lane < n ? L.rec[off - z0 + lane] : make_uint2(0u, 0u);
         if (k != curk) {
             if (curk >= 0) acc.flush(Skmine + curk * J12, J1, J2, lane);
             acc.zero();
             curk = k;
+            if constexpr (kHreg) {
+                const float* Hk = L.Hs + k * JP * JP;
+#pragma unroll
+                for (int qq = 0; qq < QN; ++qq) {
+                    const int c = w + kWaves * qq < JP ? w + kWaves * qq : 0;
+#pragma unroll
+                    for (int y = 0; y < JP; ++y) {
+                        hr[qq][y] = Hk[c * JP + y];
+                        hc[qq][y] = Hk[y * JP + c];
+                    }
+                }
+            }
         }
         const bool act = lane < n;
         const uint32_t wd = wv.x;
@@ -436,10 +495,17 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
             const int c = w + kWaves * qq;
             float t1v = 0.f, t2v = 0.f, ac = 0.f;
             if (c < JP) {
+                if constexpr (kHreg) {
 #pragma unroll
-                for (int y = 0; y < JP; ++y) t1v = fmaf(H[c * JP + y], bv[y], t1v);
+                    for (int y = 0; y < JP; ++y) t1v = fmaf(hr[qq][y], bv[y], t1v);
 #pragma unroll
-                for (int x_ = 0; x_ < JP; ++x_) t2v = fmaf(av[x_], H[x_ * JP + c], t2v);
+                    for (int x_ = 0; x_ < JP; ++x_) t2v = fmaf(av[x_], hc[qq][x_], t2v);
+                } else {
+#pragma unroll
+                    for (int y = 0; y < JP; ++y) t1v = fmaf(H[c * JP + y], bv[y], t1v);
+#pragma unroll
+                    for (int x_ = 0; x_ < JP; ++x_) t2v = fmaf(av[x_], H[x_ * JP + c], t2v);
+                }
                 ac = act ? L.Ab[il * RS + c] : 0.f;
                 xw = fmaf(ac, t1v, xw);
             }
@@ -481,7 +547,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         // 3. matrix-core sums; fixed-order run sums; owned columns of the rows
         acc.accumulate(L.As, L.Es, n, w, lane);
         {
-            const int il_up = __shfl_up(il, 1), il_dn = __shfl_down(il, 1);
+            const int il_up = dpp_move_i<kDppWaveShr1>(il), il_dn = dpp_move_i<kDppWaveShl1>(il);
             const bool ifirst = act && (lane == 0 || il_up != il);
             const bool ilast = act && (lane == 63 || il_dn != il);
             const int head = run_head(__ballot(ifirst), lane);
@@ -497,7 +563,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         }
         {
             const int sj = lane < n ? L.slotJ[lane] : -1;
-            const int sj_up = __shfl_up(sj, 1), sj_dn = __shfl_down(sj, 1);
+            const int sj_up = dpp_move_i<kDppWaveShr1>(sj), sj_dn = dpp_move_i<kDppWaveShl1>(sj);
             const bool jfirst = lane < n && (lane == 0 || sj_up != sj);
             const bool jlast = lane < n && (lane == 63 || sj_dn != sj);
             const int head = run_head(__ballot(jfirst), lane);
@@ -516,6 +582,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         }
         if (tid == 0) L.Mk[k] += n;
         __syncthreads();
+        }
     }
     acc.flush(Skmine + curk * J12, J1, J2, lane);
     __syncthreads();
@@ -533,41 +600,38 @@ __device__ inline void combine_waves(float* Sk, const float* Skw, int ni, int ti
 }
 
 // ---------------------------------------------------------------------------
-// Grid barrier for the persistent kernel.  Returns false (for every thread
-// of the workgroup) if the barrier gave up: another workgroup timed out or
-// this one waited far longer than any stratum can take.
+// Grid barrier for the persistent kernel: a monotone arrival counter (zeroed
+// before the launch).  Barrier number b of the launch is passed when the
+// counter reaches nblocks * b; arrivals do not wait for their atomic to
+// return, and nobody resets anything, so the last arrival releases the
+// others by itself.  Returns false (for every thread of the workgroup) if
+// the barrier gave up: another workgroup timed out, or this one waited far
+// longer than any stratum can take.
 // ---------------------------------------------------------------------------
 constexpr unsigned kSpinLimit = 1u << 25;
 
-__device__ bool grid_sync(GridBar* bar, unsigned nblocks, unsigned& gen, int* flag)
+__device__ bool grid_sync(GridBar* bar, unsigned nblocks, unsigned& nbar, int* flag)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        const unsigned g = gen;
+        const unsigned target = nblocks * ++nbar;
         __threadfence();
-        const unsigned arrived = atomicAdd(&bar->count, 1u);
-        if (arrived == nblocks - 1) {
-            atomicExch(&bar->count, 0u);
-            __threadfence();
-            atomicAdd(&bar->gen, 1u);
-        } else {
-            unsigned spins = 0;
-            while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                if (__hip_atomic_load(&bar->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > kSpinLimit) {
-                    atomicOr(&bar->err, 1u);
-                    ok = 0;
-                    break;
-                }
+        __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned spins = 0;
+        while (__hip_atomic_load(&bar->count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(&bar->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit) {
+                atomicOr(&bar->err, 1u);
+                ok = 0;
+                break;
             }
         }
         __threadfence();
-        gen = g + 1;
         *flag = ok;
     }
     __syncthreads();
@@ -593,6 +657,7 @@ __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
     L.Mk = reinterpret_cast<int*>(lds + S.mk);
     L.tco = reinterpret_cast<int*>(lds + S.tco);
     L.tck = reinterpret_cast<int*>(lds + S.tck);
+    L.rec = reinterpret_cast<uint2*>(lds + S.rec);
     return L;
 }
 
@@ -609,7 +674,7 @@ __global__ __launch_bounds__(kStratThreads) void strata_persistent(StratArgs a)
     const int q = blockIdx.x;
     const int P = a.P, I3 = a.I3, J1 = a.J1, J2 = a.J2, J3 = a.J3, J12 = J1 * J2;
     const int ni = I3 * J12;
-    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3);
+    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3, a.rec_cap);
     const TileLds L = tile_lds<JP>(lds, S);
     float* Cs = lds + S.c;
     float* Gs = lds + S.g;
@@ -627,8 +692,7 @@ __global__ __launch_bounds__(kStratThreads) void strata_persistent(StratArgs a)
     for (int l = tid; l < r2; l += NT) lds[S.rb + l] = a.reg2[s2 + l];
     for (int idx = tid; idx < I3 * J3; idx += NT) Cs[idx] = a.C[idx];
     for (int idx = tid; idx < J12 * J3; idx += NT) Gs[idx] = a.G[idx];
-    unsigned gen = 0;
-    if (tid == 0) gen = __hip_atomic_load(&a.bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned nbar = 0;  // grid barriers passed so far (thread 0)
     __syncthreads();
 
     // this workgroup's share of the stratum reduction
@@ -651,11 +715,11 @@ __global__ __launch_bounds__(kStratThreads) void strata_persistent(StratArgs a)
         float* Sp = a.Spart + (size_t)p * ni;
         for (int idx = tid; idx < ni; idx += NT) Sp[idx] = Sk[idx];
         for (int k = tid; k < I3; k += NT) a.Mpart[p * I3 + k] = L.Mk[k];
-        if (!grid_sync(a.bar, P, gen, flag)) return;
+        if (!grid_sync(a.bar, P, nbar, flag)) return;
 
         stratum_counts(a.Mpart, P, I3, L.Mk, msum, tid, NT);
         reduce_items(a.Spart, P, ni, i0, i1, a.Ssum + i0, red, tid, NT);
-        if (!grid_sync(a.bar, P, gen, flag)) return;
+        if (!grid_sync(a.bar, P, nbar, flag)) return;
 
         for (int idx = tid; idx < ni; idx += NT) Sk[idx] = a.Ssum[idx];
         __syncthreads();
@@ -686,7 +750,7 @@ __global__ __launch_bounds__(kStratThreads) void block_step(StratArgs a)
     const int p = blockIdx.x, P = a.P;
     const int q = (p + a.s) % P;
     const int I3 = a.I3, J1 = a.J1, J2 = a.J2, J3 = a.J3, J12 = J1 * J2, ni = I3 * J12;
-    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3);
+    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3, a.rec_cap);
     const TileLds L = tile_lds<JP>(lds, S);
     float* Cs = lds + S.c;
     float* Gs = lds + S.g;
