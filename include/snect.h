@@ -165,6 +165,16 @@ int snect_decompose(snect_ctx *ctx, const snect_tensor *X, const snect_graph *Y,
                     const snect_params *params, const snect_factors *init, snect_factors *out,
                     int32_t start_epoch, int32_t epochs, double *loss, double *rmse);
 
+/* Algorithm 1's last step: for n = 1, 2, 3, U(n) = Q R with R upper
+ * triangular and a positive diagonal, U(n) <- Q and G <- G x_n R, so the
+ * model values are unchanged and every factor gets orthonormal columns.
+ * Device factors in place (A is I1 x J1 and so on); the arithmetic is FP64
+ * (CholeskyQR2: Gram matrix, Cholesky, triangular solve, twice).  Needs
+ * J_n <= I_n.  Errors: E_ARG (also a rank-deficient factor), E_RANK, E_OOM,
+ * E_HIP.  Allocates and frees its own scratch; synchronises the stream. */
+int snect_orthonormalize(snect_ctx *ctx, int32_t I1, int32_t I2, int32_t I3, int32_t J1, int32_t J2, int32_t J3,
+                         snect_factors *f);
+
 /* The plan's seeded draws, for cross-checks: perm1[I1] and perm2[I2] (the
  * row at each position of the patient / gene permutation; block of position
  * r is floor(r P / I)), strata[P] (stratum order of `epoch`).  Any pointer
@@ -198,6 +208,70 @@ int snect_set_exec(snect_problem *prob, const snect_exec *exec);
 
 /* The stratum driver the next snect_train call will use (SNECT_PATH_*). */
 int snect_exec_path(const snect_problem *prob);
+
+/* ------------------------------------------------------------------------
+ * Fold-in and top-k search for new patients (Section 3.2.1, Eq. 6) with
+ * continuous batching.  With B, C, G fixed, a new patient's observed cells
+ * (j_t, k_t, x_t) give rows w_t = G x2 b_{j_t} x3 c_{k_t}; the server finds
+ *     u = argmin 1/2 |x - W u|^2 + lambda/2 |u|^2
+ * (Eq. 6 with a ridge term) in FP64: pg_iters projected-gradient steps from
+ * u = 0 with step 1/|Q|_F, Q = W^T W + lambda I, then one refinement
+ * u <- u + Q^{-1}(r - Q u) through a Cholesky factorisation of Q (the exact
+ * minimiser).  It then returns the topk rows of A with the largest cosine
+ * similarity to u (rows of zero norm excluded, ties to the lower row index;
+ * missing entries are -1 with score -inf).
+ *
+ * Requests are admitted while a slot (one HIP stream each) and room in the
+ * device request pool (12 bytes per cell, 256-byte aligned) are free; each
+ * runs on its own stream, so requests overlap on the device.  A request's
+ * result does not depend on the others in flight.
+ * ---------------------------------------------------------------------- */
+typedef struct snect_server snect_server;
+
+typedef struct {
+    int32_t max_slots;   /* requests in flight at once, 1..64              */
+    int64_t pool_bytes;  /* device memory for request cells (>= 4096)      */
+    int32_t pg_iters;    /* projected-gradient steps before the refinement */
+    int32_t topk;        /* neighbours returned, 1..64 (<= I1)             */
+    double lambda;       /* ridge weight, >= 0                             */
+} snect_server_config;
+
+/* A, B, C, G: device factors (row-major FP32, A is I1 x J1, ...).  The
+ * server precomputes the rows w for every (gene, platform) cell and the row
+ * norms of A, and keeps reading A: the factors must stay alive and unchanged
+ * while the server exists.  Errors: E_ARG, E_RANK, E_OOM, E_HIP. */
+int snect_server_create(snect_ctx *ctx, int32_t I1, int32_t I2, int32_t I3, int32_t J1, int32_t J2, int32_t J3,
+                        const snect_factors *f, const snect_server_config *cfg, snect_server **srv);
+
+/* Waits for requests in flight and frees the server. */
+int snect_server_destroy(snect_server *srv);
+
+/* Admit one request: nnz cells j[], k[] (0-based gene and platform) and
+ * values x[] (host memory, copied before the call returns).  *ticket
+ * identifies it for snect_server_poll.  Errors: E_BUSY (no free slot or no
+ * room in the pool now: try again after a completion), E_UNSUPPORTED (the
+ * request needs more than the whole pool: 3 * 4 * nnz bytes, each array
+ * rounded up to 256), E_INDEX, E_ARG (bad or non-finite input), E_OOM, E_HIP.  A failed submit changes
+ * nothing. */
+int snect_server_submit(snect_server *srv, int64_t nnz, const int32_t *j, const int32_t *k, const float *x,
+                        int64_t *ticket);
+
+/* 0 while the request runs; 1 when it is done, with u[J1], idx[topk] and
+ * score[topk] filled (any may be NULL) and the ticket retired; E_ARG if
+ * the fold-in system was not positive definite (lambda = 0 and too few
+ * cells) or the ticket is unknown; E_HIP. */
+int snect_server_poll(snect_server *srv, int64_t ticket, double *u, int32_t *idx, double *score);
+
+/* Open-loop replay of a request stream in native code: request r arrives
+ * arrival_s[r] seconds after the start (non-decreasing) and has the cells
+ * offsets[r] .. offsets[r+1]-1 of j, k, x.  Requests are submitted as they
+ * arrive and as slots and pool room free up, completions are polled, and
+ * latency_s[r] = completion - arrival.  u [nreq*J1], idx and score
+ * [nreq*topk] and status [nreq] (SNECT_OK or the request's error) may be
+ * NULL.  *wall_s receives the total time. */
+int snect_server_replay(snect_server *srv, int64_t nreq, const double *arrival_s, const int64_t *offsets,
+                        const int32_t *j, const int32_t *k, const float *x, double *latency_s, double *u,
+                        int32_t *idx, double *score, int32_t *status, double *wall_s);
 
 #ifdef __cplusplus
 }

@@ -8,6 +8,8 @@ Two layers:
   * ``snect_oracle.c`` (built into ``liboracle.so`` by :func:`build`): the
     plan, the stratified SGD iteration and the objective, in FP64 C with
     OpenMP over the independent blocks of a stratum;
+  * Algorithm 1 read literally on one core (``run_literal``), the
+    comparison run for the stratified schedule;
   * plain numpy definitions in this module: the dense Tucker model (Eq. 2 via
     the mode-n products of Eq. 1), the objective f_opt (Eq. 3 + lambda_g
     Eq. 4), its per-nonzero split (Section 2.3.2) and finite-difference
@@ -56,6 +58,9 @@ def _load():
     lib.oracle_run.restype = ctypes.c_int
     lib.oracle_run.argtypes = [ctypes.c_void_p] * 5 + [ctypes.c_int32, ctypes.c_int32,
                                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+    lib.oracle_run_literal.restype = ctypes.c_int
+    lib.oracle_run_literal.argtypes = [ctypes.c_void_p] * 5 + [ctypes.c_int32, ctypes.c_int32,
+                                                               ctypes.c_void_p, ctypes.c_void_p]
     lib.oracle_loss.restype = ctypes.c_double
     lib.oracle_loss.argtypes = [ctypes.c_void_p] * 7
     lib.oracle_model_values.restype = None
@@ -150,6 +155,26 @@ def run(prob: Problem, A, B, C, G, epochs: int, start_epoch: int = 0, threads: i
     if rc != 0:
         raise OracleError(rc)
     return A, B, C, G, loss[:epochs], rmse[:epochs]
+
+
+def run_literal(prob: Problem, A, B, C, G, epochs: int, start_epoch: int = 0):
+    """Algorithm 1 read literally on one core (per-nonzero C and G steps,
+    nonzeros and edges interleaved in a seeded random order); the comparison
+    run for the stratified schedule.  Returns (A, B, C, G, loss[], rmse[])."""
+    lib = _load()
+    I1, I2, I3 = prob.dims
+    J1, J2, J3 = prob.ranks
+    A = _f64(A, (I1, J1)); B = _f64(B, (I2, J2)); C = _f64(C, (I3, J3)); G = _f64(G, (J1, J2, J3))
+    loss = np.zeros(max(epochs, 1)); rmse = np.zeros(max(epochs, 1))
+    s = prob._c()
+    rc = lib.oracle_run_literal(ctypes.byref(s), A.ctypes.data, B.ctypes.data, C.ctypes.data, G.ctypes.data,
+                                int(start_epoch), int(epochs), loss.ctypes.data, rmse.ctypes.data)
+    if rc != 0:
+        raise OracleError(rc)
+    return A, B, C, G, loss[:epochs], rmse[:epochs]
+
+
+LITERAL_STREAM = 1 << 32  # stream offset of the literal run's visiting order
 
 
 def loss(prob: Problem, A, B, C, G):

@@ -582,6 +582,99 @@ done:
     return rc;
 }
 
+/* ------------------------------------------------------------------ */
+/* Algorithm 1 read literally (comparison run, not the library's       */
+/* schedule)                                                          */
+/* ------------------------------------------------------------------ */
+
+/* Stream offset of the literal run's per-epoch visiting order; far from the
+ * streams of the SNeCT-S plan (0, 1 and 2 + epoch). */
+#define ORC_LITERAL_STREAM 0x100000000ull
+
+/* Algorithm 1 on one core: each epoch visits the nnz nonzeros and the E
+ * edges once, in one random interleaving (a Fisher-Yates shuffle of item ids
+ * 0..nnz+E-1, id < nnz a nonzero, else edge id - nnz, drawn from stream
+ * ORC_LITERAL_STREAM + epoch).  A nonzero updates a_i, b_j, c_k and G at
+ * once with the Eq. (5) gradients evaluated at the values before the item,
+ * step eta for every mode and for the core (one core, so the paper's
+ * eta * P core step is eta); an edge (u, v, w) moves b_u and b_v towards
+ * each other, both from their values before the item.  Loss and RMSE at
+ * the end of every epoch.  P and T of the problem are not used. */
+int oracle_run_literal(const oracle_problem *pr, double *A, double *B, double *C, double *G,
+                       int32_t start_epoch, int32_t epochs, double *loss, double *rmse)
+{
+    oracle_plan_t *pl = NULL;
+    int rc = oracle_plan_build(pr, &pl); /* validation and slice counts */
+    if (rc) return rc;
+    const int J1 = pr->J1, J2 = pr->J2, J3 = pr->J3;
+    const int64_t NG = (int64_t)J1 * J2 * J3, nit = pr->nnz + pr->E;
+    int32_t *items = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nit > 0 ? nit : 1));
+    double *wa = (double *)malloc(sizeof(double) * J1), *wb = (double *)malloc(sizeof(double) * J2);
+    double *wc = (double *)malloc(sizeof(double) * J3), *a0 = (double *)malloc(sizeof(double) * J1);
+    double *b0 = (double *)malloc(sizeof(double) * J2), *c0 = (double *)malloc(sizeof(double) * J3);
+    double *G0 = (double *)malloc(sizeof(double) * NG);
+    if (!items || !wa || !wb || !wc || !a0 || !b0 || !c0 || !G0 || nit >= (int64_t)1 << 31) {
+        rc = ORC_E_OOM;
+        goto done;
+    }
+    for (int32_t ep = start_epoch; ep < start_epoch + epochs; ++ep) {
+        for (int64_t t = 0; t < nit; ++t) items[t] = (int32_t)t;
+        oracle_shuffle(items, nit, pr->seed, ORC_LITERAL_STREAM + (uint64_t)ep);
+        for (int64_t t = 0; t < nit; ++t) {
+            const int64_t id = items[t];
+            if (id < pr->nnz) {
+                const int32_t i = pr->i[id], j = pr->j[id], k = pr->k[id];
+                double *a = A + (int64_t)i * J1, *b = B + (int64_t)j * J2, *c = C + (int64_t)k * J3;
+                memcpy(a0, a, sizeof(double) * J1);
+                memcpy(b0, b, sizeof(double) * J2);
+                memcpy(c0, c, sizeof(double) * J3);
+                memcpy(G0, G, sizeof(double) * NG);
+                /* partial products of G with two of the three rows */
+                for (int r = 0; r < J1; ++r) wa[r] = 0.0;
+                for (int q = 0; q < J2; ++q) wb[q] = 0.0;
+                for (int s = 0; s < J3; ++s) wc[s] = 0.0;
+                for (int r = 0; r < J1; ++r)
+                    for (int q = 0; q < J2; ++q)
+                        for (int s = 0; s < J3; ++s) {
+                            const double g = G0[((int64_t)r * J2 + q) * J3 + s];
+                            wa[r] += g * b0[q] * c0[s];
+                            wb[q] += g * a0[r] * c0[s];
+                            wc[s] += g * a0[r] * b0[q];
+                        }
+                double xt = 0.0;
+                for (int r = 0; r < J1; ++r) xt += a0[r] * wa[r];
+                const double err = pr->x[id] - xt, eta = pr->lr;
+                for (int r = 0; r < J1; ++r) a[r] = a0[r] + eta * (err * wa[r] - pr->lam / (double)pl->n1[i] * a0[r]);
+                for (int q = 0; q < J2; ++q) b[q] = b0[q] + eta * (err * wb[q] - pr->lam / (double)pl->n2[j] * b0[q]);
+                for (int s = 0; s < J3; ++s) c[s] = c0[s] + eta * (err * wc[s] - pr->lam / (double)pl->n3[k] * c0[s]);
+                for (int r = 0; r < J1; ++r)
+                    for (int q = 0; q < J2; ++q)
+                        for (int s = 0; s < J3; ++s) {
+                            const int64_t g = ((int64_t)r * J2 + q) * J3 + s;
+                            G[g] = G0[g] + eta * (err * a0[r] * b0[q] * c0[s] - pr->lam / (double)pr->nnz * G0[g]);
+                        }
+            } else {
+                const int64_t e = id - pr->nnz;
+                const double w = pr->ew ? pr->ew[e] : 1.0, al = pr->lr * pr->lam_g * w;
+                double *bu = B + (int64_t)pr->eu[e] * J2, *bv = B + (int64_t)pr->ev[e] * J2;
+                for (int q = 0; q < J2; ++q) {
+                    const double d = bu[q] - bv[q];
+                    bu[q] -= al * d;
+                    bv[q] += al * d;
+                }
+            }
+        }
+        double r = 0.0;
+        double f = oracle_loss(pr, A, B, C, G, &r, NULL);
+        if (loss) loss[ep - start_epoch] = f;
+        if (rmse) rmse[ep - start_epoch] = r;
+    }
+done:
+    free(items); free(wa); free(wb); free(wc); free(a0); free(b0); free(c0); free(G0);
+    oracle_plan_free(pl);
+    return rc;
+}
+
 /* Export the plan for cross-checks: perm1[I1], perm2[I2], order[nnz] (ids in
  * plan order), tile_start[ntiles+1] (needs room for nnz+1), block_tile[P*P+1],
  * strata[P] = stratum order of `epoch`.  *ntiles receives the tile count. */

@@ -11,6 +11,8 @@ import ctypes
 import os
 import sys
 import weakref
+
+_finalizing = sys.is_finalizing
 from dataclasses import dataclass
 from typing import Optional
 
@@ -33,7 +35,8 @@ EXPORTS = (
     "snect_create", "snect_destroy", "snect_last_error", "snect_problem_create",
     "snect_problem_destroy", "snect_problem_info", "snect_train", "snect_evaluate",
     "snect_decompose", "snect_plan_export", "snect_last_timing", "snect_set_exec",
-    "snect_exec_path",
+    "snect_exec_path", "snect_orthonormalize", "snect_server_create", "snect_server_destroy",
+    "snect_server_submit", "snect_server_poll", "snect_server_replay",
 )
 PATH_AUTO, PATH_PERSISTENT, PATH_MULTI = 0, 1, 2
 
@@ -73,6 +76,11 @@ class Exec(ctypes.Structure):
     _fields_ = [("per_launch_timing", ctypes.c_int32), ("path", ctypes.c_int32)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("pool_bytes", ctypes.c_int64), ("pg_iters", ctypes.c_int32),
+                ("topk", ctypes.c_int32), ("lambda_", ctypes.c_double)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [("nnz", ctypes.c_int64), ("ntiles", ctypes.c_int64), ("edges_csr", ctypes.c_int64),
                 ("P", ctypes.c_int32), ("T", ctypes.c_int32), ("rows1_max", ctypes.c_int32),
@@ -110,6 +118,13 @@ def load(path: str = LIB_PATH):
         "snect_last_timing": (ctypes.c_int, [vp, vp]),
         "snect_set_exec": (ctypes.c_int, [vp, ctypes.POINTER(Exec)]),
         "snect_exec_path": (ctypes.c_int, [vp]),
+        "snect_orthonormalize": (ctypes.c_int, [vp, i32, i32, i32, i32, i32, i32, ctypes.POINTER(Factors)]),
+        "snect_server_create": (ctypes.c_int, [vp, i32, i32, i32, i32, i32, i32, ctypes.POINTER(Factors),
+                                               ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
+        "snect_server_destroy": (ctypes.c_int, [vp]),
+        "snect_server_submit": (ctypes.c_int, [vp, i64, vp, vp, vp, ctypes.POINTER(i64)]),
+        "snect_server_poll": (ctypes.c_int, [vp, i64, vp, vp, vp]),
+        "snect_server_replay": (ctypes.c_int, [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -188,7 +203,102 @@ class Context:
     def __del__(self):
         # at interpreter shutdown the HIP runtime may already be gone; the
         # process exit releases the memory
-        if sys.is_finalizing():
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def orthonormalize(ctx: "Context", A, B, C, G):
+    """snect_orthonormalize on torch device tensors (in place)."""
+    I1, J1 = A.shape
+    I2, J2 = B.shape
+    I3, J3 = C.shape
+    f = Factors()
+    f.A = _dev_ptr(A, (I1, J1), "A")
+    f.B = _dev_ptr(B, (I2, J2), "B")
+    f.C = _dev_ptr(C, (I3, J3), "C")
+    f.G = _dev_ptr(G, (J1, J2, J3), "G")
+    _check(load().snect_orthonormalize(ctx.h, I1, I2, I3, J1, J2, J3, ctypes.byref(f)), ctx.h)
+
+
+class Server:
+    """snect_server_*: fold-in and top-k search for new patients against
+    fixed device factors, with continuous batching."""
+
+    def __init__(self, ctx: "Context", A, B, C, G, max_slots: int = 16, pool_bytes: int = 256 << 20,
+                 pg_iters: int = 20, topk: int = 10, lam: float = 0.01):
+        I1, J1 = A.shape
+        I2, J2 = B.shape
+        I3, J3 = C.shape
+        self.ctx = ctx
+        self.J1, self.topk = int(J1), int(topk)
+        self._keep = (A, B, C, G)  # the server reads A while it lives
+        f = Factors()
+        f.A = _dev_ptr(A, (I1, J1), "A")
+        f.B = _dev_ptr(B, (I2, J2), "B")
+        f.C = _dev_ptr(C, (I3, J3), "C")
+        f.G = _dev_ptr(G, (J1, J2, J3), "G")
+        cfg = ServerConfig()
+        cfg.max_slots, cfg.pool_bytes, cfg.pg_iters = int(max_slots), int(pool_bytes), int(pg_iters)
+        cfg.topk, cfg.lambda_ = int(topk), float(lam)
+        h = ctypes.c_void_p()
+        _check(load().snect_server_create(ctx.h, I1, I2, I3, J1, J2, J3, ctypes.byref(f), ctypes.byref(cfg),
+                                          ctypes.byref(h)), ctx.h)
+        self.h = h
+        ctx._problems.add(self)
+
+    def submit(self, j, k, x) -> int:
+        """Returns a ticket; raises SnectError (code -8 when busy)."""
+        j = np.ascontiguousarray(j, dtype=np.int32)
+        k = np.ascontiguousarray(k, dtype=np.int32)
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        t = ctypes.c_int64()
+        _check(load().snect_server_submit(self.h, int(j.shape[0]), j.ctypes.data, k.ctypes.data, x.ctypes.data,
+                                          ctypes.byref(t)), self.ctx.h)
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while running, else (u, idx, score)."""
+        u = np.zeros(self.J1)
+        idx = np.zeros(self.topk, np.int32)
+        sc = np.zeros(self.topk)
+        rc = load().snect_server_poll(self.h, int(ticket), u.ctypes.data, idx.ctypes.data, sc.ctypes.data)
+        if rc == 0:
+            return None
+        if rc != 1:
+            _check(rc, self.ctx.h)
+        return u, idx, sc
+
+    def replay(self, arrival_s, offsets, j, k, x):
+        """Native open-loop replay; returns latencies, results and status."""
+        arrival_s = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        j = np.ascontiguousarray(j, dtype=np.int32)
+        k = np.ascontiguousarray(k, dtype=np.int32)
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        n = int(arrival_s.shape[0])
+        lat = np.zeros(n)
+        u = np.zeros((n, self.J1))
+        idx = np.zeros((n, self.topk), np.int32)
+        sc = np.zeros((n, self.topk))
+        st = np.zeros(n, np.int32)
+        wall = ctypes.c_double()
+        _check(load().snect_server_replay(self.h, n, arrival_s.ctypes.data, offsets.ctypes.data, j.ctypes.data,
+                                          k.ctypes.data, x.ctypes.data, lat.ctypes.data, u.ctypes.data,
+                                          idx.ctypes.data, sc.ctypes.data, st.ctypes.data,
+                                          ctypes.addressof(wall)), self.ctx.h)
+        return dict(latency_s=lat, u=u, idx=idx, score=sc, status=st, wall_s=wall.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().snect_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if _finalizing():
             return
         try:
             self.close()
@@ -293,7 +403,7 @@ class Problem:
             self.h = None
 
     def __del__(self):
-        if sys.is_finalizing():
+        if _finalizing():
             return
         try:
             self.close()
@@ -303,4 +413,4 @@ class Problem:
 
 __all__ = ["load", "Context", "Problem", "Hyper", "SnectError", "EXPORTS", "ERRORS",
            "PRECISION_FP32", "PRECISION_BF16", "LIB_PATH", "PATH_AUTO", "PATH_PERSISTENT",
-           "PATH_MULTI"]
+           "PATH_MULTI", "orthonormalize", "Server"]

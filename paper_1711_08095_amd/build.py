@@ -26,6 +26,9 @@ DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "
 SOURCES = [
     ("snect_host.cpp", False),
     ("snect_kernels.hip", True),
+    ("snect_qr.hip", True),
+    ("snect_serve.hip", True),
+    ("snect_server.cpp", False),
 ]
 
 

@@ -33,16 +33,6 @@
 
 using namespace snect;
 
-struct snect_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::string err;
-    size_t max_lds = 65536;
-    int num_cu = 0;
-    int coop = 0;
-    int live_problems = 0;  // problems still referring to this context
-};
-
 namespace {
 
 struct DevBuf {
@@ -843,6 +833,44 @@ int snect_set_exec(snect_problem* pr, const snect_exec* ex)
         return set_err(pr->ctx, SNECT_E_ARG, "unknown path");
     pr->per_launch = ex->per_launch_timing != 0;
     pr->path = ex->path;
+    return SNECT_OK;
+}
+
+int snect_orthonormalize(snect_ctx* ctx, int32_t I1, int32_t I2, int32_t I3, int32_t J1, int32_t J2, int32_t J3,
+                         snect_factors* f)
+{
+    if (!ctx) return SNECT_E_ARG;
+    ctx->err.clear();
+    int rc = check_factors(ctx, f);
+    if (rc) return rc;
+    if (I1 < 1 || I2 < 1 || I3 < 1 || J1 < 1 || J2 < 1 || J3 < 1)
+        return set_err(ctx, SNECT_E_ARG, "sizes must be positive");
+    if (J1 > SNECT_MAX_RANK || J2 > SNECT_MAX_RANK || J3 > SNECT_MAX_RANK || J1 > I1 || J2 > I2 || J3 > I3)
+        return set_err(ctx, SNECT_E_RANK, "orthonormalisation needs J_n <= I_n and J_n <= 32");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int Is[3] = {I1, I2, I3}, Js[3] = {J1, J2, J3};
+    float* Us[3] = {f->A, f->B, f->C};
+    size_t bytes = 0;
+    for (int n = 0; n < 3; ++n) bytes = std::max(bytes, qr_scratch_bytes(Is[n], Js[n], J1, J2, J3));
+    void* scratch = nullptr;
+    int* status = nullptr;
+    if (hipMalloc(&scratch, bytes) != hipSuccess || hipMalloc((void**)&status, 6 * sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (scratch) (void)hipFree(scratch);
+        return set_err(ctx, SNECT_E_OOM, "QR scratch allocation failed");
+    }
+    hipError_t e = hipMemsetAsync(status, 0, 6 * sizeof(int), ctx->stream);
+    for (int n = 0; n < 3 && e == hipSuccess; ++n)
+        e = launch_qr_mode(Us[n], Is[n], Js[n], f->G, J1, J2, J3, n, scratch, status + 2 * n, ctx->stream);
+    int hs[6] = {0, 0, 0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(scratch);
+    (void)hipFree(status);
+    if (e != hipSuccess) return set_err(ctx, SNECT_E_HIP, std::string("orthonormalize: ") + hipGetErrorString(e));
+    for (int n = 0; n < 3; ++n)
+        if (hs[2 * n] || hs[2 * n + 1])
+            return set_err(ctx, SNECT_E_ARG, "factor " + std::to_string(n + 1) + " is rank-deficient");
     return SNECT_OK;
 }
 

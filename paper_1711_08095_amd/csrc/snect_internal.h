@@ -5,6 +5,19 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
+// The opaque context of the C ABI.
+struct snect_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    size_t max_lds = 65536;
+    int num_cu = 0;
+    int coop = 0;
+    int live_problems = 0;  // problems and servers still referring to this context
+};
+
 namespace snect {
 
 // Nonzero record in plan order: .x = packed word, .y = float bits of x.
@@ -120,6 +133,10 @@ hipError_t launch_loss(const LossArgs& a, const GraphArgs& g, int jp, size_t lds
 hipError_t launch_permute(const float* src, float* dst, const int32_t* perm, int rows, int cols, int gather,
                           hipStream_t st);
 hipError_t prepare_kernels(int jp, size_t strata_lds, size_t loss_lds, size_t core_lds);
+// Orthonormalisation of one mode (FP64 CholeskyQR2); see snect_qr.hip.
+size_t qr_scratch_bytes(int I, int J, int J1, int J2, int J3);
+hipError_t launch_qr_mode(float* U, int I, int J, float* G, int J1, int J2, int J3, int mode, void* scratch,
+                          int* status, hipStream_t st);
 // Largest number of co-resident workgroups of the persistent kernel.
 int persistent_capacity(int jp, size_t lds);
 

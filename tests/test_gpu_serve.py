@@ -1,0 +1,134 @@
+"""Fold-in / top-k server on the GPU against the oracle, alone vs. in the mix,
+admission and error handling."""
+import numpy as np
+import pytest
+
+import oracle
+import snect_synth as synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    import paper_1711_08095_amd as sn
+    ctx = sn.Context(0)
+    rng = np.random.default_rng(5)
+    I1, I2, I3, J = 700, 900, 5, (10, 10, 5)
+    f = [rng.standard_normal((I1, J[0])) * 0.5, rng.standard_normal((I2, J[1])) * 0.5,
+         rng.standard_normal((I3, J[2])) * 0.5, rng.standard_normal(J) * 0.5]
+    f[0][13] = 0.0  # a zero-norm patient row is never returned
+    f = [a.astype(np.float32) for a in f]
+    t = [torch.tensor(a, device="cuda") for a in f]
+    reqs = synth.fold_in_requests(seed=77, count=24, I2=I2, I3=I3, nnz_lo=1, nnz_hi=3000)
+    yield ctx, f, t, reqs
+    ctx.close()
+
+
+def _oracle(f, r, lam, k=10):
+    A, B, C, G = (np.asarray(a, np.float64) for a in f)
+    u = oracle.fold_in(B, C, G, r["j"], r["k"], r["x"].astype(np.float64), lam=lam)
+    idx, sc = oracle.topk_cosine(A, u, k)
+    return u, idx, sc
+
+
+def _check(f, r, got, lam):
+    u, idx, sc = got
+    uo, io, so = _oracle(f, r, lam)
+    assert np.linalg.norm(u - uo) <= 1e-6 * max(np.linalg.norm(uo), 1e-12)
+    np.testing.assert_allclose(sc, so, rtol=1e-9, atol=1e-9)
+    # same set up to exact ties of the score
+    A = np.asarray(f[0], np.float64)
+    cos = (A @ uo) / (np.linalg.norm(A, axis=1) * np.linalg.norm(uo) + 1e-300)
+    assert np.all(np.abs(cos[idx] - so) <= 1e-9)
+
+
+def test_fold_in_and_topk_match_oracle(setup):
+    import paper_1711_08095_amd as sn
+    ctx, f, t, reqs = setup
+    srv = sn.Server(ctx, *t, max_slots=4, pg_iters=20, topk=10, lam=0.01)
+    for r in reqs[:8]:
+        tk = srv.submit(r["j"], r["k"], r["x"])
+        got = None
+        while got is None:
+            got = srv.poll(tk)
+        _check(f, r, got, 0.01)
+    srv.close()
+
+
+def test_alone_equals_in_the_mix(setup):
+    import paper_1711_08095_amd as sn
+    ctx, f, t, reqs = setup
+    srv = sn.Server(ctx, *t, max_slots=8, pg_iters=20, topk=10, lam=0.01)
+    alone = []
+    for r in reqs:
+        tk = srv.submit(r["j"], r["k"], r["x"])
+        got = None
+        while got is None:
+            got = srv.poll(tk)
+        alone.append(got)
+    # the same requests submitted as fast as slots allow, overlapping
+    pending, mixed, nxt = {}, {}, 0
+    while len(mixed) < len(reqs):
+        while nxt < len(reqs):
+            try:
+                pending[srv.submit(reqs[nxt]["j"], reqs[nxt]["k"], reqs[nxt]["x"])] = nxt
+                nxt += 1
+            except sn.SnectError as e:
+                assert e.code == -8
+                break
+        for tk in list(pending):
+            got = srv.poll(tk)
+            if got is not None:
+                mixed[pending.pop(tk)] = got
+    for a, (i, b) in zip(alone, sorted(mixed.items())):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+    srv.close()
+
+
+def test_replay_trace(setup):
+    import paper_1711_08095_amd as sn
+    ctx, f, t, reqs = setup
+    srv = sn.Server(ctx, *t, max_slots=4, pg_iters=20, topk=10, lam=0.01)
+    arr = np.array([r["arrival"] for r in reqs]) * 0.0  # all at once
+    offs = np.concatenate([[0], np.cumsum([len(r["j"]) for r in reqs])])
+    j = np.concatenate([r["j"] for r in reqs])
+    k = np.concatenate([r["k"] for r in reqs])
+    x = np.concatenate([r["x"] for r in reqs])
+    out = srv.replay(arr, offs, j, k, x)
+    assert np.all(out["status"] == 0)
+    assert np.all(out["latency_s"] >= 0)
+    for n in (0, 5, 23):
+        _check(f, reqs[n], (out["u"][n], out["idx"][n], out["score"][n]), 0.01)
+    srv.close()
+
+
+def test_admission_and_errors(setup):
+    import paper_1711_08095_amd as sn
+    ctx, f, t, reqs = setup
+    srv = sn.Server(ctx, *t, max_slots=2, pool_bytes=8192, pg_iters=5, topk=3, lam=0.0)
+    with pytest.raises(sn.SnectError) as e:
+        srv.submit(np.zeros(1000, np.int32), np.zeros(1000, np.int32), np.ones(1000, np.float32))
+    assert e.value.code == -9  # larger than the whole pool
+    with pytest.raises(sn.SnectError) as e:
+        srv.submit(np.array([900], np.int32), np.array([0], np.int32), np.ones(1, np.float32))
+    assert e.value.code == -2
+    # lambda = 0 and a single cell: the system is singular, that request fails alone
+    tk_bad = srv.submit(np.array([3], np.int32), np.array([1], np.int32), np.ones(1, np.float32))
+    r = reqs[1]
+    n = min(len(r["j"]), 200)
+    tk_ok = srv.submit(r["j"][:n], r["k"][:n], r["x"][:n])
+    with pytest.raises(sn.SnectError) as e:
+        while srv.poll(tk_bad) is None:
+            pass
+    assert e.value.code == -1
+    got = None
+    while got is None:
+        got = srv.poll(tk_ok)
+    sub = dict(j=r["j"][:n], k=r["k"][:n], x=r["x"][:n])
+    uo = oracle.fold_in(*(np.asarray(a, np.float64) for a in f[1:]), sub["j"], sub["k"],
+                        sub["x"].astype(np.float64), lam=0.0)
+    assert np.linalg.norm(got[0] - uo) <= 1e-6 * np.linalg.norm(uo)
+    srv.close()

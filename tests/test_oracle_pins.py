@@ -391,3 +391,100 @@ def test_validation_errors():
     big_p = oracle.Problem(prob.dims, prob.ranks, prob.i, prob.j, prob.k, prob.x, P=7)
     with pytest.raises(oracle.OracleError):
         oracle.run(big_p, A, B, C, G, 1)
+
+
+# --------------------------------------------------------------------------
+# QR post-step (last step of Algorithm 1)
+# --------------------------------------------------------------------------
+def test_qr_post_keeps_the_model_and_orthonormalises():
+    rng = np.random.default_rng(8)
+    dims, J = (30, 40, 6), (4, 5, 3)
+    A, B, C = (rng.standard_normal((d, r)) for d, r in zip(dims, J))
+    G = rng.standard_normal(J)
+    Q1, Q2, Q3, G2 = oracle.qr_post(A, B, C, G)
+    np.testing.assert_allclose(oracle.dense_model(G2, Q1, Q2, Q3), oracle.dense_model(G, A, B, C),
+                               rtol=1e-11, atol=1e-11)
+    for Q, U in ((Q1, A), (Q2, B), (Q3, C)):
+        np.testing.assert_allclose(Q.T @ Q, np.eye(Q.shape[1]), atol=1e-12)
+        R = Q.T @ U
+        np.testing.assert_allclose(np.tril(R, -1), 0, atol=1e-12)   # upper triangular
+        assert np.all(np.diag(R) > 0)                                  # positive diagonal
+        np.testing.assert_allclose(Q @ R, U, rtol=1e-12, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Fold-in (Eq. 6) and top-k search
+# --------------------------------------------------------------------------
+def test_fold_in_recovers_an_exact_profile():
+    rng = np.random.default_rng(12)
+    I2, I3, J = 40, 3, (4, 5, 2)
+    B, C = rng.standard_normal((I2, J[1])), rng.standard_normal((I3, J[2]))
+    G = rng.standard_normal(J)
+    cells = synth.sample_cells(rng, I2 * I3, 60)
+    j, k = cells // I3, cells % I3
+    u_true = rng.standard_normal(J[0])
+    # x = G x1 u x2 b_j x3 c_k, written with the dense model of a one-row A
+    x = oracle.dense_model(G, u_true[None, :], B, C)[0, j, k]
+    np.testing.assert_allclose(oracle.fold_in(B, C, G, j, k, x, lam=0.0), u_true, rtol=1e-10, atol=1e-12)
+
+
+def test_fold_in_ridge_solves_the_normal_equations():
+    rng = np.random.default_rng(13)
+    I2, I3, J = 30, 4, (3, 4, 2)
+    B, C = rng.standard_normal((I2, J[1])), rng.standard_normal((I3, J[2]))
+    G = rng.standard_normal(J)
+    cells = synth.sample_cells(rng, I2 * I3, 50)
+    j, k = cells // I3, cells % I3
+    x = rng.standard_normal(50)
+    lam = 0.7
+    W = np.stack([oracle.dense_model(G, np.eye(J[0]), B, C)[:, jj, kk] for jj, kk in zip(j, k)])
+    u = oracle.fold_in(B, C, G, j, k, x, lam=lam)
+    np.testing.assert_allclose((W.T @ W + lam * np.eye(J[0])) @ u, W.T @ x, rtol=1e-10, atol=1e-10)
+
+
+def test_topk_cosine_brute_force_with_ties_and_zero_rows():
+    A = np.array([[1.0, 0.0], [0.0, 0.0], [2.0, 0.0], [0.0, 1.0], [1.0, 1.0], [-1.0, 0.0]])
+    idx, sc = oracle.topk_cosine(A, np.array([3.0, 0.0]), k=4)
+    # rows 0 and 2 tie at cosine 1 (lower index first); row 1 has zero norm
+    assert idx.tolist() == [0, 2, 4, 3]
+    np.testing.assert_allclose(sc, [1.0, 1.0, np.sqrt(0.5), 0.0], atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1 read literally (comparison run)
+# --------------------------------------------------------------------------
+def test_literal_epoch_is_sequential_per_item_gradient_steps():
+    # one epoch visits nonzeros and edges in the seeded interleaving; each
+    # nonzero is a gradient step on its own term of the split objective
+    # (Section 2.3.2), each edge a step on its own network term (Eq. 4)
+    prob, (A, B, C, G) = _tiny(seed=3, dims=(4, 5, 2), ranks=(2, 3, 2), nnz=9, lam=0.2, lam_g=0.7,
+                               lr=0.05, edges=4)
+    A1, B1, C1, G1, loss, rmse = oracle.run_literal(prob, A, B, C, G, 1)
+    order = oracle.shuffle(prob.nnz + prob.eu.shape[0], prob.seed, oracle.LITERAL_STREAM)
+    f = [np.array(a, np.float64) for a in (A, B, C, G)]
+    for it in order:
+        if it < prob.nnz:
+            fun = lambda a, b, c, g: oracle.f_split(prob, a, b, c, g, subset=[it])
+            g = _grads(fun, *f)
+        else:
+            e = it - prob.nnz
+            u, v, w = prob.eu[e], prob.ev[e], prob.ew[e]
+            fun = lambda b: 0.5 * prob.lam_g * w * float(np.sum((b[u] - b[v]) ** 2))
+            g = [np.zeros_like(f[0]), oracle.fd_grad(fun, f[1]), np.zeros_like(f[2]), np.zeros_like(f[3])]
+        f = [x - prob.lr * gx for x, gx in zip(f, g)]
+    for got, ref in zip((A1, B1, C1, G1), f):
+        assert _rel(got, ref) < 1e-7
+    assert abs(loss[0] - oracle.f_opt_dense(prob, *f)) < 1e-8 * abs(loss[0])
+
+
+def test_literal_first_epoch_descends_on_planted_tensor():
+    p = synth.planted()
+    pr0 = oracle.Problem(p.dims, p.ranks, p.i, p.j, p.k, np.zeros(len(p.i)))
+    x = oracle.model_values(pr0, p.A, p.B, p.C, p.G) + p.noise
+    prob = oracle.Problem(p.dims, p.ranks, p.i, p.j, p.k, x, p.eu, p.ev, lam=0.01, lam_g=0.1,
+                          lr=1e-3, seed=synth.PLAN_SEED)
+    A, B, C, G = synth.normal_init(synth.INIT_SEED, p.dims, p.ranks, 1.0)
+    f0, _, _ = oracle.loss(prob, A, B, C, G)
+    *_, loss, _ = oracle.run_literal(prob, A, B, C, G, 1)
+    # plain SGD with a constant step only promises progress from far away
+    assert loss[0] < 0.1 * f0
