@@ -37,9 +37,16 @@ def parse():
     ap.add_argument("--nnz", type=int, default=25_000_000)
     ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-epochs", type=int, default=1)
+    ap.add_argument("--cpu-epochs", type=int, default=2)
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="fold-in requests replayed after training (0 = no serving leg)")
+    ap.add_argument("--serve-epochs", type=int, default=20,
+                    help="epochs the served factors are trained for")
     ap.add_argument("--path", choices=["auto", "persistent", "multi"], default="auto")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain elementwise device copy of 1 GiB (x3) and exit; its "
+                         "FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures")
     return ap.parse_args()
 
 
@@ -55,6 +62,9 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
+    if args.copy_probe:
+        copy_probe(torch)
+        return
     import paper_1711_08095_amd as sn
     import snect_synth as synth
 
@@ -148,6 +158,9 @@ def main():
         "final_rmse": float(rmse[-1]), "final_loss": float(loss[-1]),
     }
 
+    if args.serve_requests > 0:
+        out["serving"] = serve_leg(args, sn, synth, prob, f, dims, ranks)
+
     if not args.no_cpu_baseline:
         import oracle
         prob_o = oracle.Problem(dims, ranks, i, j, k, x.astype(np.float64), eu, ev, None, lam=0.01,
@@ -166,6 +179,62 @@ def main():
     prob.close()
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def copy_probe(torch):
+    """Three launches of a plain elementwise kernel that reads 1 GiB and
+    writes 1 GiB (out = -in), for calibrating the HBM byte counters."""
+    n = 1 << 28
+    a = torch.ones(n, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe": {"launches": 3, "read_bytes_per_launch": 4 * n,
+                                     "write_bytes_per_launch": 4 * n}}), flush=True)
+
+
+def serve_leg(args, sn, synth, prob, f, dims, ranks):
+    """Fold-in + top-10 serving of new patients against the factors after
+    `serve_epochs` epochs: open-loop Poisson arrivals at 2,000 requests/s,
+    nnz ~ U{2,000..60,000} (gene, platform) cells per request, 20
+    projected-gradient steps, FP64 Cholesky refinement, cosine top-10 over
+    the patient factor.  Latency = completion - arrival, queueing included."""
+    done = args.warmup + args.steps
+    if args.serve_epochs > done:
+        prob.train(*f, epochs=args.serve_epochs - done, start_epoch=done)
+    t0 = time.perf_counter()
+    reqs = synth.fold_in_requests(count=args.serve_requests, I2=dims[1], I3=dims[2])
+    arr = np.array([r["arrival"] for r in reqs])
+    offs = np.zeros(len(reqs) + 1, np.int64)
+    offs[1:] = np.cumsum([len(r["j"]) for r in reqs])
+    jj = np.concatenate([r["j"] for r in reqs])
+    kk = np.concatenate([r["k"] for r in reqs])
+    xx = np.concatenate([r["x"] for r in reqs])
+    log(f"serving: {len(reqs)} requests, {offs[-1]} cells, generated in {time.perf_counter() - t0:.1f}s",
+        args.quiet)
+    srv = sn.Server(prob.ctx, *f, max_slots=16, pool_bytes=256 << 20, pg_iters=20, topk=10, lam=0.01)
+    res = srv.replay(arr, offs, jj, kk, xx)
+    srv.close()
+    lat = res["latency_s"][res["status"] == 0] * 1e3
+    out = {"workload": "fold-in + cosine top-10, Poisson 2000 req/s, nnz U{2000..60000}, 20 PG steps",
+           "requests": len(reqs), "ok": int(np.sum(res["status"] == 0)), "factors_epochs": args.serve_epochs,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "mean_ms": float(np.mean(lat)), "queries_per_s": len(reqs) / res["wall_s"],
+           "offered_per_s": len(reqs) / max(arr[-1], 1e-9), "wall_s": res["wall_s"]}
+    if not args.no_cpu_baseline:
+        # the oracle's fold-in and top-k, one thread of numpy, on a few requests
+        import oracle
+        A, B, C, G = (t.double().cpu().numpy() for t in f)
+        tc = time.perf_counter()
+        nq = min(20, len(reqs))
+        for r in reqs[:nq]:
+            u = oracle.fold_in(B, C, G, r["j"], r["k"], r["x"].astype(np.float64), lam=0.01)
+            oracle.topk_cosine(A, u, 10)
+        out["cpu_oracle_ms_per_request"] = 1e3 * (time.perf_counter() - tc) / nq
+    log(f"serving p50 {out['p50_ms']:.3f} ms p99 {out['p99_ms']:.3f} ms, {out['queries_per_s']:.0f} q/s",
+        args.quiet)
+    return out
 
 
 if __name__ == "__main__":

@@ -99,6 +99,9 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1711_08095_amd.build`")
+    # torch brings the HIP runtime the library must share (device memory and
+    # streams come from torch), so it is loaded first
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {

@@ -120,7 +120,7 @@ double now_s()
 struct snect_problem {
     snect_ctx* ctx = nullptr;
     // shape and parameters
-    int32_t I1 = 0, I2 = 0, I3 = 0, J1 = 0, J2 = 0, J3 = 0, P = 1, T = 1, jp = 0;
+    int32_t I1 = 0, I2 = 0, I3 = 0, J1 = 0, J2 = 0, J3 = 0, P = 1, T = 1, jp = 0, bf = 0;
     int64_t nnz = 0, ntiles = 0, ecsr = 0;
     double lam = 0, lam_g = 0, lr = 0, cls = 1;
     uint64_t seed = 0;
@@ -257,7 +257,6 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
     if (pa->tile_T < 1 || pa->tile_T > SNECT_MAX_TILE) return set_err(ctx, SNECT_E_ARG, "tile_T must be in 1..64");
     if (pa->precision != SNECT_PRECISION_FP32 && pa->precision != SNECT_PRECISION_BF16)
         return set_err(ctx, SNECT_E_ARG, "unknown precision");
-    if (pa->precision == SNECT_PRECISION_BF16) return set_err(ctx, SNECT_E_UNSUPPORTED, "BF16 path not built");
     const int64_t E = Y ? Y->E : 0;
     if (E < 0 || E >= (int64_t(1) << 30)) return set_err(ctx, SNECT_E_ARG, "edge count out of range");
     if (E > 0 && (!Y->u || !Y->v)) return set_err(ctx, SNECT_E_ARG, "null edge array");
@@ -285,11 +284,13 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         return set_err(ctx, SNECT_E_UNSUPPORTED, "blocks too large to pack; raise strata_P");
     if (I3 > 4096) return set_err(ctx, SNECT_E_UNSUPPORTED, "at most 4096 platforms");
     if ((int64_t)P * P * I3 >= (int64_t(1) << 31)) return set_err(ctx, SNECT_E_UNSUPPORTED, "too many blocks");
+    const int bf = pa->precision == SNECT_PRECISION_BF16 ? 1 : 0;
     // the largest record chunk that still fits in LDS
     int rec_cap = 2048;
-    while (rec_cap > kTileMax && strata_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap) > ctx->max_lds)
+    while (rec_cap > kTileMax &&
+           strata_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf) > ctx->max_lds)
         rec_cap /= 2;
-    const size_t slds = strata_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap);
+    const size_t slds = strata_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf);
     const size_t blds = slds;
     const size_t llds = loss_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3);
     const size_t clds = core_lds_bytes(I3, J1, J2, J3, kCoreThreads);
@@ -303,7 +304,7 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
     pr->ctx = ctx;
     pr->I1 = I1; pr->I2 = I2; pr->I3 = I3;
     pr->J1 = J1; pr->J2 = J2; pr->J3 = J3;
-    pr->P = P; pr->T = T; pr->jp = jp; pr->nnz = nnz;
+    pr->P = P; pr->T = T; pr->jp = jp; pr->bf = bf; pr->nnz = nnz;
     pr->lam = pa->lambda; pr->lam_g = pa->lambda_g; pr->lr = pa->lr; pr->cls = pa->core_lr_scale;
     pr->seed = pa->seed;
     pr->rows1_max = rows1_max; pr->rows2_max = rows2_max; pr->bits_i = bits_i; pr->bits_j = bits_j;
@@ -532,13 +533,13 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         he = he ? he : up(pr->d_adj_w, adj_w.data(), adj_w.size() * 4);
         he = he ? he : up(pr->d_deg, deg.data(), (size_t)I2 * 4);
         he = he ? he : hipStreamSynchronize(st);
-        he = he ? he : prepare_kernels(jp, slds, llds, clds);
+        he = he ? he : prepare_kernels(jp, bf, slds, llds, clds);
         for (int t = 0; t < 4 && he == hipSuccess; ++t) he = hipEventCreate(&pr->ev[t]);
         if (he != hipSuccess) {
             delete pr;
             return set_err(ctx, SNECT_E_HIP, std::string("upload: ") + hipGetErrorString(he));
         }
-        pr->capacity = (ctx->coop && slds <= ctx->max_lds) ? persistent_capacity(jp, slds) : 0;
+        pr->capacity = (ctx->coop && slds <= ctx->max_lds) ? persistent_capacity(jp, bf, slds) : 0;
         pr->upload_s = now_s() - t_up0;
         ctx->live_problems++;
     } catch (const std::bad_alloc&) {
@@ -721,13 +722,13 @@ int snect_train(snect_problem* pr, snect_factors* f, int32_t start_epoch, int32_
             HIP_TRY(hipMemcpyAsync(pr->d_order, pr->h_order, (size_t)P * 4, hipMemcpyHostToDevice, st));
             HIP_TRY(hipMemsetAsync(pr->d_bar, 0, sizeof(GridBar), st));
             if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[0], st));
-            HIP_TRY(launch_strata_persistent(sa, pr->jp, pr->strata_lds, st));
+            HIP_TRY(launch_strata_persistent(sa, pr->jp, pr->bf, pr->strata_lds, st));
             if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[1], st));
         } else {
             for (int si = 0; si < P; ++si) {
                 sa.s = order[si];
                 if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[2 * si], st));
-                HIP_TRY(launch_block(sa, pr->jp, pr->block_lds, st));
+                HIP_TRY(launch_block(sa, pr->jp, pr->bf, pr->block_lds, st));
                 if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[2 * si + 1], st));
                 HIP_TRY(launch_core_step(sa, pr->core_lds, st));
             }

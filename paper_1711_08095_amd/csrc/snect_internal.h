@@ -118,29 +118,38 @@ struct GraphArgs {
     float alpha;
 };
 
-size_t strata_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3, int rec_cap);
+size_t strata_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3, int rec_cap,
+                        int bf);
 size_t loss_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3);
 size_t core_lds_bytes(int I3, int J1, int J2, int J3, int threads);
 int jp_for(int J1, int J2);
 
 // Persistent: one cooperative launch runs every stratum of one epoch.
-hipError_t launch_strata_persistent(const StratArgs& a, int jp, size_t lds, hipStream_t st);
-// Fallback: one launch per stratum plus one core-step launch.
-hipError_t launch_block(const StratArgs& a, int jp, size_t lds, hipStream_t st);
+hipError_t launch_strata_persistent(const StratArgs& a, int jp, int bf, size_t lds, hipStream_t st);
+// Fallback: one launch per stratum plus one core-step launch.  bf selects
+// the BF16 matrix-core contractions of the tile step.
+hipError_t launch_block(const StratArgs& a, int jp, int bf, size_t lds, hipStream_t st);
 hipError_t launch_core_step(const StratArgs& a, size_t lds, hipStream_t st);
 hipError_t launch_graph_step(const GraphArgs& a, int jp, hipStream_t st);
 hipError_t launch_loss(const LossArgs& a, const GraphArgs& g, int jp, size_t lds, hipStream_t st);
 hipError_t launch_permute(const float* src, float* dst, const int32_t* perm, int rows, int cols, int gather,
                           hipStream_t st);
-hipError_t prepare_kernels(int jp, size_t strata_lds, size_t loss_lds, size_t core_lds);
+hipError_t prepare_kernels(int jp, int bf, size_t strata_lds, size_t loss_lds, size_t core_lds);
 // Orthonormalisation of one mode (FP64 CholeskyQR2); see snect_qr.hip.
 size_t qr_scratch_bytes(int I, int J, int J1, int J2, int J3);
 hipError_t launch_qr_mode(float* U, int I, int J, float* G, int J1, int J2, int J3, int mode, void* scratch,
                           int* status, hipStream_t st);
 // Largest number of co-resident workgroups of the persistent kernel.
-int persistent_capacity(int jp, size_t lds);
+int persistent_capacity(int jp, int bf, size_t lds);
 
-constexpr int kStratThreads = 256;  // four wavefronts per block
+// Wavefronts per stratum workgroup (factor columns are shared among them) and
+// the four of them that accumulate the block's S on the matrix cores.
+#ifndef SNECT_STRAT_WAVES
+#define SNECT_STRAT_WAVES 8
+#endif
+__host__ __device__ constexpr int strat_waves(int jp) { return jp > 0 ? SNECT_STRAT_WAVES : SNECT_STRAT_WAVES; }
+__host__ __device__ constexpr int strat_threads(int jp) { return 64 * strat_waves(jp); }
+constexpr int kMfmaWaves = 4;
 constexpr int kCoreThreads = 1024;
 
 }  // namespace snect

@@ -42,9 +42,12 @@ namespace snect {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kTS = 66;  // pitch (words) of a staged column
-constexpr int kWaves = kStratThreads / 64;
+constexpr int kTW = 68;  // pitch (words) of a matrix-core output column (16-byte rows of 4)
+constexpr int kTB = 72;  // pitch (bf16 values) of a staged BF16 operand column
+constexpr int kKB = 32;  // K of the BF16 products (J padded to 32)
 
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
@@ -57,13 +60,14 @@ __device__ inline void lds_order_fence() { asm volatile("" ::: "memory"); }
 // ---------------------------------------------------------------------------
 struct StratLds {
     int a, b, ra, rb, c, g, h, sa, sb, as, es, xtp, slotj, skw, sk, mk, tco, tck, red, msum, cgt, flag, rec;
+    int hb, sw1, sw2, xts, esl, a16, e16;  // BF16 path only (zero-sized otherwise)
     int total;
 };
 
 __host__ __device__ inline int up4(int o) { return (o + 3) & ~3; }
 
 __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2,
-                                                     int J3, int rec_cap)
+                                                     int J3, int rec_cap, int bf)
 {
     const int rs = row_stride(jp), mp = mfma_dim(jp), j12 = J1 * J2;
     const int nch = (j12 + kCoreChunk - 1) / kCoreChunk;
@@ -76,18 +80,26 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     L.c = o;     o = up4(o + I3 * J3);
     L.g = o;     o = up4(o + j12 * J3);
     L.h = o;     o = up4(o + I3 * jp * jp);
-    L.sa = o;    o = up4(o + jp * kTS);
-    L.sb = o;    o = up4(o + jp * kTS);
-    L.as = o;    o = up4(o + mp * kTS);
-    L.es = o;    o = up4(o + mp * kTS);
-    L.xtp = o;   o = up4(o + kWaves * 64);
+    const int f32 = bf ? 0 : 1;
+    L.sa = o;    o = up4(o + f32 * jp * kTS);
+    L.sb = o;    o = up4(o + f32 * jp * kTS);
+    L.as = o;    o = up4(o + f32 * mp * kTS);
+    L.es = o;    o = up4(o + f32 * mp * kTS);
+    L.xtp = o;   o = up4(o + f32 * strat_threads(jp));
+    L.hb = o;    o = up4(o + bf * I3 * mp * kKB);        // 2 x I3 x mp x 32 bf16
+    L.sw1 = o;   o = up4(o + bf * mp * kTW);
+    L.sw2 = o;   o = up4(o + bf * mp * kTW);
+    L.xts = o;   o = up4(o + bf * kTileMax);
+    L.esl = o;   o = up4(o + bf * kTileMax);
+    L.a16 = o;   o = up4(o + bf * mp * kTB / 2);
+    L.e16 = o;   o = up4(o + bf * mp * kTB / 2);
     L.slotj = o; o = up4(o + kTileMax);
-    L.skw = o;   o = up4(o + kWaves * I3 * j12);
+    L.skw = o;   o = up4(o + kMfmaWaves * I3 * j12);
     L.sk = o;    o = up4(o + I3 * j12);
     L.mk = o;    o = up4(o + I3);
     L.tco = o;   o = up4(o + kTileCache + 1);
     L.tck = o;   o = up4(o + kTileCache);
-    L.red = o;   o = up4(o + (kStratThreads > I3 * J3 * nch ? kStratThreads : I3 * J3 * nch));
+    L.red = o;   o = up4(o + (strat_threads(jp) > I3 * J3 * nch ? strat_threads(jp) : I3 * J3 * nch));
     L.msum = o;  o = up4(o + 2 * I3);          // doubles
     L.cgt = o;   o = up4(o + I3 * J3 + j12 * J3);
     L.flag = o;  o = up4(o + 1);
@@ -96,9 +108,9 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     return L;
 }
 
-size_t strata_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3, int rec_cap)
+size_t strata_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3, int rec_cap, int bf)
 {
-    return align16(4 * (size_t)strat_lds_layout(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap).total);
+    return align16(4 * (size_t)strat_lds_layout(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf).total);
 }
 
 int jp_for(int J1, int J2)
@@ -124,6 +136,22 @@ __device__ void build_h(float* Hs, const float* Cs, const float* Gs, int I3, int
         if (x < J1 && y < J2)
             for (int c = 0; c < J3; ++c) h = fmaf(Gs[(x * J2 + y) * J3 + c], Cs[k * J3 + c], h);
         Hs[idx] = h;
+    }
+}
+
+// BF16 copies of H_k as the B operands of the matrix-core products
+// W1 = B_tile H_k^T and W2 = A_tile H_k: for platform k, Hb[(2k)(MP)(32)]
+// holds H_k[c][y] at (c, y) and Hb[(2k+1)(MP)(32)] holds H_k[x][c] at
+// (c, x), zero outside JP x JP.  Row c is read as 8 values per lane.
+template <int JP>
+__device__ void build_hb(__bf16* Hb, const float* Hs, int I3, int tid, int nthr)
+{
+    constexpr int MP = mfma_dim(JP);
+    for (int idx = tid; idx < I3 * 2 * MP * kKB; idx += nthr) {
+        const int y = idx % kKB, c = (idx / kKB) % MP, kw = idx / (kKB * MP), k = kw >> 1;
+        float h = 0.f;
+        if (c < JP && y < JP) h = (kw & 1) ? Hs[k * JP * JP + y * JP + c] : Hs[k * JP * JP + c * JP + y];
+        Hb[idx] = (__bf16)h;
     }
 }
 
@@ -289,6 +317,56 @@ template <> struct SAcc<32> {
     }
 };
 
+// BF16 matrix-core accumulator of S (v_mfma_f32_16x16x32_bf16): the
+// operands are staged column-major, element (t, c) at c*kTB + t, and lane l
+// supplies rows/columns l%16 with nonzeros 8(l/16) .. 8(l/16)+7 of a 32-wide
+// K step.  MP = 32: wavefront w < 4 owns output block (w/2, w%2) and both K
+// steps; MP = 16: wavefronts 0 and 1 own K step 0 and 1 of the one block.
+template <int MP> struct SAccB {
+    floatx4 v;
+    __device__ void zero() { v = floatx4{0.f, 0.f, 0.f, 0.f}; }
+    __device__ void accumulate(const __bf16* A16, const __bf16* E16, int n, int w, int lane)
+    {
+        const int g = lane >> 4, m = lane & 15;
+        const int mb = MP == 32 ? (w >> 1) : 0, nb = MP == 32 ? (w & 1) : 0;
+        const int ks0 = MP == 32 ? 0 : w, ks1 = MP == 32 ? 2 : (w < 2 ? w + 1 : w);
+        for (int ks = ks0; ks < ks1; ++ks) {
+            if (kKB * ks >= n) break;
+            const bf16x8 x = *reinterpret_cast<const bf16x8*>(A16 + (mb * 16 + m) * kTB + kKB * ks + 8 * g);
+            const bf16x8 y = *reinterpret_cast<const bf16x8*>(E16 + (nb * 16 + m) * kTB + kKB * ks + 8 * g);
+            v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, v, 0, 0, 0);
+        }
+    }
+    // output element (row mb*16 + 4*(l/16) + r, column nb*16 + l%16) in register r
+    __device__ void flush(float* Sk, int J1, int J2, int w, int lane)
+    {
+        const int mb = MP == 32 ? (w >> 1) : 0, nb = MP == 32 ? (w & 1) : 0;
+        const int col = nb * 16 + (lane & 15), rb = mb * 16 + (lane >> 4) * 4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = rb + r;
+            if (row < J1 && col < J2) Sk[row * J2 + col] += v[r];
+        }
+    }
+};
+
+// Eight consecutive columns [c0, c0+8) of an LDS row (stride RS, a multiple
+// of 4) as BF16; columns at or beyond RS read as zero.
+template <int RS>
+__device__ inline bf16x8 row8_bf16(const float* row, int c0, bool act)
+{
+    floatx4 lo = floatx4{0.f, 0.f, 0.f, 0.f}, hi = lo;
+    if (act && c0 < RS) lo = *reinterpret_cast<const floatx4*>(row + c0);
+    if (act && c0 + 4 < RS) hi = *reinterpret_cast<const floatx4*>(row + c0 + 4);
+    bf16x8 r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        r[i] = (__bf16)lo[i];
+        r[4 + i] = (__bf16)hi[i];
+    }
+    return r;
+}
+
 // Contiguous rows [row0, row0+nrows) of a position-ordered factor into LDS
 // rows of stride RS (padding columns are left as they are: zero).
 __device__ inline void load_rows(float* dst, const float* src, int row0, int nrows, int J, int RS, int tid,
@@ -337,19 +415,19 @@ __device__ inline void load_tile_cache(const StratArgs& a, int* tco, int* tck, i
 }
 
 // n consecutive records into LDS, eight loads in flight per thread.
-__device__ inline void load_records(uint2* dst, const uint2* src, int n, int tid)
+__device__ inline void load_records(uint2* dst, const uint2* src, int n, int tid, int nthr)
 {
     constexpr int U = 8;
-    for (int b = tid; b < n; b += U * kStratThreads) {
+    for (int b = tid; b < n; b += U * nthr) {
         uint2 v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int i = b + u * kStratThreads;
+            const int i = b + u * nthr;
             v[u] = src[i < n ? i : n - 1];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int i = b + u * kStratThreads;
+            const int i = b + u * nthr;
             if (i < n) dst[i] = v[u];
         }
     }
@@ -371,6 +449,17 @@ constexpr int kDppRowBcast15 = 0x142;  // lane 15 of each row to the next row
 constexpr int kDppRowBcast31 = 0x143;  // lane 31 to rows 2 and 3
 constexpr int kDppWaveShr1 = 0x138;    // lane l reads lane l-1
 constexpr int kDppWaveShl1 = 0x130;    // lane l reads lane l+1
+constexpr int kDppRowRor = 0x120;      // + n: lane l of a row reads lane (l+n) mod 16 of the row
+
+// Sum over the 16 lanes of each row, returned in every lane of the row.
+__device__ inline float row_sum16(float v)
+{
+    v += dpp_move<kDppRowRor + 8, 0xf>(v);
+    v += dpp_move<kDppRowRor + 4, 0xf>(v);
+    v += dpp_move<kDppRowRor + 2, 0xf>(v);
+    v += dpp_move<kDppRowRor + 1, 0xf>(v);
+    return v;
+}
 
 // Inclusive segmented scan over the lanes of a wavefront: lane l returns the
 // sum of v over lanes head..l (head <= l), added in a fixed tree order:
@@ -406,14 +495,20 @@ struct TileLds {
     float *Ab, *Bb;
     const float *rA, *rB, *Hs;
     float *sA, *sB, *As, *Es, *xtp;
+    // BF16 path: H_k and H_k^T as matrix-core B operands, raw w1 (tile order)
+    // and w2 (slot order) columns, x~ per nonzero, e in slot order, staged
+    // BF16 operands of the S product
+    const __bf16* Hb;
+    float *sW1, *sW2, *xts, *eS;
+    __bf16 *A16, *E16;
     int* slotJ;
-    float* Skw;   // [kWaves][I3*J1*J2]
+    float* Skw;   // [kMfmaWaves][I3*J1*J2]
     int* Mk;
     int *tco, *tck;
     uint2* rec;   // [rec_cap] staged records
 };
 
-// The tiles of block (p, q), run by the whole workgroup (kStratThreads
+// The tiles of block (p, q), run by the whole workgroup (strat_threads(JP)
 // threads).  L.Ab/L.Bb hold the block's rows; L.Skw receives each
 // wavefront's per-platform sums, L.Mk the block's counts.
 template <int JP>
@@ -421,8 +516,9 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
 {
     constexpr int RS = row_stride(JP);
     constexpr int MP = mfma_dim(JP);
-    constexpr int QN = (JP + kWaves - 1) / kWaves;  // owned factor columns per wavefront
-    constexpr int QM = MP / kWaves;                  // owned operand columns per wavefront
+    constexpr int NW = strat_waves(JP), NT = 64 * NW;
+    constexpr int QN = (JP + NW - 1) / NW;  // owned factor columns per wavefront
+    constexpr int QM = (MP + NW - 1) / NW;  // owned operand columns per wavefront
     const int lane = tid & 63, w = tid >> 6;
     const int J1 = a.J1, J2 = a.J2, J12 = J1 * J2;
     const uint32_t mask_i = (1u << a.bits_i) - 1u, mask_j = (1u << a.bits_j) - 1u;
@@ -433,7 +529,8 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
 
     SAcc<MP> acc;
     acc.zero();
-    float* Skmine = L.Skw + w * a.I3 * J12;
+    const bool mfw = w < kMfmaWaves;  // this wavefront accumulates S
+    float* Skmine = L.Skw + (mfw ? w : 0) * a.I3 * J12;
     int curk = -1;
     // for small cores the owned rows and columns of H_k stay in registers
     // while consecutive tiles share the platform k
@@ -444,12 +541,12 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         // a chunk: up to kTileCache tiles whose records fit in rec_cap,
         // metadata and records brought into LDS with many loads in flight
         const int base = tl;
-        load_tile_cache(a, L.tco, L.tck, base, t1, tid, kStratThreads);
+        load_tile_cache(a, L.tco, L.tck, base, t1, tid, NT);
         __syncthreads();
         const int ntc = (t1 - base) < kTileCache ? (t1 - base) : kTileCache;
         const int cend = __syncthreads_count(tid < ntc && L.tco[tid + 1] - L.tco[0] <= a.rec_cap);
         const int z0 = L.tco[0], nrec = L.tco[cend] - z0;
-        load_records(L.rec, a.nz + z0, nrec, tid);
+        load_records(L.rec, a.nz + z0, nrec, tid, NT);
         __syncthreads();
         for (int u = 0; u < cend; ++u, ++tl) {
         const int off = L.tco[u];
@@ -457,14 +554,14 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         const int k = L.tck[u];
         const uint2 wv = lane < n ? L.rec[off - z0 + lane] : make_uint2(0u, 0u);
         if (k != curk) {
-            if (curk >= 0) acc.flush(Skmine + curk * J12, J1, J2, lane);
+            if (curk >= 0 && mfw) acc.flush(Skmine + curk * J12, J1, J2, lane);
             acc.zero();
             curk = k;
             if constexpr (kHreg) {
                 const float* Hk = L.Hs + k * JP * JP;
 #pragma unroll
                 for (int qq = 0; qq < QN; ++qq) {
-                    const int c = w + kWaves * qq < JP ? w + kWaves * qq : 0;
+                    const int c = w + NW * qq < JP ? w + NW * qq : 0;
 #pragma unroll
                     for (int y = 0; y < JP; ++y) {
                         hr[qq][y] = Hk[c * JP + y];
@@ -492,7 +589,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         float xw = 0.f;
 #pragma unroll
         for (int qq = 0; qq < QN; ++qq) {
-            const int c = w + kWaves * qq;
+            const int c = w + NW * qq;
             float t1v = 0.f, t2v = 0.f, ac = 0.f;
             if (c < JP) {
                 if constexpr (kHreg) {
@@ -520,11 +617,11 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         // 2. residual; stage row terms and matrix-core operands
         float xt = L.xtp[lane];
 #pragma unroll
-        for (int ww = 1; ww < kWaves; ++ww) xt += L.xtp[ww * 64 + lane];
+        for (int ww = 1; ww < NW; ++ww) xt += L.xtp[ww * 64 + lane];
         const float e = act ? x - xt : 0.f;
 #pragma unroll
         for (int qq = 0; qq < QN; ++qq) {
-            const int c = w + kWaves * qq;
+            const int c = w + NW * qq;
             if (c < JP) {
                 L.sA[c * kTS + lane] = e * w1q[qq];
                 if (act) L.sB[c * kTS + jrank] = e * w2q[qq];
@@ -532,7 +629,8 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         }
 #pragma unroll
         for (int qm = 0; qm < QM; ++qm) {
-            const int c = w + kWaves * qm;
+            const int c = w + NW * qm;
+            if (c >= MP) continue;
             float av_c = 0.f, eb_c = 0.f;
             if (c < JP && act) {
                 av_c = qm < QN ? aq[qm < QN ? qm : 0] : L.Ab[il * RS + c];
@@ -545,7 +643,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         __syncthreads();
 
         // 3. matrix-core sums; fixed-order run sums; owned columns of the rows
-        acc.accumulate(L.As, L.Es, n, w, lane);
+        if (mfw) acc.accumulate(L.As, L.Es, n, w, lane);
         {
             const int il_up = dpp_move_i<kDppWaveShr1>(il), il_dn = dpp_move_i<kDppWaveShl1>(il);
             const bool ifirst = act && (lane == 0 || il_up != il);
@@ -554,7 +652,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
             const float cr = act ? (float)(lane - head + 1) * L.rA[il] : 0.f;
 #pragma unroll
             for (int qq = 0; qq < QN; ++qq) {
-                const int c = w + kWaves * qq;
+                const int c = w + NW * qq;
                 if (c < JP) {
                     const float v = seg_scan(L.sA[c * kTS + lane], lane, head);
                     if (ilast) L.Ab[il * RS + c] = fmaf(a.lr, v - cr * aq[qq], aq[qq]);
@@ -570,7 +668,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
             const float cr = lane < n ? (float)(lane - head + 1) * L.rB[sj] : 0.f;
 #pragma unroll
             for (int qq = 0; qq < QN; ++qq) {
-                const int c = w + kWaves * qq;
+                const int c = w + NW * qq;
                 if (c < JP) {
                     const float v = seg_scan(L.sB[c * kTS + lane], lane, head);
                     if (jlast) {
@@ -584,17 +682,198 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         __syncthreads();
         }
     }
-    acc.flush(Skmine + curk * J12, J1, J2, lane);
+    if (mfw) acc.flush(Skmine + curk * J12, J1, J2, lane);
+    __syncthreads();
+}
+
+// The tiles of block (p, q) with BF16 matrix-core contractions (FP32
+// accumulation; factor rows, residuals and updates stay FP32).  Per tile:
+//   1. wavefront w < 4 takes nonzeros 16w..16w+15 as the rows of
+//      W1 = B_tile H_k^T and W2 = A_tile H_k (BF16 operands, one K step of
+//      32); it writes W1 in tile order and W2 in the tile's gene-sorted slot
+//      order, and x~ = a . w1 for its nonzeros (FP32 row sums);
+//   2. lane t of every wavefront forms e = x - x~, keeps its owned columns
+//      of a_i from before the tile and stages the BF16 operands a_i and
+//      e b_j of the S product;
+//   3. S on the matrix cores; the patient and gene runs are summed with the
+//      same segmented scans as the FP32 path, on e*w1 and e*w2;
+// with a barrier after each of the three steps.
+template <int JP>
+__device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& L, int tid)
+{
+    constexpr int RS = row_stride(JP);
+    constexpr int MP = mfma_dim(JP);
+    constexpr int NB = MP / 16;
+    constexpr int NW = strat_waves(JP), NT = 64 * NW;
+    constexpr int QN = (JP + NW - 1) / NW;
+    constexpr int QM = (MP + NW - 1) / NW;
+    const int lane = tid & 63, w = tid >> 6, g = lane >> 4, m = lane & 15;
+    const int J1 = a.J1, J2 = a.J2, J12 = J1 * J2;
+    const uint32_t mask_i = (1u << a.bits_i) - 1u, mask_j = (1u << a.bits_j) - 1u;
+    const int sh_j = a.bits_i, sh_r = a.bits_i + a.bits_j;
+    const int blk = p * a.P + q;
+    const int t0 = a.blk_tile[blk], t1 = a.blk_tile[blk + 1];
+    if (t0 >= t1) return;
+
+    SAccB<MP> acc;
+    acc.zero();
+    const bool mfw = w < kMfmaWaves;
+    const bool pw = w < 4;  // this wavefront forms W1 and W2 for 16 nonzeros
+    float* Skmine = L.Skw + (mfw ? w : 0) * a.I3 * J12;
+    int curk = -1;
+    bf16x8 hb1[NB], hb2[NB];
+    int tl = t0;
+    while (tl < t1) {
+        const int base = tl;
+        load_tile_cache(a, L.tco, L.tck, base, t1, tid, NT);
+        __syncthreads();
+        const int ntc = (t1 - base) < kTileCache ? (t1 - base) : kTileCache;
+        const int cend = __syncthreads_count(tid < ntc && L.tco[tid + 1] - L.tco[0] <= a.rec_cap);
+        const int z0 = L.tco[0], nrec = L.tco[cend] - z0;
+        load_records(L.rec, a.nz + z0, nrec, tid, NT);
+        __syncthreads();
+        for (int u = 0; u < cend; ++u, ++tl) {
+        const int off = L.tco[u];
+        const int n = L.tco[u + 1] - off;
+        const int k = L.tck[u];
+        const uint2* rec = L.rec + (off - z0);
+        if (k != curk) {
+            if (curk >= 0 && mfw) acc.flush(Skmine + curk * J12, J1, J2, w, lane);
+            acc.zero();
+            curk = k;
+            if (pw) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    hb1[nb] = *reinterpret_cast<const bf16x8*>(L.Hb + ((2 * k) * MP + nb * 16 + m) * kKB + 8 * g);
+                    hb2[nb] = *reinterpret_cast<const bf16x8*>(L.Hb + ((2 * k + 1) * MP + nb * 16 + m) * kKB + 8 * g);
+                }
+            }
+        }
+
+        // 1. W1, W2 and x~ for nonzeros 16w .. 16w+15
+        if (pw) {
+            const int to = 16 * w + m;
+            const bool ao = to < n;
+            const uint32_t wo = ao ? rec[to].x : 0u;
+            const bf16x8 opb = row8_bf16<RS>(L.Bb + ((wo >> sh_j) & mask_j) * RS, 8 * g, ao);
+            const bf16x8 opa = row8_bf16<RS>(L.Ab + (wo & mask_i) * RS, 8 * g, ao);
+            int ilr[4], jrr[4];
+            bool actr[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int tr = 16 * w + 4 * g + r;
+                actr[r] = tr < n;
+                const uint32_t wr = actr[r] ? rec[tr].x : 0u;
+                ilr[r] = (int)(wr & mask_i);
+                jrr[r] = (int)(wr >> sh_r);
+            }
+            float xp[4] = {0.f, 0.f, 0.f, 0.f};
+            const floatx4 zero4 = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const floatx4 o1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opb, hb1[nb], zero4, 0, 0, 0);
+                const floatx4 o2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opa, hb2[nb], zero4, 0, 0, 0);
+                const int c = nb * 16 + m;
+                *reinterpret_cast<floatx4*>(L.sW1 + c * kTW + 16 * w + 4 * g) = o1;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (actr[r]) L.sW2[c * kTW + jrr[r]] = o2[r];
+                    if (c < JP) xp[r] = fmaf(L.Ab[ilr[r] * RS + c], o1[r], xp[r]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xp[r] = row_sum16(xp[r]);
+            if (m < 4) {
+                const float v = m == 0 ? xp[0] : (m == 1 ? xp[1] : (m == 2 ? xp[2] : xp[3]));
+                L.xts[16 * w + 4 * g + m] = v;
+            }
+        }
+        __syncthreads();
+
+        // 2. residual; owned columns of a_i before the tile; BF16 S operands
+        const bool act = lane < n;
+        const uint2 wv = act ? rec[lane] : make_uint2(0u, 0u);
+        const uint32_t wd = wv.x;
+        const int il = act ? (int)(wd & mask_i) : -1;
+        const int jl = act ? (int)((wd >> sh_j) & mask_j) : 0;
+        const int jrank = (int)(wd >> sh_r);
+        const float e = act ? __uint_as_float(wv.y) - L.xts[lane] : 0.f;
+        if (w == 0 && act) {
+            L.eS[jrank] = e;
+            L.slotJ[jrank] = jl;
+        }
+        float aq[QN];
+#pragma unroll
+        for (int qq = 0; qq < QN; ++qq) {
+            const int c = w + NW * qq;
+            aq[qq] = (c < JP && act) ? L.Ab[il * RS + c] : 0.f;
+        }
+#pragma unroll
+        for (int qm = 0; qm < QM; ++qm) {
+            const int c = w + NW * qm;
+            if (c >= MP) continue;
+            float av_c = 0.f, eb_c = 0.f;
+            if (c < JP && act) {
+                av_c = L.Ab[il * RS + c];
+                eb_c = e * L.Bb[jl * RS + c];
+            }
+            L.A16[c * kTB + lane] = (__bf16)av_c;
+            L.E16[c * kTB + lane] = (__bf16)eb_c;
+        }
+        __syncthreads();
+
+        // 3. S on the matrix cores; fixed-order run sums; owned row columns
+        if (mfw) acc.accumulate(L.A16, L.E16, n, w, lane);
+        {
+            const int il_up = dpp_move_i<kDppWaveShr1>(il), il_dn = dpp_move_i<kDppWaveShl1>(il);
+            const bool ifirst = act && (lane == 0 || il_up != il);
+            const bool ilast = act && (lane == 63 || il_dn != il);
+            const int head = run_head(__ballot(ifirst), lane);
+            const float cr = act ? (float)(lane - head + 1) * L.rA[il] : 0.f;
+#pragma unroll
+            for (int qq = 0; qq < QN; ++qq) {
+                const int c = w + NW * qq;
+                if (c < JP) {
+                    const float v = seg_scan(e * L.sW1[c * kTW + lane], lane, head);
+                    if (ilast) L.Ab[il * RS + c] = fmaf(a.lr, v - cr * aq[qq], aq[qq]);
+                }
+            }
+        }
+        {
+            const int sj = act ? L.slotJ[lane] : -1;
+            const float es = act ? L.eS[lane] : 0.f;
+            const int sj_up = dpp_move_i<kDppWaveShr1>(sj), sj_dn = dpp_move_i<kDppWaveShl1>(sj);
+            const bool jfirst = act && (lane == 0 || sj_up != sj);
+            const bool jlast = act && (lane == 63 || sj_dn != sj);
+            const int head = run_head(__ballot(jfirst), lane);
+            const float cr = act ? (float)(lane - head + 1) * L.rB[sj] : 0.f;
+#pragma unroll
+            for (int qq = 0; qq < QN; ++qq) {
+                const int c = w + NW * qq;
+                if (c < JP) {
+                    const float v = seg_scan(es * L.sW2[c * kTW + lane], lane, head);
+                    if (jlast) {
+                        const float bp = L.Bb[sj * RS + c];
+                        L.Bb[sj * RS + c] = fmaf(a.lr, v - cr * bp, bp);
+                    }
+                }
+            }
+        }
+        if (tid == 0) L.Mk[k] += n;
+        __syncthreads();
+        }
+    }
+    if (mfw) acc.flush(Skmine + curk * J12, J1, J2, w, lane);
     __syncthreads();
 }
 
 // The block's S = sum over wavefronts (ascending) of their partial sums.
-__device__ inline void combine_waves(float* Sk, const float* Skw, int ni, int tid)
+__device__ inline void combine_waves(float* Sk, const float* Skw, int ni, int tid, int nthr)
 {
-    for (int idx = tid; idx < ni; idx += kStratThreads) {
+    for (int idx = tid; idx < ni; idx += nthr) {
         float s = Skw[idx];
 #pragma unroll
-        for (int ww = 1; ww < kWaves; ++ww) s += Skw[ww * ni + idx];
+        for (int ww = 1; ww < kMfmaWaves; ++ww) s += Skw[ww * ni + idx];
         Sk[idx] = s;
     }
 }
@@ -638,6 +917,16 @@ __device__ bool grid_sync(GridBar* bar, unsigned nblocks, unsigned& nbar, int* f
     return *flag != 0;
 }
 
+// Workgroups are dispatched to the XCDs round-robin (workgroup q runs on XCD
+// q mod 8).  xcd_slot numbers the workgroups XCD by XCD: a bijection of
+// [0, n) that gives the workgroups of one XCD consecutive slots.
+constexpr int kXcds = 8;
+__device__ inline int xcd_slot(int q, int n)
+{
+    const int x = q % kXcds, per = n / kXcds, extra = n % kXcds;
+    return x * per + (x < extra ? x : extra) + q / kXcds;
+}
+
 template <int JP>
 __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
 {
@@ -652,6 +941,13 @@ __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
     L.As = lds + S.as;
     L.Es = lds + S.es;
     L.xtp = lds + S.xtp;
+    L.Hb = reinterpret_cast<const __bf16*>(lds + S.hb);
+    L.sW1 = lds + S.sw1;
+    L.sW2 = lds + S.sw2;
+    L.xts = lds + S.xts;
+    L.eS = lds + S.esl;
+    L.A16 = reinterpret_cast<__bf16*>(lds + S.a16);
+    L.E16 = reinterpret_cast<__bf16*>(lds + S.e16);
     L.slotJ = reinterpret_cast<int*>(lds + S.slotj);
     L.Skw = lds + S.skw;
     L.Mk = reinterpret_cast<int*>(lds + S.mk);
@@ -664,17 +960,17 @@ __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
 // ---------------------------------------------------------------------------
 // Persistent driver: every stratum of one epoch in one launch.
 // ---------------------------------------------------------------------------
-template <int JP>
-__global__ __launch_bounds__(kStratThreads) void strata_persistent(StratArgs a)
+template <int JP, bool BF>
+__global__ __launch_bounds__(strat_threads(JP)) void strata_persistent(StratArgs a)
 {
     constexpr int RS = row_stride(JP);
-    constexpr int NT = kStratThreads;
+    constexpr int NT = strat_threads(JP);
     extern __shared__ float lds[];
     const int tid = threadIdx.x;
     const int q = blockIdx.x;
     const int P = a.P, I3 = a.I3, J1 = a.J1, J2 = a.J2, J3 = a.J3, J12 = J1 * J2;
     const int ni = I3 * J12;
-    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3, a.rec_cap);
+    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3, a.rec_cap, BF ? 1 : 0);
     const TileLds L = tile_lds<JP>(lds, S);
     float* Cs = lds + S.c;
     float* Gs = lds + S.g;
@@ -695,8 +991,11 @@ __global__ __launch_bounds__(kStratThreads) void strata_persistent(StratArgs a)
     unsigned nbar = 0;  // grid barriers passed so far (thread 0)
     __syncthreads();
 
-    // this workgroup's share of the stratum reduction
-    const int i0 = (int)(((long long)ni * q) / P), i1 = (int)(((long long)ni * (q + 1)) / P);
+    // this workgroup's share of the stratum reduction: consecutive shares go
+    // to workgroups on the same XCD, so each XCD's L2 fetches its own
+    // contiguous slice of the per-block sums
+    const int r = xcd_slot(q, P);
+    const int i0 = (int)(((long long)ni * r) / P), i1 = (int)(((long long)ni * (r + 1)) / P);
 
     for (int si = 0; si < P; ++si) {
         const int s = a.order[si];
@@ -705,11 +1004,17 @@ __global__ __launch_bounds__(kStratThreads) void strata_persistent(StratArgs a)
         load_rows(L.Ab, a.Ap, s1, r1, J1, RS, tid, NT);
         for (int l = tid; l < r1; l += NT) lds[S.ra + l] = a.reg1[s1 + l];
         build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
-        for (int idx = tid; idx < kWaves * ni; idx += NT) L.Skw[idx] = 0.f;
+        for (int idx = tid; idx < kMfmaWaves * ni; idx += NT) L.Skw[idx] = 0.f;
         for (int k = tid; k < I3; k += NT) L.Mk[k] = 0;
         __syncthreads();
-        block_tiles<JP>(a, p, q, L, tid);
-        combine_waves(Sk, L.Skw, ni, tid);
+        if constexpr (BF) {
+            build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Hs, I3, tid, NT);
+            __syncthreads();
+            block_tiles_bf<JP>(a, p, q, L, tid);
+        } else {
+            block_tiles<JP>(a, p, q, L, tid);
+        }
+        combine_waves(Sk, L.Skw, ni, tid, NT);
         store_rows(a.Ap, L.Ab, s1, r1, J1, RS, tid, NT);
         __syncthreads();
         float* Sp = a.Spart + (size_t)p * ni;
@@ -740,17 +1045,17 @@ __global__ __launch_bounds__(kStratThreads) void strata_persistent(StratArgs a)
 // ---------------------------------------------------------------------------
 // Multi-launch driver: one block step per stratum, then one core step.
 // ---------------------------------------------------------------------------
-template <int JP>
-__global__ __launch_bounds__(kStratThreads) void block_step(StratArgs a)
+template <int JP, bool BF>
+__global__ __launch_bounds__(strat_threads(JP)) void block_step(StratArgs a)
 {
     constexpr int RS = row_stride(JP);
-    constexpr int NT = kStratThreads;
+    constexpr int NT = strat_threads(JP);
     extern __shared__ float lds[];
     const int tid = threadIdx.x;
     const int p = blockIdx.x, P = a.P;
     const int q = (p + a.s) % P;
     const int I3 = a.I3, J1 = a.J1, J2 = a.J2, J3 = a.J3, J12 = J1 * J2, ni = I3 * J12;
-    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3, a.rec_cap);
+    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3, a.rec_cap, BF ? 1 : 0);
     const TileLds L = tile_lds<JP>(lds, S);
     float* Cs = lds + S.c;
     float* Gs = lds + S.g;
@@ -766,13 +1071,19 @@ __global__ __launch_bounds__(kStratThreads) void block_step(StratArgs a)
     for (int l = tid; l < r2; l += NT) lds[S.rb + l] = a.reg2[s2 + l];
     for (int idx = tid; idx < I3 * J3; idx += NT) Cs[idx] = a.C[idx];
     for (int idx = tid; idx < J12 * J3; idx += NT) Gs[idx] = a.G[idx];
-    for (int idx = tid; idx < kWaves * ni; idx += NT) L.Skw[idx] = 0.f;
+    for (int idx = tid; idx < kMfmaWaves * ni; idx += NT) L.Skw[idx] = 0.f;
     for (int k = tid; k < I3; k += NT) L.Mk[k] = 0;
     __syncthreads();
     build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
     __syncthreads();
-    block_tiles<JP>(a, p, q, L, tid);
-    combine_waves(Sk, L.Skw, ni, tid);
+    if constexpr (BF) {
+        build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Hs, I3, tid, NT);
+        __syncthreads();
+        block_tiles_bf<JP>(a, p, q, L, tid);
+    } else {
+        block_tiles<JP>(a, p, q, L, tid);
+    }
+    combine_waves(Sk, L.Skw, ni, tid, NT);
     store_rows(a.Ap, L.Ab, s1, r1, J1, RS, tid, NT);
     store_rows(a.Bp, L.Bb, s2, r2, J2, RS, tid, NT);
     __syncthreads();
@@ -1071,32 +1382,32 @@ __global__ __launch_bounds__(256) void permute_rows(const float* src, float* dst
     default: return hipErrorInvalidValue;     \
     }
 
-template <int JP>
+template <int JP, bool BF>
 static hipError_t launch_persistent_t(const StratArgs& a, size_t lds, hipStream_t st)
 {
     StratArgs copy = a;
     void* args[] = {&copy};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&strata_persistent<JP>), dim3(a.P),
-                                      dim3(kStratThreads), args, (unsigned)lds, st);
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&strata_persistent<JP, BF>), dim3(a.P),
+                                      dim3(strat_threads(JP)), args, (unsigned)lds, st);
 }
 
-hipError_t launch_strata_persistent(const StratArgs& a, int jp, size_t lds, hipStream_t st)
+hipError_t launch_strata_persistent(const StratArgs& a, int jp, int bf, size_t lds, hipStream_t st)
 {
-#define CALL_P(J) launch_persistent_t<J>(a, lds, st)
+#define CALL_P(J) (bf ? launch_persistent_t<J, true>(a, lds, st) : launch_persistent_t<J, false>(a, lds, st))
     SNECT_JP_SWITCH(jp, CALL_P)
 #undef CALL_P
 }
 
-template <int JP>
+template <int JP, bool BF>
 static hipError_t launch_block_t(const StratArgs& a, size_t lds, hipStream_t st)
 {
-    hipLaunchKernelGGL(block_step<JP>, dim3(a.P), dim3(kStratThreads), lds, st, a);
+    hipLaunchKernelGGL((block_step<JP, BF>), dim3(a.P), dim3(strat_threads(JP)), lds, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_block(const StratArgs& a, int jp, size_t lds, hipStream_t st)
+hipError_t launch_block(const StratArgs& a, int jp, int bf, size_t lds, hipStream_t st)
 {
-#define CALL_B(J) launch_block_t<J>(a, lds, st)
+#define CALL_B(J) (bf ? launch_block_t<J, true>(a, lds, st) : launch_block_t<J, false>(a, lds, st))
     SNECT_JP_SWITCH(jp, CALL_B)
 #undef CALL_B
 }
@@ -1156,18 +1467,23 @@ hipError_t launch_permute(const float* src, float* dst, const int32_t* perm, int
     return hipGetLastError();
 }
 
+template <int JP, bool BF>
+static hipError_t prepare_strata_t(size_t slds)
+{
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&strata_persistent<JP, BF>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&block_step<JP, BF>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds);
+    return e;
+}
+
 template <int JP>
-static hipError_t prepare_t(size_t slds, size_t llds, size_t clds)
+static hipError_t prepare_t(int bf, size_t slds, size_t llds, size_t clds)
 {
     hipError_t e = hipSuccess;
     const int limit = 65536;
-    if (slds > (size_t)limit) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&strata_persistent<JP>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&block_step<JP>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds);
-    }
+    if (slds > (size_t)limit) e = bf ? prepare_strata_t<JP, true>(slds) : prepare_strata_t<JP, false>(slds);
     if (e == hipSuccess && llds > (size_t)limit)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&loss_blocks<JP>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)llds);
@@ -1177,19 +1493,20 @@ static hipError_t prepare_t(size_t slds, size_t llds, size_t clds)
     return e;
 }
 
-hipError_t prepare_kernels(int jp, size_t slds, size_t llds, size_t clds)
+hipError_t prepare_kernels(int jp, int bf, size_t slds, size_t llds, size_t clds)
 {
-#define CALL_R(J) prepare_t<J>(slds, llds, clds)
+#define CALL_R(J) prepare_t<J>(bf, slds, llds, clds)
     SNECT_JP_SWITCH(jp, CALL_R)
 #undef CALL_R
 }
 
-template <int JP>
+template <int JP, bool BF>
 static int capacity_t(size_t lds)
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&strata_persistent<JP>),
-                                                     kStratThreads, lds) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                     reinterpret_cast<const void*>(&strata_persistent<JP, BF>),
+                                                     strat_threads(JP), lds) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
@@ -1199,9 +1516,9 @@ static int capacity_t(size_t lds)
     return per_cu * cus;
 }
 
-int persistent_capacity(int jp, size_t lds)
+int persistent_capacity(int jp, int bf, size_t lds)
 {
-#define CALL_C(J) capacity_t<J>(lds)
+#define CALL_C(J) (bf ? capacity_t<J, true>(lds) : capacity_t<J, false>(lds))
     SNECT_JP_SWITCH(jp, CALL_C)
 #undef CALL_C
 }
