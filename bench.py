@@ -42,6 +42,12 @@ def parse():
                     help="fold-in requests replayed after training (0 = no serving leg)")
     ap.add_argument("--serve-epochs", type=int, default=20,
                     help="epochs the served factors are trained for")
+    ap.add_argument("--equal-rmse-epochs", type=int, default=20,
+                    help="FP32 epochs of the core 20x20x5 run whose RMSE the BF16 run must reach "
+                         "(0 = skip the FP32 vs BF16 comparison)")
+    ap.add_argument("--bf16-oracle", action="store_true",
+                    help="also run the FP64 oracle on the core 20x20x5 problem and report the FP32 and "
+                         "BF16 factor errors at epoch 1 and at the last FP32 epoch (minutes of CPU)")
     ap.add_argument("--path", choices=["auto", "persistent", "multi"], default="auto")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -160,6 +166,8 @@ def main():
 
     if args.serve_requests > 0:
         out["serving"] = serve_leg(args, sn, synth, prob, f, dims, ranks)
+    if args.equal_rmse_epochs > 0:
+        out["fp32_vs_bf16"] = equal_rmse_leg(args, sn, synth, ctx, (i, j, k, x, eu, ev), dims)
 
     if not args.no_cpu_baseline:
         import oracle
@@ -192,6 +200,82 @@ def copy_probe(torch):
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe": {"launches": 3, "read_bytes_per_launch": 4 * n,
                                      "write_bytes_per_launch": 4 * n}}), flush=True)
+
+
+def equal_rmse_leg(args, sn, synth, ctx, data, dims):
+    """The same tensor and graph with core 20x20x5: FP32 for `equal_rmse_epochs`
+    epochs, then BF16 matrix-core contractions until the training RMSE is
+    within +0.5% of FP32's final RMSE.  Wall time counts the training calls
+    (one epoch per call, synchronised), inputs resident in HBM."""
+    import torch
+    i, j, k, x, eu, ev = data
+    ranks = (20, 20, 5)
+    sigma = synth.default_sigma(x, ranks)
+    init = synth.normal_init(synth.INIT_SEED + 2, dims, ranks, sigma)
+    nnz = int(i.shape[0])
+    runs = {}
+    factors = {}
+    target = None
+    for name, prec in (("fp32", sn.PRECISION_FP32), ("bf16", sn.PRECISION_BF16)):
+        hyper = sn.Hyper(ranks=ranks, lam=0.01, lam_g=0.1, lr=1e-3, core_lr_scale=1.0, P=args.strata,
+                         T=args.tile, precision=prec, seed=synth.PLAN_SEED + 2)
+        prob = sn.Problem(ctx, dims, i, j, k, x, eu, ev, None, hyper)
+        f = [torch.tensor(a.astype(np.float32), device="cuda:0").contiguous() for a in init]
+        max_ep = args.equal_rmse_epochs if target is None else 2 * args.equal_rmse_epochs
+        wall, rmses, reached = 0.0, [], None
+        snaps = {}
+        for ep in range(max_ep):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, rmse = prob.train(*f, epochs=1, start_epoch=ep)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            rmses.append(float(rmse[0]))
+            if ep == 0 or ep == args.equal_rmse_epochs - 1:
+                snaps[ep + 1] = [t.double().cpu().numpy() for t in f]
+            if target is not None and reached is None and rmses[-1] <= target:
+                reached = (ep + 1, wall)
+            if reached is not None and ep + 1 >= args.equal_rmse_epochs:
+                break
+        prob.close()
+        runs[name] = {"epochs": len(rmses), "wall_s": wall, "rmse_first": rmses[0], "rmse_last": rmses[-1],
+                      "updates_per_s": nnz * len(rmses) / wall}
+        factors[name] = snaps
+        if target is None:
+            target = rmses[-1] * 1.005
+            runs[name]["target_rmse"] = target
+        else:
+            runs[name]["epochs_to_target"] = reached[0] if reached else None
+            runs[name]["wall_s_to_target"] = reached[1] if reached else None
+    out = {"workload": "pancan-shaped tensor, core 20x20x5, P=%d, T=%d" % (args.strata, args.tile),
+           "target": "RMSE <= 1.005 x FP32 RMSE after %d epochs" % args.equal_rmse_epochs, **runs}
+    if runs["bf16"].get("wall_s_to_target"):
+        out["speedup_at_equal_rmse"] = runs["fp32"]["wall_s"] / runs["bf16"]["wall_s_to_target"]
+    if args.bf16_oracle:
+        out["vs_oracle"] = bf16_oracle_errors(args, synth, data, dims, ranks, init, factors)
+    log(f"fp32 vs bf16: {json.dumps(out)}", args.quiet)
+    return out
+
+
+def bf16_oracle_errors(args, synth, data, dims, ranks, init, factors):
+    """Relative Frobenius error of A, B, C, G against the FP64 oracle."""
+    import oracle
+    i, j, k, x, eu, ev = data
+    prob_o = oracle.Problem(dims, ranks, i, j, k, x.astype(np.float64), eu, ev, None, lam=0.01, lam_g=0.1,
+                            lr=1e-3, core_lr_scale=1.0, P=args.strata, T=args.tile, seed=synth.PLAN_SEED + 2)
+    res = {}
+    cur = [np.asarray(a, np.float64) for a in init]
+    done = 0
+    for ep in sorted(factors["fp32"]):
+        A, B, C, G, loss, rmse = oracle.run(prob_o, *cur, ep - done, start_epoch=done)
+        cur, done = [A, B, C, G], ep
+        res[f"epoch_{ep}"] = {"oracle_rmse": float(rmse[-1])}
+        for name in ("fp32", "bf16"):
+            if ep in factors[name]:
+                res[f"epoch_{ep}"][name] = {
+                    n: float(np.linalg.norm(g - o) / np.linalg.norm(o))
+                    for n, g, o in zip("ABCG", factors[name][ep], cur)}
+    return res
 
 
 def serve_leg(args, sn, synth, prob, f, dims, ranks):

@@ -193,18 +193,60 @@ int snect_last_timing(const snect_problem *prob, double *ms5);
 #define SNECT_PATH_PERSISTENT 1 /* one cooperative launch per epoch           */
 #define SNECT_PATH_MULTI 2      /* one launch per stratum + a core-step launch */
 
-/* Execution choices; they never change results (both paths are
- * bit-identical).  per_launch_timing records a pair of HIP events around
+/* Execution choices; they never change results: every sum of the stratum
+ * kernels is taken in an order fixed by the problem alone, so both drivers,
+ * both wavefront counts and every record-chunk size give bit-identical
+ * factors and losses.  per_launch_timing records a pair of HIP events around
  * every stratum-kernel launch (no extra host synchronisation); path selects
- * the stratum driver.  SNECT_PATH_PERSISTENT fails with E_UNSUPPORTED at
- * snect_train if the P workgroups cannot all be resident.  Errors: E_ARG,
- * E_HIP. */
+ * the stratum driver; waves and rec_cap shape the stratum workgroups.
+ * SNECT_PATH_PERSISTENT fails with E_UNSUPPORTED at snect_train if the P
+ * workgroups cannot all be resident.  Errors: E_ARG, E_HIP. */
 typedef struct {
     int32_t per_launch_timing;
     int32_t path;
+    int32_t waves;   /* wavefronts per stratum workgroup: 0 (default, 8), 4 or 8 */
+    int32_t rec_cap; /* nonzero records staged in LDS per chunk: 0 (the largest
+                        that fits) or a power of two from 64 up to that */
 } snect_exec;
 
 int snect_set_exec(snect_problem *prob, const snect_exec *exec);
+
+/* Batched sweep: trains n independent problems of one context together,
+ * each epoch's strata of all of them in ONE cooperative launch (problem i
+ * takes P_i workgroups and synchronises on its own grid barrier).  Each
+ * problem follows
+ * exactly the schedule snect_train would run for it, so its factors and
+ * losses are bit-identical to snect_train's (Algorithm 1 per problem, as
+ * read in snect_train).  fs[i] are problem i's factors (device, caller
+ * owned); loss and rmse (host, may be NULL) receive n * epochs values,
+ * problem-major.  The problems must share a precision; every problem runs
+ * the code of its own core size in workgroups of eight wavefronts with the
+ * record chunk snect_sweep_autotune chose (default: the largest that fits).  Errors: E_ARG, E_UNSUPPORTED (sum of P_i above the
+ * co-resident workgroups), E_OOM, E_HIP, E_DIVERGED (the message names the problem;
+ * that problem's factors are rolled back to the start of the failing
+ * epoch, the others end after it; later loss entries are undefined). */
+int snect_sweep_train(snect_ctx *ctx, int32_t n, snect_problem *const *probs, snect_factors *fs,
+                      int32_t start_epoch, int32_t epochs, double *loss, double *rmse);
+
+/* Execution autotuner.  Times `trials` epochs (the best one counts) of
+ * every execution choice -- both stratum drivers (the persistent one where
+ * its workgroups can be resident), 8 or 4 wavefronts, record chunks from
+ * the largest that fits down to 256 in powers of two -- on scratch copies
+ * of the factors f (device; f itself is not changed), keeps the fastest on
+ * the problem (as snect_set_exec would) and reports it in *best (may be
+ * NULL) with its epoch time in ms (*best_ms, may be NULL).  Results never
+ * depend on the choice.  Allocates device scratch for the copies.
+ * Errors: E_ARG, E_OOM, E_HIP, E_DIVERGED (f diverges in one epoch). */
+int snect_autotune(snect_problem *prob, const snect_factors *f, int32_t trials, snect_exec *best,
+                   double *best_ms);
+
+/* Autotuner of a batched sweep: times `trials` sweep epochs on scratch
+ * copies of fs for every problem's record chunk scaled by 1, 1/2 and 1/4
+ * (not below 256) and keeps the fastest for later snect_sweep_train calls
+ * on these problems; *best_ms (may be NULL) receives its epoch time.
+ * Errors: those of snect_sweep_train, E_OOM. */
+int snect_sweep_autotune(snect_ctx *ctx, int32_t n, snect_problem *const *probs, const snect_factors *fs,
+                         int32_t trials, double *best_ms);
 
 /* The stratum driver the next snect_train call will use (SNECT_PATH_*). */
 int snect_exec_path(const snect_problem *prob);

@@ -36,7 +36,8 @@ EXPORTS = (
     "snect_problem_destroy", "snect_problem_info", "snect_train", "snect_evaluate",
     "snect_decompose", "snect_plan_export", "snect_last_timing", "snect_set_exec",
     "snect_exec_path", "snect_orthonormalize", "snect_server_create", "snect_server_destroy",
-    "snect_server_submit", "snect_server_poll", "snect_server_replay",
+    "snect_server_submit", "snect_server_poll", "snect_server_replay", "snect_sweep_train",
+    "snect_autotune", "snect_sweep_autotune",
 )
 PATH_AUTO, PATH_PERSISTENT, PATH_MULTI = 0, 1, 2
 
@@ -73,7 +74,8 @@ class Factors(ctypes.Structure):
 
 
 class Exec(ctypes.Structure):
-    _fields_ = [("per_launch_timing", ctypes.c_int32), ("path", ctypes.c_int32)]
+    _fields_ = [("per_launch_timing", ctypes.c_int32), ("path", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("rec_cap", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -128,6 +130,9 @@ def load(path: str = LIB_PATH):
         "snect_server_submit": (ctypes.c_int, [vp, i64, vp, vp, vp, ctypes.POINTER(i64)]),
         "snect_server_poll": (ctypes.c_int, [vp, i64, vp, vp, vp]),
         "snect_server_replay": (ctypes.c_int, [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "snect_sweep_train": (ctypes.c_int, [vp, i32, vp, vp, i32, i32, vp, vp]),
+        "snect_autotune": (ctypes.c_int, [vp, ctypes.POINTER(Factors), i32, ctypes.POINTER(Exec), vp]),
+        "snect_sweep_autotune": (ctypes.c_int, [vp, i32, vp, vp, i32, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -225,6 +230,36 @@ def orthonormalize(ctx: "Context", A, B, C, G):
     f.C = _dev_ptr(C, (I3, J3), "C")
     f.G = _dev_ptr(G, (J1, J2, J3), "G")
     _check(load().snect_orthonormalize(ctx.h, I1, I2, I3, J1, J2, J3, ctypes.byref(f)), ctx.h)
+
+
+def _sweep_args(problems, factors):
+    n = len(problems)
+    if n == 0 or len(factors) != n:
+        raise ValueError("one factor set per problem")
+    hs = (ctypes.c_void_p * n)(*[p.h.value for p in problems])
+    fs = (Factors * n)(*[p._factors(*f) for p, f in zip(problems, factors)])
+    return n, hs, fs
+
+
+def sweep_train(ctx: "Context", problems, factors, epochs: int, start_epoch: int = 0):
+    """snect_sweep_train: all problems' strata of each epoch in one launch;
+    factors[i] = (A, B, C, G) torch tensors of problem i (updated in place).
+    Returns (loss, rmse), arrays of shape (n, epochs)."""
+    n, hs, fs = _sweep_args(problems, factors)
+    loss = np.zeros((n, max(epochs, 1)))
+    rmse = np.zeros((n, max(epochs, 1)))
+    _check(load().snect_sweep_train(ctx.h, n, ctypes.cast(hs, ctypes.c_void_p), ctypes.cast(fs, ctypes.c_void_p),
+                                    int(start_epoch), int(epochs), loss.ctypes.data, rmse.ctypes.data), ctx.h)
+    return loss[:, :epochs], rmse[:, :epochs]
+
+
+def sweep_autotune(ctx: "Context", problems, factors, trials: int = 1) -> float:
+    """snect_sweep_autotune; returns the best sweep epoch time in ms."""
+    n, hs, fs = _sweep_args(problems, factors)
+    ms = ctypes.c_double()
+    _check(load().snect_sweep_autotune(ctx.h, n, ctypes.cast(hs, ctypes.c_void_p), ctypes.cast(fs, ctypes.c_void_p),
+                                       int(trials), ctypes.addressof(ms)), ctx.h)
+    return ms.value
 
 
 class Server:
@@ -384,12 +419,26 @@ class Problem:
                                         strata.ctypes.data), self.ctx.h)
         return dict(perm1=perm1, perm2=perm2, strata=strata)
 
-    def set_exec(self, per_launch_timing: bool = False, path: int = PATH_AUTO):
-        """snect_set_exec: per-launch timing events and the stratum driver."""
+    def set_exec(self, per_launch_timing: bool = False, path: int = PATH_AUTO, waves: int = 0,
+                 rec_cap: int = 0):
+        """snect_set_exec: per-launch timing events, the stratum driver, the
+        wavefronts per workgroup and the record chunk (results unchanged)."""
         e = Exec()
         e.per_launch_timing = 1 if per_launch_timing else 0
         e.path = int(path)
+        e.waves = int(waves)
+        e.rec_cap = int(rec_cap)
         _check(load().snect_set_exec(self.h, ctypes.byref(e)), self.ctx.h)
+
+    def autotune(self, A, B, C, G, trials: int = 1):
+        """snect_autotune on copies of the given factors; returns the chosen
+        execution choice (dict) and its epoch time in ms."""
+        f = self._factors(A, B, C, G)
+        e = Exec()
+        ms = ctypes.c_double()
+        _check(load().snect_autotune(self.h, ctypes.byref(f), int(trials), ctypes.byref(e), ctypes.addressof(ms)),
+               self.ctx.h)
+        return {n: getattr(e, n) for n, _ in Exec._fields_}, ms.value
 
     def exec_path(self) -> int:
         return int(load().snect_exec_path(self.h))
@@ -416,4 +465,4 @@ class Problem:
 
 __all__ = ["load", "Context", "Problem", "Hyper", "SnectError", "EXPORTS", "ERRORS",
            "PRECISION_FP32", "PRECISION_BF16", "LIB_PATH", "PATH_AUTO", "PATH_PERSISTENT",
-           "PATH_MULTI", "orthonormalize", "Server"]
+           "PATH_MULTI", "orthonormalize", "Server", "sweep_train", "sweep_autotune"]

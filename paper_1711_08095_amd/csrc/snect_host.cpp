@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <thread>
@@ -128,7 +129,10 @@ struct snect_problem {
     double dmax = 0;
     size_t strata_lds = 0, block_lds = 0, loss_lds = 0, core_lds = 0;
     int capacity = 0;
-    int rec_cap = 2048;
+    int rec_cap = 2048;       // records staged per LDS chunk
+    int rec_cap_max = 2048;   // the largest that fits
+    int sweep_rec_cap = 0;    // record chunk inside a batched sweep (0: rec_cap_max)
+    int nw = kDefaultWaves;   // wavefronts per stratum workgroup
     double plan_s = 0, upload_s = 0;
     std::vector<int32_t> perm1, perm2;  // host copies kept for export
     // device buffers
@@ -187,6 +191,30 @@ struct snect_problem {
         return persistent_ok() ? SNECT_PATH_PERSISTENT : SNECT_PATH_MULTI;
     }
 };
+
+// Wavefronts per workgroup and records per LDS chunk of the stratum kernels
+// (execution choices: results do not depend on them).  Sets the LDS size,
+// allows it for the chosen variant and counts the co-resident workgroups.
+static hipError_t configure_exec(snect_problem* pr, int nw, int rec_cap)
+{
+    const size_t slds = strata_lds_bytes(pr->jp, pr->rows1_max, pr->rows2_max, pr->I3, pr->J1, pr->J2, pr->J3,
+                                         rec_cap, pr->bf, nw);
+    if (slds > pr->ctx->max_lds) return hipErrorInvalidValue;
+    const hipError_t e = prepare_strata(pr->jp, pr->bf, nw, slds);
+    if (e != hipSuccess) return e;
+    pr->nw = nw;
+    pr->rec_cap = rec_cap;
+    pr->strata_lds = pr->block_lds = slds;
+    pr->capacity = pr->ctx->coop ? persistent_capacity(pr->jp, pr->bf, nw, slds) : 0;
+    return hipSuccess;
+}
+
+#define HIP_TRY_CTX(C, call)                                                                  \
+    do {                                                                                       \
+        hipError_t _e = (call);                                                                \
+        if (_e != hipSuccess)                                                                  \
+            return set_err((C), SNECT_E_HIP, std::string(#call ": ") + hipGetErrorString(_e)); \
+    } while (0)
 
 #define HIP_TRY(call)                                                                          \
     do {                                                                                       \
@@ -288,9 +316,9 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
     // the largest record chunk that still fits in LDS
     int rec_cap = 2048;
     while (rec_cap > kTileMax &&
-           strata_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf) > ctx->max_lds)
+           strata_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf, 8) > ctx->max_lds)
         rec_cap /= 2;
-    const size_t slds = strata_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf);
+    const size_t slds = strata_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf, 8);
     const size_t blds = slds;
     const size_t llds = loss_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3);
     const size_t clds = core_lds_bytes(I3, J1, J2, J3, kCoreThreads);
@@ -310,6 +338,7 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
     pr->rows1_max = rows1_max; pr->rows2_max = rows2_max; pr->bits_i = bits_i; pr->bits_j = bits_j;
     pr->strata_lds = slds; pr->block_lds = blds; pr->loss_lds = llds; pr->core_lds = clds;
     pr->rec_cap = rec_cap;
+    pr->rec_cap_max = rec_cap;
     pr->n_reg_wg = (I1 + 255) / 256 + (I2 + 255) / 256 + 1;
 
     int rc = SNECT_OK;
@@ -533,13 +562,13 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         he = he ? he : up(pr->d_adj_w, adj_w.data(), adj_w.size() * 4);
         he = he ? he : up(pr->d_deg, deg.data(), (size_t)I2 * 4);
         he = he ? he : hipStreamSynchronize(st);
-        he = he ? he : prepare_kernels(jp, bf, slds, llds, clds);
+        he = he ? he : prepare_kernels(jp, llds, clds);
+        he = he ? he : configure_exec(pr, kDefaultWaves, rec_cap);
         for (int t = 0; t < 4 && he == hipSuccess; ++t) he = hipEventCreate(&pr->ev[t]);
         if (he != hipSuccess) {
             delete pr;
             return set_err(ctx, SNECT_E_HIP, std::string("upload: ") + hipGetErrorString(he));
         }
-        pr->capacity = (ctx->coop && slds <= ctx->max_lds) ? persistent_capacity(jp, bf, slds) : 0;
         pr->upload_s = now_s() - t_up0;
         ctx->live_problems++;
     } catch (const std::bad_alloc&) {
@@ -657,6 +686,106 @@ int snect_evaluate(snect_problem* pr, const snect_factors* f, double* loss, doub
     return SNECT_OK;
 }
 
+static StratArgs strat_args(const snect_problem* pr, const snect_factors* f)
+{
+    StratArgs sa;
+    sa.nz = pr->d_nz; sa.tile_off = pr->d_tile_off; sa.tile_k = pr->d_tile_k; sa.blk_tile = pr->d_blk_tile;
+    sa.start1 = pr->d_start1; sa.start2 = pr->d_start2;
+    sa.reg1 = pr->d_reg1; sa.reg2 = pr->d_reg2; sa.cnt3 = pr->d_cnt3;
+    sa.Ap = pr->d_Ap; sa.Bp = pr->d_Bp; sa.C = f->C; sa.G = f->G;
+    sa.Spart = pr->d_Spart; sa.Mpart = pr->d_Mpart; sa.Ssum = pr->d_Ssum;
+    sa.order = pr->d_order; sa.bar = pr->d_bar; sa.jp = pr->jp;
+    sa.P = pr->P; sa.s = 0; sa.I3 = pr->I3; sa.J1 = pr->J1; sa.J2 = pr->J2; sa.J3 = pr->J3;
+    sa.rows1_max = pr->rows1_max; sa.rows2_max = pr->rows2_max; sa.bits_i = pr->bits_i; sa.bits_j = pr->bits_j;
+    sa.rec_cap = pr->rec_cap;
+    sa.lr = (float)pr->lr; sa.lam = (float)pr->lam; sa.etac = (float)(pr->lr * pr->cls);
+    sa.nnz = (double)pr->nnz;
+    return sa;
+}
+
+// Start of an epoch: keep the factors (position order) for a divergence
+// rollback, then the network step (Jacobi sub-steps through Btmp).
+static int epoch_begin(snect_problem* pr, snect_factors* f)
+{
+    snect_ctx* ctx = pr->ctx;
+    hipStream_t st = ctx->stream;
+    const size_t szA = (size_t)pr->I1 * pr->J1 * 4, szB = (size_t)pr->I2 * pr->J2 * 4,
+                 szC = (size_t)pr->I3 * pr->J3 * 4, szG = (size_t)pr->J1 * pr->J2 * pr->J3 * 4;
+    HIP_TRY(hipMemcpyAsync(pr->d_bakA, pr->d_Ap, szA, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(pr->d_bakB, pr->d_Bp, szB, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(pr->d_bakC, f->C, szC, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(pr->d_bakG, f->G, szG, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipEventRecord(pr->ev[0], st));
+    GraphArgs ga = graph_args(pr);
+    for (int it = 0; it < pr->n_sub; ++it) {
+        const bool even = (it % 2) == 0;
+        ga.Bin = even ? pr->d_Bp : pr->d_Btmp;
+        ga.Bout = even ? pr->d_Btmp : pr->d_Bp;
+        HIP_TRY(launch_graph_step(ga, pr->jp, st));
+    }
+    if (pr->n_sub % 2 == 1) HIP_TRY(hipMemcpyAsync(pr->d_Bp, pr->d_Btmp, szB, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipEventRecord(pr->ev[1], st));
+    return SNECT_OK;
+}
+
+// The persistent driver's per-epoch inputs: the stratum order (through the
+// pinned buffer, free because the previous epoch ended with a stream
+// synchronisation) and a cleared grid barrier.
+static int persistent_inputs(snect_problem* pr, int32_t ep)
+{
+    snect_ctx* ctx = pr->ctx;
+    const std::vector<int32_t> order = stratum_order(pr->P, pr->seed, ep);
+    std::memcpy(pr->h_order, order.data(), (size_t)pr->P * 4);
+    HIP_TRY(hipMemcpyAsync(pr->d_order, pr->h_order, (size_t)pr->P * 4, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipMemsetAsync(pr->d_bar, 0, sizeof(GridBar), ctx->stream));
+    return SNECT_OK;
+}
+
+// After the strata: the loss launch (asynchronous).
+static int epoch_loss(snect_problem* pr, snect_factors* f)
+{
+    HIP_TRY_CTX(pr->ctx, hipEventRecord(pr->ev[2], pr->ctx->stream));
+    int rc = run_loss(pr, f->C, f->G);
+    if (rc) return rc;
+    HIP_TRY_CTX(pr->ctx, hipEventRecord(pr->ev[3], pr->ctx->stream));
+    return SNECT_OK;
+}
+
+// After the stream synchronisation: barrier health, timings, the epoch's
+// loss, and the rollback of a non-finite epoch (SNECT_E_DIVERGED).
+static int epoch_finish(snect_problem* pr, snect_factors* f, int32_t ep, bool persistent, double* loss,
+                        double* rmse)
+{
+    snect_ctx* ctx = pr->ctx;
+    hipStream_t st = ctx->stream;
+    if (persistent) {
+        GridBar hb;
+        HIP_TRY(hipMemcpy(&hb, pr->d_bar, sizeof(GridBar), hipMemcpyDeviceToHost));
+        if (hb.err) return set_err(ctx, SNECT_E_HIP, "grid barrier timed out in the stratum kernel");
+    }
+    float m0 = 0, m1 = 0, m2 = 0;
+    HIP_TRY(hipEventElapsedTime(&m0, pr->ev[0], pr->ev[1]));
+    HIP_TRY(hipEventElapsedTime(&m1, pr->ev[1], pr->ev[2]));
+    HIP_TRY(hipEventElapsedTime(&m2, pr->ev[2], pr->ev[3]));
+    pr->t_ms[0] += m0;
+    pr->t_ms[1] += m1;
+    pr->t_ms[2] += m2;
+    const double fl = pr->h_lossout[0];
+    const double r = pr->nnz > 0 ? std::sqrt(pr->h_lossout[1] / (double)pr->nnz) : 0.0;
+    if (loss) *loss = fl;
+    if (rmse) *rmse = r;
+    if (!std::isfinite(fl) || !std::isfinite(r)) {
+        const size_t szA = (size_t)pr->I1 * pr->J1 * 4, szB = (size_t)pr->I2 * pr->J2 * 4,
+                     szC = (size_t)pr->I3 * pr->J3 * 4, szG = (size_t)pr->J1 * pr->J2 * pr->J3 * 4;
+        HIP_TRY(hipMemcpyAsync(pr->d_Ap, pr->d_bakA, szA, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(pr->d_Bp, pr->d_bakB, szB, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(f->C, pr->d_bakC, szC, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(f->G, pr->d_bakG, szG, hipMemcpyDeviceToDevice, st));
+        return set_err(ctx, SNECT_E_DIVERGED, "loss not finite at epoch " + std::to_string(ep));
+    }
+    return SNECT_OK;
+}
+
 int snect_train(snect_problem* pr, snect_factors* f, int32_t start_epoch, int32_t epochs, double* loss,
                 double* rmse)
 {
@@ -679,77 +808,27 @@ int snect_train(snect_problem* pr, snect_factors* f, int32_t start_epoch, int32_
         pr->evl.resize(2 * (size_t)nlaunch, nullptr);
         for (size_t t = have; t < pr->evl.size(); ++t) HIP_TRY(hipEventCreate(&pr->evl[t]));
     }
-
-    StratArgs sa;
-    sa.nz = pr->d_nz; sa.tile_off = pr->d_tile_off; sa.tile_k = pr->d_tile_k; sa.blk_tile = pr->d_blk_tile;
-    sa.start1 = pr->d_start1; sa.start2 = pr->d_start2;
-    sa.reg1 = pr->d_reg1; sa.reg2 = pr->d_reg2; sa.cnt3 = pr->d_cnt3;
-    sa.Ap = pr->d_Ap; sa.Bp = pr->d_Bp; sa.C = f->C; sa.G = f->G;
-    sa.Spart = pr->d_Spart; sa.Mpart = pr->d_Mpart; sa.Ssum = pr->d_Ssum;
-    sa.order = pr->d_order; sa.bar = pr->d_bar;
-    sa.P = P; sa.s = 0; sa.I3 = pr->I3; sa.J1 = pr->J1; sa.J2 = pr->J2; sa.J3 = pr->J3;
-    sa.rows1_max = pr->rows1_max; sa.rows2_max = pr->rows2_max; sa.bits_i = pr->bits_i; sa.bits_j = pr->bits_j;
-    sa.rec_cap = pr->rec_cap;
-    sa.lr = (float)pr->lr; sa.lam = (float)pr->lam; sa.etac = (float)(pr->lr * pr->cls);
-    sa.nnz = (double)pr->nnz;
-    GraphArgs ga = graph_args(pr);
-
-    const size_t szA = (size_t)pr->I1 * pr->J1 * 4, szB = (size_t)pr->I2 * pr->J2 * 4,
-                 szC = (size_t)pr->I3 * pr->J3 * 4, szG = (size_t)pr->J1 * pr->J2 * pr->J3 * 4;
+    StratArgs sa = strat_args(pr, f);
     if ((rc = to_positions(pr, f))) return rc;
     for (int32_t ep = start_epoch; ep < start_epoch + epochs; ++ep) {
-        // keep the last finite epoch's factors
-        HIP_TRY(hipMemcpyAsync(pr->d_bakA, pr->d_Ap, szA, hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipMemcpyAsync(pr->d_bakB, pr->d_Bp, szB, hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipMemcpyAsync(pr->d_bakC, f->C, szC, hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipMemcpyAsync(pr->d_bakG, f->G, szG, hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipEventRecord(pr->ev[0], st));
-        // (a) network step, Jacobi sub-steps ping-ponging through Btmp
-        for (int it = 0; it < pr->n_sub; ++it) {
-            const bool even = (it % 2) == 0;
-            ga.Bin = even ? pr->d_Bp : pr->d_Btmp;
-            ga.Bout = even ? pr->d_Btmp : pr->d_Bp;
-            HIP_TRY(launch_graph_step(ga, pr->jp, st));
-        }
-        if (pr->n_sub % 2 == 1) HIP_TRY(hipMemcpyAsync(pr->d_Bp, pr->d_Btmp, szB, hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipEventRecord(pr->ev[1], st));
-        // (b) strata
-        const std::vector<int32_t> order = stratum_order(P, pr->seed, ep);
+        if ((rc = epoch_begin(pr, f))) return rc;
         if (path == SNECT_PATH_PERSISTENT) {
-            // the pinned order buffer is free: the previous epoch ended with a
-            // stream synchronisation
-            std::memcpy(pr->h_order, order.data(), (size_t)P * 4);
-            HIP_TRY(hipMemcpyAsync(pr->d_order, pr->h_order, (size_t)P * 4, hipMemcpyHostToDevice, st));
-            HIP_TRY(hipMemsetAsync(pr->d_bar, 0, sizeof(GridBar), st));
+            if ((rc = persistent_inputs(pr, ep))) return rc;
             if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[0], st));
-            HIP_TRY(launch_strata_persistent(sa, pr->jp, pr->bf, pr->strata_lds, st));
+            HIP_TRY(launch_strata_persistent(sa, pr->jp, pr->bf, pr->nw, pr->strata_lds, st));
             if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[1], st));
         } else {
+            const std::vector<int32_t> order = stratum_order(P, pr->seed, ep);
             for (int si = 0; si < P; ++si) {
                 sa.s = order[si];
                 if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[2 * si], st));
-                HIP_TRY(launch_block(sa, pr->jp, pr->bf, pr->block_lds, st));
+                HIP_TRY(launch_block(sa, pr->jp, pr->bf, pr->nw, pr->block_lds, st));
                 if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[2 * si + 1], st));
                 HIP_TRY(launch_core_step(sa, pr->core_lds, st));
             }
         }
-        HIP_TRY(hipEventRecord(pr->ev[2], st));
-        // (c) loss
-        if ((rc = run_loss(pr, f->C, f->G))) return rc;
-        HIP_TRY(hipEventRecord(pr->ev[3], st));
+        if ((rc = epoch_loss(pr, f))) return rc;
         HIP_TRY(hipStreamSynchronize(st));
-        if (path == SNECT_PATH_PERSISTENT) {
-            GridBar hb;
-            HIP_TRY(hipMemcpy(&hb, pr->d_bar, sizeof(GridBar), hipMemcpyDeviceToHost));
-            if (hb.err) return set_err(ctx, SNECT_E_HIP, "grid barrier timed out in the stratum kernel");
-        }
-        float m0 = 0, m1 = 0, m2 = 0;
-        HIP_TRY(hipEventElapsedTime(&m0, pr->ev[0], pr->ev[1]));
-        HIP_TRY(hipEventElapsedTime(&m1, pr->ev[1], pr->ev[2]));
-        HIP_TRY(hipEventElapsedTime(&m2, pr->ev[2], pr->ev[3]));
-        pr->t_ms[0] += m0;
-        pr->t_ms[1] += m1;
-        pr->t_ms[2] += m2;
         if (pr->per_launch) {
             for (int l = 0; l < nlaunch; ++l) {
                 float ms = 0.f;
@@ -758,22 +837,248 @@ int snect_train(snect_problem* pr, snect_factors* f, int32_t start_epoch, int32_
             }
             pr->t_ms[4] += nlaunch;
         }
-        const double fl = pr->h_lossout[0];
-        const double r = pr->nnz > 0 ? std::sqrt(pr->h_lossout[1] / (double)pr->nnz) : 0.0;
-        if (loss) loss[ep - start_epoch] = fl;
-        if (rmse) rmse[ep - start_epoch] = r;
-        if (!std::isfinite(fl) || !std::isfinite(r)) {
-            HIP_TRY(hipMemcpyAsync(pr->d_Ap, pr->d_bakA, szA, hipMemcpyDeviceToDevice, st));
-            HIP_TRY(hipMemcpyAsync(pr->d_Bp, pr->d_bakB, szB, hipMemcpyDeviceToDevice, st));
-            HIP_TRY(hipMemcpyAsync(f->C, pr->d_bakC, szC, hipMemcpyDeviceToDevice, st));
-            HIP_TRY(hipMemcpyAsync(f->G, pr->d_bakG, szG, hipMemcpyDeviceToDevice, st));
-            if ((rc = from_positions(pr, f))) return rc;
-            HIP_TRY(hipStreamSynchronize(st));
-            return set_err(ctx, SNECT_E_DIVERGED, "loss not finite at epoch " + std::to_string(ep));
+        rc = epoch_finish(pr, f, ep, path == SNECT_PATH_PERSISTENT, loss ? loss + (ep - start_epoch) : nullptr,
+                          rmse ? rmse + (ep - start_epoch) : nullptr);
+        if (rc) {
+            const std::string msg = ctx->err;
+            if (rc == SNECT_E_DIVERGED) {
+                int r2 = from_positions(pr, f);
+                if (r2 == SNECT_OK) (void)hipStreamSynchronize(st);
+            }
+            ctx->err = msg;
+            return rc;
         }
     }
     if ((rc = from_positions(pr, f))) return rc;
     HIP_TRY(hipStreamSynchronize(st));
+    return SNECT_OK;
+}
+
+int snect_sweep_train(snect_ctx* ctx, int32_t n, snect_problem* const* probs, snect_factors* fs, int32_t start_epoch,
+                      int32_t epochs, double* loss, double* rmse)
+{
+    if (!ctx) return SNECT_E_ARG;
+    ctx->err.clear();
+    if (n < 1 || !probs || !fs || epochs < 0 || start_epoch < 0)
+        return set_err(ctx, SNECT_E_ARG, "bad sweep arguments");
+    int bf = -1, nwg = 0;
+    for (int i = 0; i < n; ++i) {
+        snect_problem* pr = probs[i];
+        if (!pr || pr->ctx != ctx) return set_err(ctx, SNECT_E_ARG, "problem " + std::to_string(i) + " is not on ctx");
+        int rc = check_factors(ctx, &fs[i]);
+        if (rc) return rc;
+        for (int t = 0; t < i; ++t)
+            if (probs[t] == pr) return set_err(ctx, SNECT_E_ARG, "a problem appears twice in the sweep");
+        if (bf >= 0 && pr->bf != bf) return set_err(ctx, SNECT_E_ARG, "all problems of a sweep share one precision");
+        bf = pr->bf;
+        nwg += pr->P;
+    }
+    if (!ctx->coop) return set_err(ctx, SNECT_E_UNSUPPORTED, "cooperative launches not available");
+    // one launch of kDefaultWaves-wavefront workgroups; each problem keeps
+    // its own core-size code, LDS layout and largest record chunk
+    std::vector<int> rcap(n);
+    size_t lds = 0;
+    for (int i = 0; i < n; ++i) {
+        const snect_problem* pr = probs[i];
+        rcap[i] = pr->sweep_rec_cap ? pr->sweep_rec_cap : pr->rec_cap_max;
+        lds = std::max(lds, strata_lds_bytes(pr->jp, pr->rows1_max, pr->rows2_max, pr->I3, pr->J1, pr->J2, pr->J3,
+                                             rcap[i], bf, kDefaultWaves));
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(prepare_sweep(bf, lds));
+    const int cap = sweep_capacity(bf, lds);
+    if (nwg > cap)
+        return set_err(ctx, SNECT_E_UNSUPPORTED, "the sweep needs " + std::to_string(nwg) +
+                                                     " co-resident workgroups, the device holds " + std::to_string(cap));
+    hipStream_t st = ctx->stream;
+    // launch arguments in device memory
+    std::vector<StratArgs> args(n);
+    std::vector<int32_t> wg_start(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        args[i] = strat_args(probs[i], &fs[i]);
+        args[i].rec_cap = rcap[i];
+        wg_start[i + 1] = wg_start[i] + probs[i]->P;
+    }
+    void* d_args = nullptr;
+    if (hipMalloc(&d_args, sizeof(StratArgs) * n + sizeof(int32_t) * (n + 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(ctx, SNECT_E_OOM, "sweep argument buffer");
+    }
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(d_args);
+    };
+    int32_t* d_wg = reinterpret_cast<int32_t*>(static_cast<char*>(d_args) + sizeof(StratArgs) * n);
+    hipError_t e = hipMemcpyAsync(d_args, args.data(), sizeof(StratArgs) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_wg, wg_start.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+        cleanup();
+        return set_err(ctx, SNECT_E_HIP, std::string("sweep arguments: ") + hipGetErrorString(e));
+    }
+    int rc = SNECT_OK;
+    for (int i = 0; i < n && !rc; ++i) {
+        for (double& t : probs[i]->t_ms) t = 0.0;
+        rc = to_positions(probs[i], &fs[i]);
+    }
+    for (int32_t ep = start_epoch; ep < start_epoch + epochs && !rc; ++ep) {
+        for (int i = 0; i < n && !rc; ++i) rc = epoch_begin(probs[i], &fs[i]);
+        for (int i = 0; i < n && !rc; ++i) rc = persistent_inputs(probs[i], ep);
+        if (!rc) {
+            e = launch_strata_sweep(static_cast<const StratArgs*>(d_args), d_wg, n, nwg, bf, lds, st);
+            if (e != hipSuccess) rc = set_err(ctx, SNECT_E_HIP, std::string("sweep launch: ") + hipGetErrorString(e));
+        }
+        for (int i = 0; i < n && !rc; ++i) rc = epoch_loss(probs[i], &fs[i]);
+        if (!rc && (e = hipStreamSynchronize(st)) != hipSuccess)
+            rc = set_err(ctx, SNECT_E_HIP, std::string("sweep: ") + hipGetErrorString(e));
+        for (int i = 0; i < n && !rc; ++i) {
+            const size_t o = (size_t)i * epochs + (ep - start_epoch);
+            rc = epoch_finish(probs[i], &fs[i], ep, true, loss ? loss + o : nullptr, rmse ? rmse + o : nullptr);
+            if (rc == SNECT_E_DIVERGED) ctx->err = "problem " + std::to_string(i) + ": " + ctx->err;
+        }
+    }
+    const std::string msg = ctx->err;
+    for (int i = 0; i < n; ++i) (void)from_positions(probs[i], &fs[i]);
+    cleanup();
+    ctx->err = msg;
+    return rc;
+}
+
+// Device copies of a problem's factors (scratch for the autotuners).
+struct FactorCopy {
+    snect_factors f{nullptr, nullptr, nullptr, nullptr};
+    size_t sz[4] = {0, 0, 0, 0};
+    ~FactorCopy()
+    {
+        (void)hipFree(f.A);
+        (void)hipFree(f.B);
+        (void)hipFree(f.C);
+        (void)hipFree(f.G);
+    }
+    hipError_t alloc(const snect_problem* pr)
+    {
+        sz[0] = (size_t)pr->I1 * pr->J1 * 4;
+        sz[1] = (size_t)pr->I2 * pr->J2 * 4;
+        sz[2] = (size_t)pr->I3 * pr->J3 * 4;
+        sz[3] = (size_t)pr->J1 * pr->J2 * pr->J3 * 4;
+        float** d[4] = {&f.A, &f.B, &f.C, &f.G};
+        for (int t = 0; t < 4; ++t)
+            if (hipMalloc(reinterpret_cast<void**>(d[t]), std::max<size_t>(sz[t], 16)) != hipSuccess) {
+                (void)hipGetLastError();
+                return hipErrorOutOfMemory;
+            }
+        return hipSuccess;
+    }
+    hipError_t load(const snect_factors* src, hipStream_t st)
+    {
+        const float* s_[4] = {src->A, src->B, src->C, src->G};
+        float* d_[4] = {f.A, f.B, f.C, f.G};
+        for (int t = 0; t < 4; ++t) {
+            const hipError_t e = hipMemcpyAsync(d_[t], s_[t], sz[t], hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+};
+
+int snect_autotune(snect_problem* pr, const snect_factors* f, int32_t trials, snect_exec* best, double* best_ms)
+{
+    if (!pr) return SNECT_E_ARG;
+    snect_ctx* ctx = pr->ctx;
+    ctx->err.clear();
+    int rc = check_factors(ctx, f);
+    if (rc) return rc;
+    if (trials < 1) return set_err(ctx, SNECT_E_ARG, "trials must be >= 1");
+    HIP_TRY(hipSetDevice(ctx->device));
+    FactorCopy fc;
+    if (fc.alloc(pr) != hipSuccess) return set_err(ctx, SNECT_E_OOM, "autotune scratch factors");
+    const int keep_path = pr->path, keep_nw = pr->nw, keep_rc = pr->rec_cap;
+    const bool keep_pl = pr->per_launch;
+    pr->per_launch = false;
+    snect_exec b{0, keep_path, keep_nw, keep_rc};
+    double bt = -1.0;
+    for (int path : {SNECT_PATH_PERSISTENT, SNECT_PATH_MULTI})
+        for (int nw : {8, 4})
+            for (int rcap = pr->rec_cap_max; rcap >= std::min(256, pr->rec_cap_max); rcap /= 2) {
+                if (configure_exec(pr, nw, rcap) != hipSuccess) continue;
+                pr->path = path;
+                if (path == SNECT_PATH_PERSISTENT && !pr->persistent_ok()) continue;
+                double t = -1.0;
+                for (int k = 0; k < trials; ++k) {
+                    HIP_TRY(fc.load(f, ctx->stream));
+                    rc = snect_train(pr, &fc.f, 0, 1, nullptr, nullptr);
+                    if (rc) break;
+                    const double ms = pr->t_ms[0] + pr->t_ms[1] + pr->t_ms[2];
+                    t = t < 0 ? ms : std::min(t, ms);
+                }
+                if (rc) {
+                    (void)configure_exec(pr, keep_nw, keep_rc);
+                    pr->path = keep_path;
+                    pr->per_launch = keep_pl;
+                    return rc;
+                }
+                if (bt < 0 || t < bt) {
+                    bt = t;
+                    b = snect_exec{0, path, nw, rcap};
+                }
+            }
+    pr->per_launch = keep_pl;
+    if (bt < 0) {
+        (void)configure_exec(pr, keep_nw, keep_rc);
+        pr->path = keep_path;
+        return set_err(ctx, SNECT_E_UNSUPPORTED, "no execution choice could run");
+    }
+    HIP_TRY(configure_exec(pr, b.waves, b.rec_cap));
+    pr->path = b.path;
+    b.per_launch_timing = keep_pl ? 1 : 0;
+    if (best) *best = b;
+    if (best_ms) *best_ms = bt;
+    return SNECT_OK;
+}
+
+int snect_sweep_autotune(snect_ctx* ctx, int32_t n, snect_problem* const* probs, const snect_factors* fs,
+                         int32_t trials, double* best_ms)
+{
+    if (!ctx) return SNECT_E_ARG;
+    ctx->err.clear();
+    if (n < 1 || !probs || !fs || trials < 1) return set_err(ctx, SNECT_E_ARG, "bad sweep autotune arguments");
+    for (int i = 0; i < n; ++i)
+        if (!probs[i] || probs[i]->ctx != ctx) return set_err(ctx, SNECT_E_ARG, "problem not on ctx");
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::vector<std::unique_ptr<FactorCopy>> fc(n);
+    std::vector<snect_factors> sf(n);
+    std::vector<int> keep(n);
+    for (int i = 0; i < n; ++i) {
+        fc[i].reset(new (std::nothrow) FactorCopy());
+        if (!fc[i] || fc[i]->alloc(probs[i]) != hipSuccess) return set_err(ctx, SNECT_E_OOM, "autotune scratch");
+        sf[i] = fc[i]->f;
+        keep[i] = probs[i]->sweep_rec_cap;
+    }
+    // candidates: every problem's record chunk scaled by 1, 1/2, 1/4 (>= 256)
+    double bt = -1.0;
+    int bshift = 0;
+    int rc = SNECT_OK;
+    for (int shift = 0; shift <= 2; ++shift) {
+        for (int i = 0; i < n; ++i)
+            probs[i]->sweep_rec_cap = std::max(std::min(256, probs[i]->rec_cap_max), probs[i]->rec_cap_max >> shift);
+        double t = -1.0;
+        for (int k = 0; k < trials && !rc; ++k) {
+            for (int i = 0; i < n; ++i) HIP_TRY(fc[i]->load(&fs[i], ctx->stream));
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = snect_sweep_train(ctx, n, probs, sf.data(), 0, 1, nullptr, nullptr);
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            t = t < 0 ? ms : std::min(t, ms);
+        }
+        if (rc) break;
+        if (bt < 0 || t < bt) {
+            bt = t;
+            bshift = shift;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        probs[i]->sweep_rec_cap =
+            rc ? keep[i] : std::max(std::min(256, probs[i]->rec_cap_max), probs[i]->rec_cap_max >> bshift);
+    if (rc) return rc;
+    if (best_ms) *best_ms = bt;
     return SNECT_OK;
 }
 
@@ -832,6 +1137,15 @@ int snect_set_exec(snect_problem* pr, const snect_exec* ex)
     if (!pr || !ex) return SNECT_E_ARG;
     if (ex->path < SNECT_PATH_AUTO || ex->path > SNECT_PATH_MULTI)
         return set_err(pr->ctx, SNECT_E_ARG, "unknown path");
+    const int nw = ex->waves == 0 ? kDefaultWaves : ex->waves;
+    if (nw != 4 && nw != 8) return set_err(pr->ctx, SNECT_E_ARG, "waves must be 0, 4 or 8");
+    const int rc = ex->rec_cap == 0 ? pr->rec_cap_max : ex->rec_cap;
+    if (rc < kTileMax || rc > pr->rec_cap_max || (rc & (rc - 1)) != 0)
+        return set_err(pr->ctx, SNECT_E_ARG,
+                       "rec_cap must be 0 or a power of two in [64, " + std::to_string(pr->rec_cap_max) + "]");
+    snect_ctx* ctx = pr->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(configure_exec(pr, nw, rc));
     pr->per_launch = ex->per_launch_timing != 0;
     pr->path = ex->path;
     return SNECT_OK;

@@ -70,6 +70,7 @@ struct StratArgs {
     float* Ssum;               // [I3*J1*J2] stratum sums (persistent kernel)
     const int32_t* order;      // [P] stratum order of this epoch
     GridBar* bar;
+    int32_t jp;                // kernel instantiation of this problem's core
     int32_t P, s, I3, J1, J2, J3;
     int32_t rows1_max, rows2_max;
     int32_t bits_i, bits_j;
@@ -119,36 +120,41 @@ struct GraphArgs {
 };
 
 size_t strata_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3, int rec_cap,
-                        int bf);
+                        int bf, int nw);
 size_t loss_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3);
 size_t core_lds_bytes(int I3, int J1, int J2, int J3, int threads);
 int jp_for(int J1, int J2);
 
 // Persistent: one cooperative launch runs every stratum of one epoch.
-hipError_t launch_strata_persistent(const StratArgs& a, int jp, int bf, size_t lds, hipStream_t st);
+hipError_t launch_strata_persistent(const StratArgs& a, int jp, int bf, int nw, size_t lds, hipStream_t st);
+// Batched sweep: n problems in one cooperative launch of nwg workgroups of
+// kDefaultWaves wavefronts (args and wg_start in device memory).
+hipError_t launch_strata_sweep(const StratArgs* args, const int32_t* wg_start, int n, int nwg, int bf, size_t lds,
+                               hipStream_t st);
+hipError_t prepare_sweep(int bf, size_t lds);
 // Fallback: one launch per stratum plus one core-step launch.  bf selects
 // the BF16 matrix-core contractions of the tile step.
-hipError_t launch_block(const StratArgs& a, int jp, int bf, size_t lds, hipStream_t st);
+hipError_t launch_block(const StratArgs& a, int jp, int bf, int nw, size_t lds, hipStream_t st);
 hipError_t launch_core_step(const StratArgs& a, size_t lds, hipStream_t st);
 hipError_t launch_graph_step(const GraphArgs& a, int jp, hipStream_t st);
 hipError_t launch_loss(const LossArgs& a, const GraphArgs& g, int jp, size_t lds, hipStream_t st);
 hipError_t launch_permute(const float* src, float* dst, const int32_t* perm, int rows, int cols, int gather,
                           hipStream_t st);
-hipError_t prepare_kernels(int jp, int bf, size_t strata_lds, size_t loss_lds, size_t core_lds);
+hipError_t prepare_kernels(int jp, size_t loss_lds, size_t core_lds);
+// Allows the stratum kernels of one variant more than 64 KB of LDS.
+hipError_t prepare_strata(int jp, int bf, int nw, size_t strata_lds);
 // Orthonormalisation of one mode (FP64 CholeskyQR2); see snect_qr.hip.
 size_t qr_scratch_bytes(int I, int J, int J1, int J2, int J3);
 hipError_t launch_qr_mode(float* U, int I, int J, float* G, int J1, int J2, int J3, int mode, void* scratch,
                           int* status, hipStream_t st);
 // Largest number of co-resident workgroups of the persistent kernel.
-int persistent_capacity(int jp, int bf, size_t lds);
+int persistent_capacity(int jp, int bf, int nw, size_t lds);
+// Largest number of co-resident workgroups of the batched sweep kernel.
+int sweep_capacity(int bf, size_t lds);
 
-// Wavefronts per stratum workgroup (factor columns are shared among them) and
-// the four of them that accumulate the block's S on the matrix cores.
-#ifndef SNECT_STRAT_WAVES
-#define SNECT_STRAT_WAVES 8
-#endif
-__host__ __device__ constexpr int strat_waves(int jp) { return jp > 0 ? SNECT_STRAT_WAVES : SNECT_STRAT_WAVES; }
-__host__ __device__ constexpr int strat_threads(int jp) { return 64 * strat_waves(jp); }
+// Wavefronts per stratum workgroup (4 or 8; factor columns are shared
+// among them); four of them accumulate the block's S on the matrix cores.
+constexpr int kDefaultWaves = 8;
 constexpr int kMfmaWaves = 4;
 constexpr int kCoreThreads = 1024;
 

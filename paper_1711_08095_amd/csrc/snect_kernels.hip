@@ -67,7 +67,7 @@ struct StratLds {
 __host__ __device__ inline int up4(int o) { return (o + 3) & ~3; }
 
 __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2,
-                                                     int J3, int rec_cap, int bf)
+                                                     int J3, int rec_cap, int bf, int nw)
 {
     const int rs = row_stride(jp), mp = mfma_dim(jp), j12 = J1 * J2;
     const int nch = (j12 + kCoreChunk - 1) / kCoreChunk;
@@ -85,7 +85,7 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     L.sb = o;    o = up4(o + f32 * jp * kTS);
     L.as = o;    o = up4(o + f32 * mp * kTS);
     L.es = o;    o = up4(o + f32 * mp * kTS);
-    L.xtp = o;   o = up4(o + f32 * strat_threads(jp));
+    L.xtp = o;   o = up4(o + f32 * jp * kTileMax);          // a_c w1_c per column
     L.hb = o;    o = up4(o + bf * I3 * mp * kKB);        // 2 x I3 x mp x 32 bf16
     L.sw1 = o;   o = up4(o + bf * mp * kTW);
     L.sw2 = o;   o = up4(o + bf * mp * kTW);
@@ -99,7 +99,7 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     L.mk = o;    o = up4(o + I3);
     L.tco = o;   o = up4(o + kTileCache + 1);
     L.tck = o;   o = up4(o + kTileCache);
-    L.red = o;   o = up4(o + (strat_threads(jp) > I3 * J3 * nch ? strat_threads(jp) : I3 * J3 * nch));
+    L.red = o;   o = up4(o + (64 * nw > I3 * J3 * nch ? 64 * nw : I3 * J3 * nch));
     L.msum = o;  o = up4(o + 2 * I3);          // doubles
     L.cgt = o;   o = up4(o + I3 * J3 + j12 * J3);
     L.flag = o;  o = up4(o + 1);
@@ -108,9 +108,10 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     return L;
 }
 
-size_t strata_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3, int rec_cap, int bf)
+size_t strata_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3, int rec_cap, int bf,
+                        int nw)
 {
-    return align16(4 * (size_t)strat_lds_layout(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf).total);
+    return align16(4 * (size_t)strat_lds_layout(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf, nw).total);
 }
 
 int jp_for(int J1, int J2)
@@ -508,15 +509,17 @@ struct TileLds {
     uint2* rec;   // [rec_cap] staged records
 };
 
-// The tiles of block (p, q), run by the whole workgroup (strat_threads(JP)
-// threads).  L.Ab/L.Bb hold the block's rows; L.Skw receives each
-// wavefront's per-platform sums, L.Mk the block's counts.
-template <int JP>
+// The tiles of block (p, q), run by the whole workgroup (NW wavefronts).
+// L.Ab/L.Bb hold the block's rows; L.Skw receives the per-platform sums of
+// the four matrix-core wavefronts, L.Mk the block's counts.  Every sum is
+// taken in an order that does not depend on NW (x~ over ascending columns,
+// S over four fixed nonzero ranges), so NW is an execution choice only.
+template <int JP, int NW>
 __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, int tid)
 {
     constexpr int RS = row_stride(JP);
     constexpr int MP = mfma_dim(JP);
-    constexpr int NW = strat_waves(JP), NT = 64 * NW;
+    constexpr int NT = 64 * NW;
     constexpr int QN = (JP + NW - 1) / NW;  // owned factor columns per wavefront
     constexpr int QM = (MP + NW - 1) / NW;  // owned operand columns per wavefront
     const int lane = tid & 63, w = tid >> 6;
@@ -586,7 +589,6 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         }
         const float* H = L.Hs + k * JP * JP;
         float w1q[QN], w2q[QN], aq[QN];
-        float xw = 0.f;
 #pragma unroll
         for (int qq = 0; qq < QN; ++qq) {
             const int c = w + NW * qq;
@@ -604,20 +606,20 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
                     for (int x_ = 0; x_ < JP; ++x_) t2v = fmaf(av[x_], H[x_ * JP + c], t2v);
                 }
                 ac = act ? L.Ab[il * RS + c] : 0.f;
-                xw = fmaf(ac, t1v, xw);
+                L.xtp[c * kTileMax + lane] = ac * t1v;
             }
             w1q[qq] = t1v;
             w2q[qq] = t2v;
             aq[qq] = ac;
             if constexpr (JP > 16) lds_order_fence();
         }
-        L.xtp[w * 64 + lane] = xw;
         __syncthreads();
 
-        // 2. residual; stage row terms and matrix-core operands
+        // 2. residual (x~ summed over ascending columns); stage row terms
+        //    and matrix-core operands
         float xt = L.xtp[lane];
 #pragma unroll
-        for (int ww = 1; ww < NW; ++ww) xt += L.xtp[ww * 64 + lane];
+        for (int c = 1; c < JP; ++c) xt += L.xtp[c * kTileMax + lane];
         const float e = act ? x - xt : 0.f;
 #pragma unroll
         for (int qq = 0; qq < QN; ++qq) {
@@ -698,13 +700,13 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
 //   3. S on the matrix cores; the patient and gene runs are summed with the
 //      same segmented scans as the FP32 path, on e*w1 and e*w2;
 // with a barrier after each of the three steps.
-template <int JP>
+template <int JP, int NW>
 __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& L, int tid)
 {
     constexpr int RS = row_stride(JP);
     constexpr int MP = mfma_dim(JP);
     constexpr int NB = MP / 16;
-    constexpr int NW = strat_waves(JP), NT = 64 * NW;
+    constexpr int NT = 64 * NW;
     constexpr int QN = (JP + NW - 1) / NW;
     constexpr int QM = (MP + NW - 1) / NW;
     const int lane = tid & 63, w = tid >> 6, g = lane >> 4, m = lane & 15;
@@ -960,17 +962,17 @@ __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
 // ---------------------------------------------------------------------------
 // Persistent driver: every stratum of one epoch in one launch.
 // ---------------------------------------------------------------------------
-template <int JP, bool BF>
-__global__ __launch_bounds__(strat_threads(JP)) void strata_persistent(StratArgs a)
+// Every stratum of one epoch of one problem, run by its workgroup q (gene
+// block q) of the problem's P co-resident workgroups.
+template <int JP, bool BF, int NW>
+__device__ void strata_body(const StratArgs& a, int q, float* lds)
 {
     constexpr int RS = row_stride(JP);
-    constexpr int NT = strat_threads(JP);
-    extern __shared__ float lds[];
+    constexpr int NT = 64 * NW;
     const int tid = threadIdx.x;
-    const int q = blockIdx.x;
     const int P = a.P, I3 = a.I3, J1 = a.J1, J2 = a.J2, J3 = a.J3, J12 = J1 * J2;
     const int ni = I3 * J12;
-    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3, a.rec_cap, BF ? 1 : 0);
+    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3, a.rec_cap, BF ? 1 : 0, NW);
     const TileLds L = tile_lds<JP>(lds, S);
     float* Cs = lds + S.c;
     float* Gs = lds + S.g;
@@ -1010,9 +1012,9 @@ __global__ __launch_bounds__(strat_threads(JP)) void strata_persistent(StratArgs
         if constexpr (BF) {
             build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Hs, I3, tid, NT);
             __syncthreads();
-            block_tiles_bf<JP>(a, p, q, L, tid);
+            block_tiles_bf<JP, NW>(a, p, q, L, tid);
         } else {
-            block_tiles<JP>(a, p, q, L, tid);
+            block_tiles<JP, NW>(a, p, q, L, tid);
         }
         combine_waves(Sk, L.Skw, ni, tid, NT);
         store_rows(a.Ap, L.Ab, s1, r1, J1, RS, tid, NT);
@@ -1042,20 +1044,57 @@ __global__ __launch_bounds__(strat_threads(JP)) void strata_persistent(StratArgs
     }
 }
 
+template <int JP, bool BF, int NW>
+__global__ __launch_bounds__(64 * NW) void strata_persistent(StratArgs a)
+{
+    extern __shared__ float lds[];
+    strata_body<JP, BF, NW>(a, blockIdx.x, lds);
+}
+
+// Batched sweep: the workgroups [wg_start[i], wg_start[i+1]) of one
+// cooperative launch run problem i with the code of its own core size
+// (a.jp), exactly as the single-problem kernel would; each problem
+// synchronises on its own grid barrier.
+template <bool BF>
+__global__ __launch_bounds__(64 * kDefaultWaves) void strata_sweep(const StratArgs* args, const int32_t* wg_start,
+                                                                   int n)
+{
+    constexpr int NW = kDefaultWaves;
+    extern __shared__ float lds[];
+    const int b = blockIdx.x;
+    int i = 0;
+    while (i + 1 < n && b >= wg_start[i + 1]) ++i;
+    const StratArgs a = args[i];
+    const int q = b - wg_start[i];
+    switch (a.jp) {
+    case 2: strata_body<2, BF, NW>(a, q, lds); break;
+    case 4: strata_body<4, BF, NW>(a, q, lds); break;
+    case 5: strata_body<5, BF, NW>(a, q, lds); break;
+    case 8: strata_body<8, BF, NW>(a, q, lds); break;
+    case 10: strata_body<10, BF, NW>(a, q, lds); break;
+    case 12: strata_body<12, BF, NW>(a, q, lds); break;
+    case 16: strata_body<16, BF, NW>(a, q, lds); break;
+    case 20: strata_body<20, BF, NW>(a, q, lds); break;
+    case 24: strata_body<24, BF, NW>(a, q, lds); break;
+    case 32: strata_body<32, BF, NW>(a, q, lds); break;
+    default: break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Multi-launch driver: one block step per stratum, then one core step.
 // ---------------------------------------------------------------------------
-template <int JP, bool BF>
-__global__ __launch_bounds__(strat_threads(JP)) void block_step(StratArgs a)
+template <int JP, bool BF, int NW>
+__global__ __launch_bounds__(64 * NW) void block_step(StratArgs a)
 {
     constexpr int RS = row_stride(JP);
-    constexpr int NT = strat_threads(JP);
+    constexpr int NT = 64 * NW;
     extern __shared__ float lds[];
     const int tid = threadIdx.x;
     const int p = blockIdx.x, P = a.P;
     const int q = (p + a.s) % P;
     const int I3 = a.I3, J1 = a.J1, J2 = a.J2, J3 = a.J3, J12 = J1 * J2, ni = I3 * J12;
-    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3, a.rec_cap, BF ? 1 : 0);
+    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3, a.rec_cap, BF ? 1 : 0, NW);
     const TileLds L = tile_lds<JP>(lds, S);
     float* Cs = lds + S.c;
     float* Gs = lds + S.g;
@@ -1079,9 +1118,9 @@ __global__ __launch_bounds__(strat_threads(JP)) void block_step(StratArgs a)
     if constexpr (BF) {
         build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Hs, I3, tid, NT);
         __syncthreads();
-        block_tiles_bf<JP>(a, p, q, L, tid);
+        block_tiles_bf<JP, NW>(a, p, q, L, tid);
     } else {
-        block_tiles<JP>(a, p, q, L, tid);
+        block_tiles<JP, NW>(a, p, q, L, tid);
     }
     combine_waves(Sk, L.Skw, ni, tid, NT);
     store_rows(a.Ap, L.Ab, s1, r1, J1, RS, tid, NT);
@@ -1382,32 +1421,53 @@ __global__ __launch_bounds__(256) void permute_rows(const float* src, float* dst
     default: return hipErrorInvalidValue;     \
     }
 
-template <int JP, bool BF>
+// Instantiation of a (JP, BF16?, wavefronts) variant of a stratum-kernel helper.
+#define SNECT_VARIANT(F, J, ...)                                                              \
+    (bf ? (nw == 4 ? F<J, true, 4>(__VA_ARGS__) : F<J, true, 8>(__VA_ARGS__))                 \
+        : (nw == 4 ? F<J, false, 4>(__VA_ARGS__) : F<J, false, 8>(__VA_ARGS__)))
+
+template <int JP, bool BF, int NW>
 static hipError_t launch_persistent_t(const StratArgs& a, size_t lds, hipStream_t st)
 {
     StratArgs copy = a;
     void* args[] = {&copy};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&strata_persistent<JP, BF>), dim3(a.P),
-                                      dim3(strat_threads(JP)), args, (unsigned)lds, st);
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&strata_persistent<JP, BF, NW>), dim3(a.P),
+                                      dim3(64 * NW), args, (unsigned)lds, st);
 }
 
-hipError_t launch_strata_persistent(const StratArgs& a, int jp, int bf, size_t lds, hipStream_t st)
+hipError_t launch_strata_persistent(const StratArgs& a, int jp, int bf, int nw, size_t lds, hipStream_t st)
 {
-#define CALL_P(J) (bf ? launch_persistent_t<J, true>(a, lds, st) : launch_persistent_t<J, false>(a, lds, st))
+#define CALL_P(J) SNECT_VARIANT(launch_persistent_t, J, a, lds, st)
     SNECT_JP_SWITCH(jp, CALL_P)
 #undef CALL_P
 }
 
-template <int JP, bool BF>
+template <bool BF>
+static hipError_t launch_sweep_t(const StratArgs* args, const int32_t* wg_start, int n, int nwg, size_t lds,
+                                 hipStream_t st)
+{
+    void* kargs[] = {&args, &wg_start, &n};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&strata_sweep<BF>), dim3(nwg),
+                                      dim3(64 * kDefaultWaves), kargs, (unsigned)lds, st);
+}
+
+hipError_t launch_strata_sweep(const StratArgs* args, const int32_t* wg_start, int n, int nwg, int bf, size_t lds,
+                               hipStream_t st)
+{
+    return bf ? launch_sweep_t<true>(args, wg_start, n, nwg, lds, st)
+              : launch_sweep_t<false>(args, wg_start, n, nwg, lds, st);
+}
+
+template <int JP, bool BF, int NW>
 static hipError_t launch_block_t(const StratArgs& a, size_t lds, hipStream_t st)
 {
-    hipLaunchKernelGGL((block_step<JP, BF>), dim3(a.P), dim3(strat_threads(JP)), lds, st, a);
+    hipLaunchKernelGGL((block_step<JP, BF, NW>), dim3(a.P), dim3(64 * NW), lds, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_block(const StratArgs& a, int jp, int bf, size_t lds, hipStream_t st)
+hipError_t launch_block(const StratArgs& a, int jp, int bf, int nw, size_t lds, hipStream_t st)
 {
-#define CALL_B(J) (bf ? launch_block_t<J, true>(a, lds, st) : launch_block_t<J, false>(a, lds, st))
+#define CALL_B(J) SNECT_VARIANT(launch_block_t, J, a, lds, st)
     SNECT_JP_SWITCH(jp, CALL_B)
 #undef CALL_B
 }
@@ -1467,24 +1527,39 @@ hipError_t launch_permute(const float* src, float* dst, const int32_t* perm, int
     return hipGetLastError();
 }
 
-template <int JP, bool BF>
+template <int JP, bool BF, int NW>
 static hipError_t prepare_strata_t(size_t slds)
 {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&strata_persistent<JP, BF>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&strata_persistent<JP, BF, NW>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&block_step<JP, BF>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&block_step<JP, BF, NW>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds);
     return e;
 }
 
+hipError_t prepare_sweep(int bf, size_t lds)
+{
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(bf ? reinterpret_cast<const void*>(&strata_sweep<true>)
+                                  : reinterpret_cast<const void*>(&strata_sweep<false>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t prepare_strata(int jp, int bf, int nw, size_t slds)
+{
+    if (slds <= 65536) return hipSuccess;
+#define CALL_S(J) SNECT_VARIANT(prepare_strata_t, J, slds)
+    SNECT_JP_SWITCH(jp, CALL_S)
+#undef CALL_S
+}
+
 template <int JP>
-static hipError_t prepare_t(int bf, size_t slds, size_t llds, size_t clds)
+static hipError_t prepare_t(size_t llds, size_t clds)
 {
     hipError_t e = hipSuccess;
     const int limit = 65536;
-    if (slds > (size_t)limit) e = bf ? prepare_strata_t<JP, true>(slds) : prepare_strata_t<JP, false>(slds);
-    if (e == hipSuccess && llds > (size_t)limit)
+    if (llds > (size_t)limit)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&loss_blocks<JP>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)llds);
     if (e == hipSuccess && clds > (size_t)limit)
@@ -1493,20 +1568,20 @@ static hipError_t prepare_t(int bf, size_t slds, size_t llds, size_t clds)
     return e;
 }
 
-hipError_t prepare_kernels(int jp, int bf, size_t slds, size_t llds, size_t clds)
+hipError_t prepare_kernels(int jp, size_t llds, size_t clds)
 {
-#define CALL_R(J) prepare_t<J>(bf, slds, llds, clds)
+#define CALL_R(J) prepare_t<J>(llds, clds)
     SNECT_JP_SWITCH(jp, CALL_R)
 #undef CALL_R
 }
 
-template <int JP, bool BF>
+template <int JP, bool BF, int NW>
 static int capacity_t(size_t lds)
 {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
-                                                     reinterpret_cast<const void*>(&strata_persistent<JP, BF>),
-                                                     strat_threads(JP), lds) != hipSuccess) {
+                                                     reinterpret_cast<const void*>(&strata_persistent<JP, BF, NW>),
+                                                     64 * NW, lds) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
@@ -1516,9 +1591,24 @@ static int capacity_t(size_t lds)
     return per_cu * cus;
 }
 
-int persistent_capacity(int jp, int bf, size_t lds)
+int sweep_capacity(int bf, size_t lds)
 {
-#define CALL_C(J) (bf ? capacity_t<J, true>(lds) : capacity_t<J, false>(lds))
+    int per_cu = 0;
+    const void* fn = bf ? reinterpret_cast<const void*>(&strata_sweep<true>)
+                        : reinterpret_cast<const void*>(&strata_sweep<false>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kDefaultWaves, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return per_cu * cus;
+}
+
+int persistent_capacity(int jp, int bf, int nw, size_t lds)
+{
+#define CALL_C(J) SNECT_VARIANT(capacity_t, J, lds)
     SNECT_JP_SWITCH(jp, CALL_C)
 #undef CALL_C
 }

@@ -39,3 +39,30 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.snect_problem_info(None, None) == -1
     assert lib.snect_train(None, None, 0, 1, None, None) == -1
     assert lib.snect_last_error(None) == b"null context"
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct of the header has the size and field offsets the Python
+    binding uses (checked with the host C compiler)."""
+    import paper_1711_08095_amd as sn
+    pairs = {"snect_tensor": sn.Tensor, "snect_graph": sn.Graph, "snect_params": sn.Params,
+             "snect_factors": sn.Factors, "snect_info": sn.Info, "snect_exec": sn.Exec,
+             "snect_server_config": sn.ServerConfig}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "snect.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            cf = "lambda" if fname == "lambda_" else fname
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {cf}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
