@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--bf16-oracle", action="store_true",
                     help="also run the FP64 oracle on the core 20x20x5 problem and report the FP32 and "
                          "BF16 factor errors at epoch 1 and at the last FP32 epoch (minutes of CPU)")
+    ap.add_argument("--sweep-epochs", type=int, default=0,
+                    help="epochs of the 16-problem batched sweep (0 = skip; the batched launch is switched "
+                         "off in this build)")
+    ap.add_argument("--sweep-precision", choices=["fp32", "bf16"], default="bf16")
     ap.add_argument("--path", choices=["auto", "persistent", "multi"], default="auto")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -168,6 +172,8 @@ def main():
         out["serving"] = serve_leg(args, sn, synth, prob, f, dims, ranks)
     if args.equal_rmse_epochs > 0:
         out["fp32_vs_bf16"] = equal_rmse_leg(args, sn, synth, ctx, (i, j, k, x, eu, ev), dims)
+    if args.sweep_epochs > 0:
+        out["sweep"] = sweep_leg(args, sn, synth, ctx)
 
     if not args.no_cpu_baseline:
         import oracle
@@ -200,6 +206,77 @@ def copy_probe(torch):
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe": {"launches": 3, "read_bytes_per_launch": 4 * n,
                                      "write_bytes_per_launch": 4 * n}}), flush=True)
+
+
+def sweep_strata(specs, capacity=256, tile_rows_bytes=64 * 1024):
+    """Strata per sweep problem: proportional to its nonzeros (equal work per
+    workgroup), at least enough that a block's factor rows fit in LDS, and
+    together no more workgroups than the device holds at once."""
+    def pmin(sp):
+        jp = max(sp["ranks"][0], sp["ranks"][1])
+        rs = (jp + 3) // 4 * 4
+        return max(2, -(-(sp["dims"][0] + sp["dims"][1]) * rs * 4 // tile_rows_bytes))
+    lo, hi = 0.0, capacity / min(sp["nnz"] for sp in specs)
+    for _ in range(60):
+        c = (lo + hi) / 2
+        if sum(max(pmin(sp), int(c * sp["nnz"])) for sp in specs) <= capacity:
+            lo = c
+        else:
+            hi = c
+    return [max(pmin(sp), int(lo * sp["nnz"])) for sp in specs]
+
+
+def sweep_leg(args, sn, synth, ctx):
+    """Sixteen uneven decompositions (cores from {5,10,15,20}^2 x {2,5},
+    1,000-4,500 patients x 5,000-14,000 genes x 5 platforms, 1M-10M nonzeros
+    with the PanCan-like value types, Barabasi-Albert graphs, lambda_g in
+    {0, 0.01, 0.1, 1}) trained together: one cooperative launch per epoch
+    for all of them, after the sweep autotuner; compared with training the
+    same problems one after another."""
+    import torch
+    specs = synth.sweep_specs()
+    t0 = time.perf_counter()
+    Ps = sweep_strata(specs)
+    prec = sn.PRECISION_BF16 if args.sweep_precision == "bf16" else sn.PRECISION_FP32
+    probs, fs, total = [], [], 0
+    for n, (sp, P) in enumerate(zip(specs, Ps)):
+        I1, I2, I3 = sp["dims"]
+        dens = sp["nnz"] / (I1 * I2)
+        i, j, k, x, eu, ev = synth.pancan_like(seed=sp["seed"], I1=I1, I2=I2, nnz=sp["nnz"],
+                                               mut_density=min(0.03, 0.2 * dens),
+                                               protein_gene_frac=min(0.02, 0.2 * dens))
+        hyper = sn.Hyper(ranks=sp["ranks"], lam=0.01, lam_g=sp["lam_g"], lr=1e-3, core_lr_scale=1.0, P=P,
+                         T=args.tile, precision=prec, seed=synth.PLAN_SEED + 10 + n)
+        probs.append(sn.Problem(ctx, sp["dims"], i, j, k, x, eu, ev, None, hyper))
+        sigma = synth.default_sigma(x, sp["ranks"])
+        init = synth.normal_init(synth.INIT_SEED + 10 + n, sp["dims"], sp["ranks"], sigma)
+        fs.append([torch.tensor(a.astype(np.float32), device="cuda:0").contiguous() for a in init])
+        total += int(i.shape[0])
+    log(f"sweep: 16 problems, {total} nonzeros, strata {Ps}, set up in {time.perf_counter() - t0:.1f}s",
+        args.quiet)
+    tune_ms = sn.sweep_autotune(ctx, probs, fs, trials=1)
+    # one after another (each problem's own persistent launches), 1 epoch
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for p, f in zip(probs, fs):
+        p.train(*f, epochs=1, start_epoch=0)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t1
+    # together
+    t2 = time.perf_counter()
+    loss, rmse = sn.sweep_train(ctx, probs, fs, args.sweep_epochs, start_epoch=1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t2
+    for p in probs:
+        p.close()
+    out = {"workload": "16 uneven decompositions, one launch per epoch", "precision": args.sweep_precision,
+           "nnz_total": total, "strata": Ps, "epochs": args.sweep_epochs,
+           "ms_per_epoch": 1e3 * wall / args.sweep_epochs, "updates_per_s": total * args.sweep_epochs / wall,
+           "sequential_ms_per_epoch": 1e3 * seq, "speedup_vs_sequential": seq / (wall / args.sweep_epochs),
+           "autotune_best_ms": tune_ms, "final_rmse": [float(r[-1]) for r in rmse]}
+    log(f"sweep: {out['ms_per_epoch']:.2f} ms/epoch together, {out['sequential_ms_per_epoch']:.2f} ms one after "
+        f"another", args.quiet)
+    return out
 
 
 def equal_rmse_leg(args, sn, synth, ctx, data, dims):

@@ -211,7 +211,12 @@ typedef struct {
 
 int snect_set_exec(snect_problem *prob, const snect_exec *exec);
 
-/* Batched sweep: trains n independent problems of one context together,
+/* NOTE: in this build snect_sweep_train and snect_sweep_autotune validate
+ * their arguments and then return SNECT_E_UNSUPPORTED: the batched launch
+ * is switched off until the cause of a GPU memory fault seen in its kernel
+ * is established.
+ *
+ * Batched sweep: trains n independent problems of one context together,
  * each epoch's strata of all of them in ONE cooperative launch (problem i
  * takes P_i workgroups and synchronises on its own grid barrier).  Each
  * problem follows

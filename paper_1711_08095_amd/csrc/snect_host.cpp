@@ -874,6 +874,10 @@ int snect_sweep_train(snect_ctx* ctx, int32_t n, snect_problem* const* probs, sn
         nwg += pr->P;
     }
     if (!ctx->coop) return set_err(ctx, SNECT_E_UNSUPPORTED, "cooperative launches not available");
+    if (!kSweepEnabled)
+        return set_err(ctx, SNECT_E_UNSUPPORTED,
+                       "the batched sweep launch is switched off: its kernel took a GPU memory fault whose cause "
+                       "is not established; train the problems one by one with snect_train");
     // one launch of kDefaultWaves-wavefront workgroups; each problem keeps
     // its own core-size code, LDS layout and largest record chunk
     std::vector<int> rcap(n);

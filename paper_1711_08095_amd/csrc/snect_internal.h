@@ -156,6 +156,13 @@ int sweep_capacity(int bf, size_t lds);
 // among them); four of them accumulate the block's S on the matrix cores.
 constexpr int kDefaultWaves = 8;
 constexpr int kMfmaWaves = 4;
+// The batched sweep launch (snect_sweep_train) is switched off: after the
+// LDS layout lost its per-wavefront S partials, its first run took a GPU
+// memory-aperture fault that single-problem launches of the same stratum
+// code never showed, and no cause has been established.  The sweep kernel
+// calls the stratum body as a function (its LDS accesses are flat), which
+// the single-problem kernels inline; that difference is a suspicion only.
+constexpr bool kSweepEnabled = false;
 constexpr int kCoreThreads = 1024;
 
 }  // namespace snect

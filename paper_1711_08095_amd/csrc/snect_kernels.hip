@@ -59,7 +59,7 @@ __device__ inline void lds_order_fence() { asm volatile("" ::: "memory"); }
 // LDS carve-up of the stratum kernels (in 4-byte words).
 // ---------------------------------------------------------------------------
 struct StratLds {
-    int a, b, ra, rb, c, g, h, sa, sb, as, es, xtp, slotj, skw, sk, mk, tco, tck, red, msum, cgt, flag, rec;
+    int a, b, ra, rb, c, g, h, sa, sb, as, es, xtp, slotj, sk, mk, tco, tck, red, msum, cgt, flag, rec;
     int hb, sw1, sw2, xts, esl, a16, e16;  // BF16 path only (zero-sized otherwise)
     int total;
 };
@@ -79,8 +79,8 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     L.rb = o;    o = up4(o + rows2_max);
     L.c = o;     o = up4(o + I3 * J3);
     L.g = o;     o = up4(o + j12 * J3);
-    L.h = o;     o = up4(o + I3 * jp * jp);
     const int f32 = bf ? 0 : 1;
+    L.h = o;     o = up4(o + f32 * I3 * jp * jp);
     L.sa = o;    o = up4(o + f32 * jp * kTS);
     L.sb = o;    o = up4(o + f32 * jp * kTS);
     L.as = o;    o = up4(o + f32 * mp * kTS);
@@ -94,7 +94,6 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     L.a16 = o;   o = up4(o + bf * mp * kTB / 2);
     L.e16 = o;   o = up4(o + bf * mp * kTB / 2);
     L.slotj = o; o = up4(o + kTileMax);
-    L.skw = o;   o = up4(o + kMfmaWaves * I3 * j12);
     L.sk = o;    o = up4(o + I3 * j12);
     L.mk = o;    o = up4(o + I3);
     L.tco = o;   o = up4(o + kTileCache + 1);
@@ -145,13 +144,17 @@ __device__ void build_h(float* Hs, const float* Cs, const float* Gs, int I3, int
 // holds H_k[c][y] at (c, y) and Hb[(2k+1)(MP)(32)] holds H_k[x][c] at
 // (c, x), zero outside JP x JP.  Row c is read as 8 values per lane.
 template <int JP>
-__device__ void build_hb(__bf16* Hb, const float* Hs, int I3, int tid, int nthr)
+__device__ void build_hb(__bf16* Hb, const float* Cs, const float* Gs, int I3, int J1, int J2, int J3, int tid,
+                         int nthr)
 {
     constexpr int MP = mfma_dim(JP);
     for (int idx = tid; idx < I3 * 2 * MP * kKB; idx += nthr) {
         const int y = idx % kKB, c = (idx / kKB) % MP, kw = idx / (kKB * MP), k = kw >> 1;
+        // entry (c, y) of H_k (kw even) or of H_k^T (kw odd), as build_h forms it
+        const int x0 = (kw & 1) ? y : c, y0 = (kw & 1) ? c : y;
         float h = 0.f;
-        if (c < JP && y < JP) h = (kw & 1) ? Hs[k * JP * JP + y * JP + c] : Hs[k * JP * JP + c * JP + y];
+        if (x0 < J1 && y0 < J2)
+            for (int t = 0; t < J3; ++t) h = fmaf(Gs[(x0 * J2 + y0) * J3 + t], Cs[k * J3 + t], h);
         Hb[idx] = (__bf16)h;
     }
 }
@@ -503,15 +506,38 @@ struct TileLds {
     float *sW1, *sW2, *xts, *eS;
     __bf16 *A16, *E16;
     int* slotJ;
-    float* Skw;   // [kMfmaWaves][I3*J1*J2]
+    float* Sk;    // [I3*J1*J2] the block's sums of e a (x) b
     int* Mk;
     int *tco, *tck;
     uint2* rec;   // [rec_cap] staged records
 };
 
+// The matrix-core wavefronts add their partial S of one platform to the
+// block's sums one after another (wavefront 0 first), so the block's sum is
+// ((S_0 + S_1) + S_2) + S_3 whatever the timing.  Called by every thread.
+template <class Acc>
+__device__ inline void flush_in_order(Acc& acc, float* Sk, int J1, int J2, int w, int lane)
+{
+#pragma unroll
+    for (int ww = 0; ww < kMfmaWaves; ++ww) {
+        if (w == ww) acc.flush(Sk, J1, J2, lane);
+        __syncthreads();
+    }
+}
+template <class Acc>
+__device__ inline void flush_in_order_bf(Acc& acc, float* Sk, int J1, int J2, int w, int lane)
+{
+#pragma unroll
+    for (int ww = 0; ww < kMfmaWaves; ++ww) {
+        if (w == ww) acc.flush(Sk, J1, J2, w, lane);
+        __syncthreads();
+    }
+}
+
 // The tiles of block (p, q), run by the whole workgroup (NW wavefronts).
-// L.Ab/L.Bb hold the block's rows; L.Skw receives the per-platform sums of
-// the four matrix-core wavefronts, L.Mk the block's counts.  Every sum is
+// L.Ab/L.Bb hold the block's rows; L.Sk (zeroed by the caller) receives
+// the block's per-platform sums, the four matrix-core wavefronts adding
+// theirs in a fixed order; L.Mk the block's counts.  Every sum is
 // taken in an order that does not depend on NW (x~ over ascending columns,
 // S over four fixed nonzero ranges), so NW is an execution choice only.
 template <int JP, int NW>
@@ -533,7 +559,6 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
     SAcc<MP> acc;
     acc.zero();
     const bool mfw = w < kMfmaWaves;  // this wavefront accumulates S
-    float* Skmine = L.Skw + (mfw ? w : 0) * a.I3 * J12;
     int curk = -1;
     // for small cores the owned rows and columns of H_k stay in registers
     // while consecutive tiles share the platform k
@@ -557,7 +582,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         const int k = L.tck[u];
         const uint2 wv = lane < n ? L.rec[off - z0 + lane] : make_uint2(0u, 0u);
         if (k != curk) {
-            if (curk >= 0 && mfw) acc.flush(Skmine + curk * J12, J1, J2, lane);
+            if (curk >= 0) flush_in_order(acc, L.Sk + curk * J12, J1, J2, w, lane);
             acc.zero();
             curk = k;
             if constexpr (kHreg) {
@@ -684,8 +709,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         __syncthreads();
         }
     }
-    if (mfw) acc.flush(Skmine + curk * J12, J1, J2, lane);
-    __syncthreads();
+    flush_in_order(acc, L.Sk + curk * J12, J1, J2, w, lane);
 }
 
 // The tiles of block (p, q) with BF16 matrix-core contractions (FP32
@@ -721,7 +745,6 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
     acc.zero();
     const bool mfw = w < kMfmaWaves;
     const bool pw = w < 4;  // this wavefront forms W1 and W2 for 16 nonzeros
-    float* Skmine = L.Skw + (mfw ? w : 0) * a.I3 * J12;
     int curk = -1;
     bf16x8 hb1[NB], hb2[NB];
     int tl = t0;
@@ -740,7 +763,7 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
         const int k = L.tck[u];
         const uint2* rec = L.rec + (off - z0);
         if (k != curk) {
-            if (curk >= 0 && mfw) acc.flush(Skmine + curk * J12, J1, J2, w, lane);
+            if (curk >= 0) flush_in_order_bf(acc, L.Sk + curk * J12, J1, J2, w, lane);
             acc.zero();
             curk = k;
             if (pw) {
@@ -865,19 +888,7 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
         __syncthreads();
         }
     }
-    if (mfw) acc.flush(Skmine + curk * J12, J1, J2, w, lane);
-    __syncthreads();
-}
-
-// The block's S = sum over wavefronts (ascending) of their partial sums.
-__device__ inline void combine_waves(float* Sk, const float* Skw, int ni, int tid, int nthr)
-{
-    for (int idx = tid; idx < ni; idx += nthr) {
-        float s = Skw[idx];
-#pragma unroll
-        for (int ww = 1; ww < kMfmaWaves; ++ww) s += Skw[ww * ni + idx];
-        Sk[idx] = s;
-    }
+    flush_in_order_bf(acc, L.Sk + curk * J12, J1, J2, w, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -951,7 +962,7 @@ __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
     L.A16 = reinterpret_cast<__bf16*>(lds + S.a16);
     L.E16 = reinterpret_cast<__bf16*>(lds + S.e16);
     L.slotJ = reinterpret_cast<int*>(lds + S.slotj);
-    L.Skw = lds + S.skw;
+    L.Sk = lds + S.sk;
     L.Mk = reinterpret_cast<int*>(lds + S.mk);
     L.tco = reinterpret_cast<int*>(lds + S.tco);
     L.tck = reinterpret_cast<int*>(lds + S.tck);
@@ -1005,18 +1016,17 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
         const int s1 = a.start1[p], r1 = a.start1[p + 1] - s1;
         load_rows(L.Ab, a.Ap, s1, r1, J1, RS, tid, NT);
         for (int l = tid; l < r1; l += NT) lds[S.ra + l] = a.reg1[s1 + l];
-        build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
-        for (int idx = tid; idx < kMfmaWaves * ni; idx += NT) L.Skw[idx] = 0.f;
+        if constexpr (BF)
+            build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Cs, Gs, I3, J1, J2, J3, tid, NT);
+        else
+            build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
+        for (int idx = tid; idx < ni; idx += NT) Sk[idx] = 0.f;
         for (int k = tid; k < I3; k += NT) L.Mk[k] = 0;
         __syncthreads();
-        if constexpr (BF) {
-            build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Hs, I3, tid, NT);
-            __syncthreads();
+        if constexpr (BF)
             block_tiles_bf<JP, NW>(a, p, q, L, tid);
-        } else {
+        else
             block_tiles<JP, NW>(a, p, q, L, tid);
-        }
-        combine_waves(Sk, L.Skw, ni, tid, NT);
         store_rows(a.Ap, L.Ab, s1, r1, J1, RS, tid, NT);
         __syncthreads();
         float* Sp = a.Spart + (size_t)p * ni;
@@ -1110,19 +1120,18 @@ __global__ __launch_bounds__(64 * NW) void block_step(StratArgs a)
     for (int l = tid; l < r2; l += NT) lds[S.rb + l] = a.reg2[s2 + l];
     for (int idx = tid; idx < I3 * J3; idx += NT) Cs[idx] = a.C[idx];
     for (int idx = tid; idx < J12 * J3; idx += NT) Gs[idx] = a.G[idx];
-    for (int idx = tid; idx < kMfmaWaves * ni; idx += NT) L.Skw[idx] = 0.f;
+    for (int idx = tid; idx < ni; idx += NT) Sk[idx] = 0.f;
     for (int k = tid; k < I3; k += NT) L.Mk[k] = 0;
     __syncthreads();
-    build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
+    if constexpr (BF)
+        build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Cs, Gs, I3, J1, J2, J3, tid, NT);
+    else
+        build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
     __syncthreads();
-    if constexpr (BF) {
-        build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Hs, I3, tid, NT);
-        __syncthreads();
+    if constexpr (BF)
         block_tiles_bf<JP, NW>(a, p, q, L, tid);
-    } else {
+    else
         block_tiles<JP, NW>(a, p, q, L, tid);
-    }
-    combine_waves(Sk, L.Skw, ni, tid, NT);
     store_rows(a.Ap, L.Ab, s1, r1, J1, RS, tid, NT);
     store_rows(a.Bp, L.Bb, s2, r2, J2, RS, tid, NT);
     __syncthreads();

@@ -77,6 +77,8 @@ def _sweep_cases():
     return out
 
 
+@pytest.mark.skip(reason="batched sweep launch switched off: its first FP32 run after the LDS-layout change "
+                         "took a GPU memory-aperture fault with no established cause; kept off the GPU")
 @pytest.mark.parametrize("precision", [0, 1])
 def test_sweep_equals_individual_training(ctx, precision):
     import paper_1711_08095_amd as sn
@@ -98,6 +100,15 @@ def test_sweep_equals_individual_training(ctx, precision):
     for a, b in zip(fs, fs2):
         for x, y in zip(a, b):
             assert bool((x == y).all())
+
+
+def test_sweep_is_switched_off(ctx):
+    import paper_1711_08095_amd as sn
+    cases = _sweep_cases()[:2]
+    probs = [gpu_problem(ctx, c) for c in cases]
+    with pytest.raises(sn.SnectError) as e:
+        sn.sweep_train(ctx, probs, [gpu_factors(c) for c in cases], 1)
+    assert e.value.code == -9
 
 
 def test_sweep_validation(ctx):
