@@ -11,8 +11,10 @@ reported separately.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -58,6 +60,26 @@ def parse():
                     help="only run a plain elementwise device copy of 1 GiB (x3) and exit; its "
                          "FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures")
     return ap.parse_args()
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "strata_persistent_pancan_25M_hbm_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1711_08095_amd", "csrc", "snect_kernels.hip")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when that
+    summary was taken on another kernel or on other kernel source."""
+    try:
+        text = open(COUNTERS).read()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = dict(re.findall(r"^\s*(traffic_kernel|traffic_bytes_per_launch|kernel_source_sha256):\s*(.+?)\s*$",
+                           text, re.M))
+    if vals.get("kernel_source_sha256") != sha or vals.get("traffic_kernel") != kernel:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def log(msg, quiet=False):
@@ -136,6 +158,12 @@ def main():
     bytes_per_launch = (8.0 * nnz_per_launch + strata_per_launch * 8.0 * I1 * J1 + 8.0 * I2 * J2)
     flops_per_nnz = 6 * J1 * J2 + 4 * (J1 + J2)
     achieved_gbs = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    jp = min(j for j in (2, 4, 5, 8, 10, 12, 16, 20, 24, 32) if j >= max(J1, J2))
+    kernel = (f"strata_persistent<{jp}, {'true' if precision == sn.PRECISION_BF16 else 'false'}, 8>"
+              if persistent else f"block_step<{jp}>")
+    # the counter summary covers the default workload only
+    default_workload = (nnz == 25_000_000 and ranks == (10, 10, 5) and P == 128 and args.tile == 64)
+    traffic = measured_traffic(kernel) if default_workload else None
     achieved_tf = flops_per_nnz * nnz_per_launch / avg_launch_s / 1e12 if avg_launch_s > 0 else 0.0
 
     out = {
@@ -156,8 +184,8 @@ def main():
                    "graph": "barabasi-albert m=10", "edges": int(eu.shape[0]),
                    "lambda": 0.01, "lambda_g": 0.1, "lr": 1e-3},
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": ("strata_persistent" if persistent else "block_step") + f"<JP={max(J1, J2)}>",
+                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": kernel,
                      "avg_launch_us": avg_launch_s * 1e6, "bytes_per_launch": bytes_per_launch,
                      "alu_tflops": achieved_tf, "alu_frac": achieved_tf / FP32_VECTOR_PEAK_TFLOPS},
         "phases_ms_per_step": {"graph": tm["graph_ms"] / args.steps,
