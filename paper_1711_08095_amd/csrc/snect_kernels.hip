@@ -59,7 +59,7 @@ __device__ inline void lds_order_fence() { asm volatile("" ::: "memory"); }
 // LDS carve-up of the stratum kernels (in 4-byte words).
 // ---------------------------------------------------------------------------
 struct StratLds {
-    int a, b, ra, rb, c, g, h, sa, sb, as, es, xtp, slotj, sk, mk, tco, tck, red, msum, cgt, flag, rec;
+    int a, b, ra, rb, c, g, h, sa, sb, as, es, xtp, slotj, stg, sk, mk, tco, tck, red, msum, cgt, flag, rec;
     int hb, sw1, sw2, xts, esl, a16, e16;  // BF16 path only (zero-sized otherwise)
     int total;
 };
@@ -94,6 +94,7 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     L.a16 = o;   o = up4(o + bf * mp * kTB / 2);
     L.e16 = o;   o = up4(o + bf * mp * kTB / 2);
     L.slotj = o; o = up4(o + kTileMax);
+    L.stg = o;   o = up4(o + kMfmaWaves * j12);
     L.sk = o;    o = up4(o + I3 * j12);
     L.mk = o;    o = up4(o + I3);
     L.tco = o;   o = up4(o + kTileCache + 1);
@@ -278,13 +279,13 @@ template <> struct SAcc<16> {
         }
     }
     // output element (row 4*(l/16)+r, column l%16) sits in register r of lane l
-    __device__ void flush(float* Sk, int J1, int J2, int lane)
+    __device__ void store(float* St, int J1, int J2, int lane)
     {
         const int col = lane & 15, rb = (lane >> 4) * 4;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = rb + r;
-            if (row < J1 && col < J2) Sk[row * J2 + col] += v[r];
+            if (row < J1 && col < J2) St[row * J2 + col] = v[r];
         }
     }
 };
@@ -310,13 +311,13 @@ template <> struct SAcc<32> {
         }
     }
     // output element (row 8*(r/4) + 4*(l/32) + r%4, column l%32) in register r
-    __device__ void flush(float* Sk, int J1, int J2, int lane)
+    __device__ void store(float* St, int J1, int J2, int lane)
     {
         const int col = lane & 31, rb = (lane >> 5) * 4;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int row = (r >> 2) * 8 + rb + (r & 3);
-            if (row < J1 && col < J2) Sk[row * J2 + col] += v[r];
+            if (row < J1 && col < J2) St[row * J2 + col] = v[r];
         }
     }
 };
@@ -342,14 +343,14 @@ template <int MP> struct SAccB {
         }
     }
     // output element (row mb*16 + 4*(l/16) + r, column nb*16 + l%16) in register r
-    __device__ void flush(float* Sk, int J1, int J2, int w, int lane)
+    __device__ void store(float* St, int J1, int J2, int w, int lane)
     {
         const int mb = MP == 32 ? (w >> 1) : 0, nb = MP == 32 ? (w & 1) : 0;
         const int col = nb * 16 + (lane & 15), rb = mb * 16 + (lane >> 4) * 4;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = rb + r;
-            if (row < J1 && col < J2) Sk[row * J2 + col] += v[r];
+            if (row < J1 && col < J2) St[row * J2 + col] = v[r];
         }
     }
 };
@@ -507,37 +508,45 @@ struct TileLds {
     __bf16 *A16, *E16;
     int* slotJ;
     float* Sk;    // [I3*J1*J2] the block's sums of e a (x) b
+    float* St;    // [kMfmaWaves][J1*J2] staged partial sums of one platform
     int* Mk;
     int *tco, *tck;
     uint2* rec;   // [rec_cap] staged records
 };
 
-// The matrix-core wavefronts add their partial S of one platform to the
-// block's sums one after another (wavefront 0 first), so the block's sum is
-// ((S_0 + S_1) + S_2) + S_3 whatever the timing.  Called by every thread.
-template <class Acc>
-__device__ inline void flush_in_order(Acc& acc, float* Sk, int J1, int J2, int w, int lane)
+// The block's S of one platform is staged: each matrix-core wavefront
+// stores its partial sums (St, kMfmaWaves x J1J2), and after the next
+// workgroup barrier every thread adds them up, wavefront 0 first, so the
+// block's sum is ((S_0 + S_1) + S_2) + S_3 whatever the timing.  covers()
+// names the wavefronts that produce entry (row, col): all four in the FP32
+// step (each over a quarter of the nonzeros); in the BF16 step the owner of
+// the entry's 16x16 block (MP = 32) or wavefronts 0 and 1 (MP = 16).
+template <bool BF, int MP>
+__device__ inline bool covers(int w, int row, int col)
 {
-#pragma unroll
-    for (int ww = 0; ww < kMfmaWaves; ++ww) {
-        if (w == ww) acc.flush(Sk, J1, J2, lane);
-        __syncthreads();
-    }
+    if (!BF) return true;
+    if (MP == 32) return w == 2 * (row >> 4) + (col >> 4);
+    return w < 2;
 }
-template <class Acc>
-__device__ inline void flush_in_order_bf(Acc& acc, float* Sk, int J1, int J2, int w, int lane)
+
+template <bool BF, int MP>
+__device__ inline void stage_sum(const float* St, float* Skk, int J1, int J2, int tid, int nthr)
 {
+    const int J12 = J1 * J2;
+    for (int e = tid; e < J12; e += nthr) {
+        const int row = e / J2, col = e - row * J2;
+        float sum = 0.f;
 #pragma unroll
-    for (int ww = 0; ww < kMfmaWaves; ++ww) {
-        if (w == ww) acc.flush(Sk, J1, J2, w, lane);
-        __syncthreads();
+        for (int ww = 0; ww < kMfmaWaves; ++ww)
+            if (covers<BF, MP>(ww, row, col)) sum += St[ww * J12 + e];
+        Skk[e] = sum;
     }
 }
 
 // The tiles of block (p, q), run by the whole workgroup (NW wavefronts).
 // L.Ab/L.Bb hold the block's rows; L.Sk (zeroed by the caller) receives
-// the block's per-platform sums, the four matrix-core wavefronts adding
-// theirs in a fixed order; L.Mk the block's counts.  Every sum is
+// the block's per-platform sums through the staged partials of the four
+// matrix-core wavefronts; L.Mk the block's counts.  Every sum is
 // taken in an order that does not depend on NW (x~ over ascending columns,
 // S over four fixed nonzero ranges), so NW is an execution choice only.
 template <int JP, int NW>
@@ -560,6 +569,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
     acc.zero();
     const bool mfw = w < kMfmaWaves;  // this wavefront accumulates S
     int curk = -1;
+    int pend = -1;  // platform whose partial S waits in L.St
     // for small cores the owned rows and columns of H_k stay in registers
     // while consecutive tiles share the platform k
     constexpr bool kHreg = JP <= 12;
@@ -582,7 +592,10 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         const int k = L.tck[u];
         const uint2 wv = lane < n ? L.rec[off - z0 + lane] : make_uint2(0u, 0u);
         if (k != curk) {
-            if (curk >= 0) flush_in_order(acc, L.Sk + curk * J12, J1, J2, w, lane);
+            if (curk >= 0) {
+                if (mfw) acc.store(L.St + w * J12, J1, J2, lane);
+                pend = curk;
+            }
             acc.zero();
             curk = k;
             if constexpr (kHreg) {
@@ -639,6 +652,10 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
             if constexpr (JP > 16) lds_order_fence();
         }
         __syncthreads();
+        if (pend >= 0) {
+            stage_sum<false, MP>(L.St, L.Sk + pend * J12, J1, J2, tid, NT);
+            pend = -1;
+        }
 
         // 2. residual (x~ summed over ascending columns); stage row terms
         //    and matrix-core operands
@@ -709,7 +726,10 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         __syncthreads();
         }
     }
-    flush_in_order(acc, L.Sk + curk * J12, J1, J2, w, lane);
+    if (mfw) acc.store(L.St + w * J12, J1, J2, lane);
+    __syncthreads();
+    stage_sum<false, MP>(L.St, L.Sk + curk * J12, J1, J2, tid, NT);
+    __syncthreads();
 }
 
 // The tiles of block (p, q) with BF16 matrix-core contractions (FP32
@@ -746,6 +766,7 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
     const bool mfw = w < kMfmaWaves;
     const bool pw = w < 4;  // this wavefront forms W1 and W2 for 16 nonzeros
     int curk = -1;
+    int pend = -1;  // platform whose partial S waits in L.St
     bf16x8 hb1[NB], hb2[NB];
     int tl = t0;
     while (tl < t1) {
@@ -763,7 +784,10 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
         const int k = L.tck[u];
         const uint2* rec = L.rec + (off - z0);
         if (k != curk) {
-            if (curk >= 0) flush_in_order_bf(acc, L.Sk + curk * J12, J1, J2, w, lane);
+            if (curk >= 0) {
+                if (mfw) acc.store(L.St + w * J12, J1, J2, w, lane);
+                pend = curk;
+            }
             acc.zero();
             curk = k;
             if (pw) {
@@ -814,6 +838,10 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
             }
         }
         __syncthreads();
+        if (pend >= 0) {
+            stage_sum<true, MP>(L.St, L.Sk + pend * J12, J1, J2, tid, NT);
+            pend = -1;
+        }
 
         // 2. residual; owned columns of a_i before the tile; BF16 S operands
         const bool act = lane < n;
@@ -888,7 +916,10 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
         __syncthreads();
         }
     }
-    flush_in_order_bf(acc, L.Sk + curk * J12, J1, J2, w, lane);
+    if (mfw) acc.store(L.St + w * J12, J1, J2, w, lane);
+    __syncthreads();
+    stage_sum<true, MP>(L.St, L.Sk + curk * J12, J1, J2, tid, NT);
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -963,6 +994,7 @@ __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
     L.E16 = reinterpret_cast<__bf16*>(lds + S.e16);
     L.slotJ = reinterpret_cast<int*>(lds + S.slotj);
     L.Sk = lds + S.sk;
+    L.St = lds + S.stg;
     L.Mk = reinterpret_cast<int*>(lds + S.mk);
     L.tco = reinterpret_cast<int*>(lds + S.tco);
     L.tck = reinterpret_cast<int*>(lds + S.tck);
@@ -1014,8 +1046,10 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
         const int s = a.order[si];
         const int p = (q - s + P) % P;
         const int s1 = a.start1[p], r1 = a.start1[p + 1] - s1;
-        load_rows(L.Ab, a.Ap, s1, r1, J1, RS, tid, NT);
-        for (int l = tid; l < r1; l += NT) lds[S.ra + l] = a.reg1[s1 + l];
+        if (si == 0) {  // later strata load their patient rows during the previous reduction
+            load_rows(L.Ab, a.Ap, s1, r1, J1, RS, tid, NT);
+            for (int l = tid; l < r1; l += NT) lds[S.ra + l] = a.reg1[s1 + l];
+        }
         if constexpr (BF)
             build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Cs, Gs, I3, J1, J2, J3, tid, NT);
         else
@@ -1034,6 +1068,14 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
         for (int k = tid; k < I3; k += NT) a.Mpart[p * I3 + k] = L.Mk[k];
         if (!grid_sync(a.bar, P, nbar, flag)) return;
 
+        // every block of this stratum has stored its rows: the next
+        // stratum's patient rows are final and load while the sums reduce
+        if (si + 1 < P) {
+            const int pn = (q - a.order[si + 1] + P) % P;
+            const int s1n = a.start1[pn], r1n = a.start1[pn + 1] - s1n;
+            load_rows(L.Ab, a.Ap, s1n, r1n, J1, RS, tid, NT);
+            for (int l = tid; l < r1n; l += NT) lds[S.ra + l] = a.reg1[s1n + l];
+        }
         stratum_counts(a.Mpart, P, I3, L.Mk, msum, tid, NT);
         reduce_items(a.Spart, P, ni, i0, i1, a.Ssum + i0, red, tid, NT);
         if (!grid_sync(a.bar, P, nbar, flag)) return;
