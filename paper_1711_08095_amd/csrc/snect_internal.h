@@ -38,6 +38,11 @@ constexpr int kJpSet[] = {2, 4, 5, 8, 10, 12, 16, 20, 24, 32};
 constexpr int kJpCount = sizeof(kJpSet) / sizeof(kJpSet[0]);
 
 __host__ __device__ constexpr int row_stride(int jp) { return (jp + 3) & ~3; }
+// LDS row stride of the stratum kernels' factor rows: odd in the FP32 step,
+// so that rows gathered by the lanes of a tile fall in different banks; a
+// multiple of four in the BF16 step, whose operands are read 16 bytes at a
+// time.
+__host__ __device__ constexpr int strat_row_stride(int jp, int bf) { return bf ? ((jp + 3) & ~3) : (jp | 1); }
 __host__ __device__ constexpr int mfma_dim(int jp) { return jp <= 16 ? 16 : 32; }
 
 // Grid barrier state of the persistent kernel (zeroed before each launch).

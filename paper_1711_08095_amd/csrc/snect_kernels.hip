@@ -69,7 +69,7 @@ __host__ __device__ inline int up4(int o) { return (o + 3) & ~3; }
 __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2,
                                                      int J3, int rec_cap, int bf, int nw)
 {
-    const int rs = row_stride(jp), mp = mfma_dim(jp), j12 = J1 * J2;
+    const int rs = strat_row_stride(jp, bf), mp = mfma_dim(jp), j12 = J1 * J2;
     const int nch = (j12 + kCoreChunk - 1) / kCoreChunk;
     StratLds L;
     int o = 0;
@@ -552,7 +552,7 @@ __device__ inline void stage_sum(const float* St, float* Skk, int J1, int J2, in
 template <int JP, int NW>
 __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, int tid)
 {
-    constexpr int RS = row_stride(JP);
+    constexpr int RS = strat_row_stride(JP, 0);
     constexpr int MP = mfma_dim(JP);
     constexpr int NT = 64 * NW;
     constexpr int QN = (JP + NW - 1) / NW;  // owned factor columns per wavefront
@@ -747,7 +747,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
 template <int JP, int NW>
 __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& L, int tid)
 {
-    constexpr int RS = row_stride(JP);
+    constexpr int RS = strat_row_stride(JP, 1);
     constexpr int MP = mfma_dim(JP);
     constexpr int NB = MP / 16;
     constexpr int NT = 64 * NW;
@@ -1010,7 +1010,7 @@ __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
 template <int JP, bool BF, int NW>
 __device__ void strata_body(const StratArgs& a, int q, float* lds)
 {
-    constexpr int RS = row_stride(JP);
+    constexpr int RS = strat_row_stride(JP, BF ? 1 : 0);
     constexpr int NT = 64 * NW;
     const int tid = threadIdx.x;
     const int P = a.P, I3 = a.I3, J1 = a.J1, J2 = a.J2, J3 = a.J3, J12 = J1 * J2;
@@ -1026,7 +1026,8 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
     float* cgt = lds + S.cgt;
     int* flag = reinterpret_cast<int*>(lds + S.flag);
 
-    for (int idx = tid; idx < (a.rows1_max + a.rows2_max) * RS; idx += NT) lds[S.a + idx] = 0.f;
+    for (int idx = tid; idx < a.rows1_max * RS; idx += NT) lds[S.a + idx] = 0.f;
+    for (int idx = tid; idx < a.rows2_max * RS; idx += NT) lds[S.b + idx] = 0.f;
     __syncthreads();
     const int s2 = a.start2[q], r2 = a.start2[q + 1] - s2;
     load_rows(L.Bb, a.Bp, s2, r2, J2, RS, tid, NT);
@@ -1139,7 +1140,7 @@ __global__ __launch_bounds__(64 * kDefaultWaves) void strata_sweep(const StratAr
 template <int JP, bool BF, int NW>
 __global__ __launch_bounds__(64 * NW) void block_step(StratArgs a)
 {
-    constexpr int RS = row_stride(JP);
+    constexpr int RS = strat_row_stride(JP, BF ? 1 : 0);
     constexpr int NT = 64 * NW;
     extern __shared__ float lds[];
     const int tid = threadIdx.x;
@@ -1152,7 +1153,8 @@ __global__ __launch_bounds__(64 * NW) void block_step(StratArgs a)
     float* Gs = lds + S.g;
     float* Hs = lds + S.h;
     float* Sk = lds + S.sk;
-    for (int idx = tid; idx < (a.rows1_max + a.rows2_max) * RS; idx += NT) lds[S.a + idx] = 0.f;
+    for (int idx = tid; idx < a.rows1_max * RS; idx += NT) lds[S.a + idx] = 0.f;
+    for (int idx = tid; idx < a.rows2_max * RS; idx += NT) lds[S.b + idx] = 0.f;
     __syncthreads();
     const int s1 = a.start1[p], r1 = a.start1[p + 1] - s1;
     const int s2 = a.start2[q], r2 = a.start2[q + 1] - s2;
