@@ -3,26 +3,31 @@
 // Eq. 3).
 //
 // Factor rows are kept in plan (position) order, so the rows of a block are
-// one contiguous range.  A block (p, q) is processed by one workgroup of four
-// wavefronts: its patient rows and gene rows sit in LDS, H_k = G x3 c_k for
-// every platform k is built in LDS from the stratum's frozen C and G, and
-// each tile (<= 64 nonzeros of one platform) is one step in which lane t of
-// every wavefront stands for nonzero t and wavefront w owns the factor
-// columns c = w, w+4, ...:
+// one contiguous range.  A block (p, q) is processed by one workgroup of NW
+// wavefronts (8 by default, 4 as an execution choice): its patient rows and
+// gene rows sit in LDS, H_k = G x3 c_k for every platform k is built in LDS
+// from the stratum's frozen C and G, and each tile (<= 64 nonzeros of one
+// platform) is one step in which lane t of every wavefront stands for
+// nonzero t and wavefront w owns the factor columns c = w, w+NW, ...:
 //   1. every wavefront reads the tile's rows as they were before the tile;
 //      wavefront w forms w1[x] = (H_k b_j)[x] and w2[y] = (H_k^T a_i)[y] for
-//      its columns and its share of x~ = a_i . w1;
-//   2. after a barrier all wavefronts know e = x - x~; each stages e*w1 (in
-//      tile order), e*w2 (in the tile's gene-sorted slot order) and the
-//      matrix-core operands for its columns;
+//      its columns and stages a_c w1_c per column;
+//   2. after a barrier every lane sums x~ = a_i . w1 over ascending columns
+//      and forms e = x - x~; each wavefront stages e*w1 (in tile order),
+//      e*w2 (in the tile's gene-sorted slot order) and the matrix-core
+//      operands for its columns;
 //   3. after a barrier a segmented wavefront scan sums the terms of every
 //      patient run (contiguous: tiles are sorted by i) and every gene run
 //      (contiguous in slot order) in a fixed tree order; the last lane of a
-//      run writes the row's owned columns; wavefront w also accumulates the
-//      block's sum of e a (x) b over nonzeros 16w..16w+15 on the matrix cores;
+//      run writes the row's owned columns; the last four wavefronts also
+//      accumulate the block's sum of e a (x) b, each over a fixed quarter of
+//      the nonzeros, on the matrix cores;
 //   4. a barrier ends the tile.
-// Staging arrays are column-major with a pitch of 66 words, which keeps the
-// column writes and the matrix-core operand reads free of bank conflicts.
+// Every sum runs in an order fixed by the problem alone, so NW and the other
+// execution choices never change a bit of the result.  Staging arrays are
+// column-major with a pitch of 66 words, which keeps the column writes and
+// the matrix-core operand reads free of bank conflicts; factor rows use an
+// odd stride so that the rows gathered by one tile spread over the banks.
 //
 // Two drivers share that block step and all of the arithmetic:
 //   strata_persistent: one cooperative launch per epoch; P workgroups stay
@@ -267,7 +272,7 @@ template <> struct SAcc<16> {
     __device__ void zero() { v = floatx4{0.f, 0.f, 0.f, 0.f}; }
     // v_mfma_f32_16x16x4f32: step s covers nonzeros 4s..4s+3; lane l supplies
     // A[l%16][l/16] = a_{4s+l/16}[l%16] and B[l/16][l%16] = (e b)_{4s+l/16}[l%16].
-    // Wavefront w takes nonzeros 16w..16w+15, i.e. steps 4w..4w+3.
+    // Matrix-core wavefront w (0..3) takes nonzeros 16w..16w+15, i.e. steps 4w..4w+3.
     __device__ void accumulate(const float* As, const float* Es, int n, int w, int lane)
     {
         const int s_end = (n + 3) >> 2;
@@ -298,7 +303,7 @@ template <> struct SAcc<32> {
         for (int r = 0; r < 16; ++r) v[r] = 0.f;
     }
     // v_mfma_f32_32x32x2f32: step s covers nonzeros 2s, 2s+1; lane l supplies
-    // a_{2s+l/32}[l%32] and (e b)_{2s+l/32}[l%32].  Wavefront w takes steps
+    // a_{2s+l/32}[l%32] and (e b)_{2s+l/32}[l%32].  Matrix-core wavefront w takes steps
     // 8w..8w+7.
     __device__ void accumulate(const float* As, const float* Es, int n, int w, int lane)
     {
@@ -325,8 +330,9 @@ template <> struct SAcc<32> {
 // BF16 matrix-core accumulator of S (v_mfma_f32_16x16x32_bf16): the
 // operands are staged column-major, element (t, c) at c*kTB + t, and lane l
 // supplies rows/columns l%16 with nonzeros 8(l/16) .. 8(l/16)+7 of a 32-wide
-// K step.  MP = 32: wavefront w < 4 owns output block (w/2, w%2) and both K
-// steps; MP = 16: wavefronts 0 and 1 own K step 0 and 1 of the one block.
+// K step.  MP = 32: matrix-core wavefront w (0..3) owns output block
+// (w/2, w%2) and both K steps; MP = 16: matrix-core wavefronts 0 and 1 own
+// K step 0 and 1 of the one block.
 template <int MP> struct SAccB {
     floatx4 v;
     __device__ void zero() { v = floatx4{0.f, 0.f, 0.f, 0.f}; }
@@ -567,7 +573,10 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
 
     SAcc<MP> acc;
     acc.zero();
-    const bool mfw = w < kMfmaWaves;  // this wavefront accumulates S
+    // the last four wavefronts accumulate S (they own the fewest factor
+    // columns); mw numbers them 0..3
+    const int mw = w - (NW - kMfmaWaves);
+    const bool mfw = mw >= 0;
     int curk = -1;
     int pend = -1;  // platform whose partial S waits in L.St
     // for small cores the owned rows and columns of H_k stay in registers
@@ -593,7 +602,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         const uint2 wv = lane < n ? L.rec[off - z0 + lane] : make_uint2(0u, 0u);
         if (k != curk) {
             if (curk >= 0) {
-                if (mfw) acc.store(L.St + w * J12, J1, J2, lane);
+                if (mfw) acc.store(L.St + mw * J12, J1, J2, lane);
                 pend = curk;
             }
             acc.zero();
@@ -687,7 +696,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         __syncthreads();
 
         // 3. matrix-core sums; fixed-order run sums; owned columns of the rows
-        if (mfw) acc.accumulate(L.As, L.Es, n, w, lane);
+        if (mfw) acc.accumulate(L.As, L.Es, n, mw, lane);
         {
             const int il_up = dpp_move_i<kDppWaveShr1>(il), il_dn = dpp_move_i<kDppWaveShl1>(il);
             const bool ifirst = act && (lane == 0 || il_up != il);
@@ -726,7 +735,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         __syncthreads();
         }
     }
-    if (mfw) acc.store(L.St + w * J12, J1, J2, lane);
+    if (mfw) acc.store(L.St + mw * J12, J1, J2, lane);
     __syncthreads();
     stage_sum<false, MP>(L.St, L.Sk + curk * J12, J1, J2, tid, NT);
     __syncthreads();
@@ -734,7 +743,8 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
 
 // The tiles of block (p, q) with BF16 matrix-core contractions (FP32
 // accumulation; factor rows, residuals and updates stay FP32).  Per tile:
-//   1. wavefront w < 4 takes nonzeros 16w..16w+15 as the rows of
+//   1. matrix-core wavefront w (the last four, w = 0..3) takes nonzeros
+//      16w..16w+15 as the rows of
 //      W1 = B_tile H_k^T and W2 = A_tile H_k (BF16 operands, one K step of
 //      32); it writes W1 in tile order and W2 in the tile's gene-sorted slot
 //      order, and x~ = a . w1 for its nonzeros (FP32 row sums);
@@ -763,8 +773,11 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
 
     SAccB<MP> acc;
     acc.zero();
-    const bool mfw = w < kMfmaWaves;
-    const bool pw = w < 4;  // this wavefront forms W1 and W2 for 16 nonzeros
+    // the last four wavefronts (the fewest factor columns) form W1 and W2
+    // for 16 nonzeros each and accumulate S; mw numbers them 0..3
+    const int mw = w - (NW - kMfmaWaves);
+    const bool mfw = mw >= 0;
+    const bool pw = mfw;
     int curk = -1;
     int pend = -1;  // platform whose partial S waits in L.St
     bf16x8 hb1[NB], hb2[NB];
@@ -785,7 +798,7 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
         const uint2* rec = L.rec + (off - z0);
         if (k != curk) {
             if (curk >= 0) {
-                if (mfw) acc.store(L.St + w * J12, J1, J2, w, lane);
+                if (mfw) acc.store(L.St + mw * J12, J1, J2, mw, lane);
                 pend = curk;
             }
             acc.zero();
@@ -801,7 +814,7 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
 
         // 1. W1, W2 and x~ for nonzeros 16w .. 16w+15
         if (pw) {
-            const int to = 16 * w + m;
+            const int to = 16 * mw + m;
             const bool ao = to < n;
             const uint32_t wo = ao ? rec[to].x : 0u;
             const bf16x8 opb = row8_bf16<RS>(L.Bb + ((wo >> sh_j) & mask_j) * RS, 8 * g, ao);
@@ -810,7 +823,7 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
             bool actr[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int tr = 16 * w + 4 * g + r;
+                const int tr = 16 * mw + 4 * g + r;
                 actr[r] = tr < n;
                 const uint32_t wr = actr[r] ? rec[tr].x : 0u;
                 ilr[r] = (int)(wr & mask_i);
@@ -823,7 +836,7 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
                 const floatx4 o1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opb, hb1[nb], zero4, 0, 0, 0);
                 const floatx4 o2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opa, hb2[nb], zero4, 0, 0, 0);
                 const int c = nb * 16 + m;
-                *reinterpret_cast<floatx4*>(L.sW1 + c * kTW + 16 * w + 4 * g) = o1;
+                *reinterpret_cast<floatx4*>(L.sW1 + c * kTW + 16 * mw + 4 * g) = o1;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     if (actr[r]) L.sW2[c * kTW + jrr[r]] = o2[r];
@@ -834,7 +847,7 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
             for (int r = 0; r < 4; ++r) xp[r] = row_sum16(xp[r]);
             if (m < 4) {
                 const float v = m == 0 ? xp[0] : (m == 1 ? xp[1] : (m == 2 ? xp[2] : xp[3]));
-                L.xts[16 * w + 4 * g + m] = v;
+                L.xts[16 * mw + 4 * g + m] = v;
             }
         }
         __syncthreads();
@@ -876,7 +889,7 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
         __syncthreads();
 
         // 3. S on the matrix cores; fixed-order run sums; owned row columns
-        if (mfw) acc.accumulate(L.A16, L.E16, n, w, lane);
+        if (mfw) acc.accumulate(L.A16, L.E16, n, mw, lane);
         {
             const int il_up = dpp_move_i<kDppWaveShr1>(il), il_dn = dpp_move_i<kDppWaveShl1>(il);
             const bool ifirst = act && (lane == 0 || il_up != il);
@@ -916,7 +929,7 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
         __syncthreads();
         }
     }
-    if (mfw) acc.store(L.St + w * J12, J1, J2, w, lane);
+    if (mfw) acc.store(L.St + mw * J12, J1, J2, mw, lane);
     __syncthreads();
     stage_sum<true, MP>(L.St, L.Sk + curk * J12, J1, J2, tid, NT);
     __syncthreads();
