@@ -952,10 +952,14 @@ __device__ bool grid_sync(GridBar* bar, unsigned nblocks, unsigned& nbar, int* f
     if (threadIdx.x == 0) {
         int ok = 1;
         const unsigned target = nblocks * ++nbar;
-        __threadfence();
+        // the release publishes every write the workgroup made before the
+        // barrier above
         __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        // poll with relaxed loads (no cache invalidation per poll: a waiting
+        // workgroup must not keep invalidating the L2 that workgroups still
+        // running tiles share), then acquire once
         unsigned spins = 0;
-        while (__hip_atomic_load(&bar->count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(&bar->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(&bar->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
                 ok = 0;
                 break;
@@ -967,7 +971,7 @@ __device__ bool grid_sync(GridBar* bar, unsigned nblocks, unsigned& nbar, int* f
                 break;
             }
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *flag = ok;
     }
     __syncthreads();
