@@ -55,6 +55,8 @@ def parse():
                          "off in this build)")
     ap.add_argument("--sweep-precision", choices=["fp32", "bf16"], default="bf16")
     ap.add_argument("--path", choices=["auto", "persistent", "multi"], default="auto")
+    ap.add_argument("--waves", type=int, default=0, help="wavefronts per stratum workgroup (0 = default)")
+    ap.add_argument("--rec-cap", type=int, default=0, help="records staged per LDS chunk (0 = largest)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain elementwise device copy of 1 GiB (x3) and exit; its "
@@ -127,7 +129,7 @@ def main():
     if args.warmup > 0:
         prob.train(*f, epochs=args.warmup, start_epoch=0)
     path = {"auto": sn.PATH_AUTO, "persistent": sn.PATH_PERSISTENT, "multi": sn.PATH_MULTI}[args.path]
-    prob.set_exec(per_launch_timing=True, path=path)
+    prob.set_exec(per_launch_timing=True, path=path, waves=args.waves, rec_cap=args.rec_cap)
     chosen = prob.exec_path()
     torch.cuda.synchronize()
     ts = time.perf_counter()
@@ -159,7 +161,8 @@ def main():
     flops_per_nnz = 6 * J1 * J2 + 4 * (J1 + J2)
     achieved_gbs = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
     jp = min(j for j in (2, 4, 5, 8, 10, 12, 16, 20, 24, 32) if j >= max(J1, J2))
-    kernel = (f"strata_persistent<{jp}, {'true' if precision == sn.PRECISION_BF16 else 'false'}, 8>"
+    kernel = (f"strata_persistent<{jp}, {'true' if precision == sn.PRECISION_BF16 else 'false'}, "
+              f"{args.waves or 8}>"
               if persistent else f"block_step<{jp}>")
     # the counter summary covers the default workload only
     default_workload = (nnz == 25_000_000 and ranks == (10, 10, 5) and P == 128 and args.tile == 64)
