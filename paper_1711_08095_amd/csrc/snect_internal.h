@@ -161,6 +161,8 @@ int sweep_capacity(int bf, size_t lds);
 // among them); four of them accumulate the block's S on the matrix cores.
 constexpr int kDefaultWaves = 8;
 constexpr int kMfmaWaves = 4;
+// Workgroups that share one fold-in request's Gram sums (at most).
+constexpr int kServeMaxParts = 256;
 // The batched sweep launch (snect_sweep_train) is switched off: after the
 // LDS layout lost its per-wavefront S partials, its first run took a GPU
 // memory-aperture fault that single-problem launches of the same stratum

@@ -51,7 +51,8 @@ __global__ __launch_bounds__(256) void serve_row_norms(const float* A, int I1, i
 
 constexpr int kFoldBatch = 128;  // nonzeros staged per pass (34 KB of LDS)
 
-// Partial Gram sums: workgroup g takes nonzeros [g*chunk, (g+1)*chunk).
+// Partial Gram sums: workgroup g takes nonzeros [g*chunk, (g+1)*chunk)
+// (at most kServeMaxParts workgroups per request).
 // Entry e < J1(J1+1)/2 is Q[a][b] (a <= b, row-major upper triangle); entry
 // NQ + a is r[a].
 __global__ __launch_bounds__(256) void serve_gram(const int32_t* jj, const int32_t* kk, const float* xx, int n,
@@ -66,12 +67,12 @@ __global__ __launch_bounds__(256) void serve_gram(const int32_t* jj, const int32
     for (int b0 = z0; b0 < z1; b0 += kFoldBatch) {
         const int nb = (z1 - b0) < kFoldBatch ? (z1 - b0) : kFoldBatch;
         __syncthreads();
-        if (tid < nb) {
-            const int z = b0 + tid;
-            const double* w = W + ((size_t)kk[z] * I2 + jj[z]) * J1;
-            for (int a = 0; a < J1; ++a) wb[tid * 33 + a] = w[a];
-            xb[tid] = (double)xx[z];
+        // the batch's rows of W, every thread gathering (independent loads)
+        for (int idx = tid; idx < nb * J1; idx += 256) {
+            const int t = idx / J1, a = idx - t * J1, z = b0 + t;
+            wb[t * 33 + a] = W[((size_t)kk[z] * I2 + jj[z]) * J1 + a];
         }
+        if (tid < nb) xb[tid] = (double)xx[b0 + tid];
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < 3; ++u) {
@@ -110,8 +111,8 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
     __shared__ double Q[32 * 32];
     __shared__ double L[32 * 32];
     __shared__ double r[32], u[32], g[32], d[32];
-    __shared__ double red_s[256];
-    __shared__ int red_i[256];
+    __shared__ double red_s[4];
+    __shared__ int red_i[4];
     __shared__ double unorm, step;
     __shared__ int bad;
     const int tid = threadIdx.x;
@@ -208,7 +209,9 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
     }
     __syncthreads();
     // top k by repeated arg-max: larger score first, lower index on ties;
-    // a taken row is marked with NaN
+    // a taken row is marked with NaN.  Each round reduces within every
+    // wavefront by lane exchanges, then over the four wavefronts.
+    const int lane = tid & 63, wv = tid >> 6;
     for (int t = 0; t < topk; ++t) {
         double bs = -INFINITY;
         int bi = -1;
@@ -220,27 +223,34 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
                 bi = i;
             }
         }
-        red_s[tid] = bs;
-        red_i[tid] = bi;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double s2 = __shfl_xor(bs, o);
+            const int i2 = __shfl_xor(bi, o);
+            if (i2 >= 0 && (bi < 0 || s2 > bs || (s2 == bs && i2 < bi))) {
+                bs = s2;
+                bi = i2;
+            }
+        }
+        if (lane == 0) {
+            red_s[wv] = bs;
+            red_i[wv] = bi;
+        }
         __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (tid < w) {
-                const double s2 = red_s[tid + w];
-                const int i2 = red_i[tid + w];
-                const double s1 = red_s[tid];
-                const int i1 = red_i[tid];
-                const bool take = i2 >= 0 && (i1 < 0 || s2 > s1 || (s2 == s1 && i2 < i1));
-                if (take) {
-                    red_s[tid] = s2;
-                    red_i[tid] = i2;
+        if (tid == 0) {
+            double s1 = red_s[0];
+            int i1 = red_i[0];
+            for (int w = 1; w < 4; ++w) {
+                const double s2 = red_s[w];
+                const int i2 = red_i[w];
+                if (i2 >= 0 && (i1 < 0 || s2 > s1 || (s2 == s1 && i2 < i1))) {
+                    s1 = s2;
+                    i1 = i2;
                 }
             }
-            __syncthreads();
-        }
-        if (tid == 0) {
-            out[J1 + t] = red_s[0];
-            out[J1 + topk + t] = (double)red_i[0];
-            if (red_i[0] >= 0) scores[red_i[0]] = NAN;
+            out[J1 + t] = s1;
+            out[J1 + topk + t] = (double)i1;
+            if (i1 >= 0) scores[i1] = NAN;
         }
         __syncthreads();
     }
@@ -257,7 +267,13 @@ hipError_t launch_serve_setup(const float* A, const float* B, const float* C, co
     return hipGetLastError();
 }
 
-int serve_parts(int n) { return n <= 0 ? 1 : (n + 4095) / 4096 < 64 ? (n + 4095) / 4096 : 64; }
+// Workgroups for a request of n nonzeros: about 256 nonzeros each (two
+// batches), at most kServeMaxParts.
+int serve_parts(int n)
+{
+    const int p = (n + 255) / 256;
+    return p < 1 ? 1 : (p < kServeMaxParts ? p : kServeMaxParts);
+}
 
 hipError_t launch_serve_request(const int32_t* jj, const int32_t* kk, const float* xx, int n, const double* W, int I2,
                                 int J1, double lam, int pg_iters, const float* A, const double* anrm, int I1,

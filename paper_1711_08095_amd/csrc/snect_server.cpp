@@ -183,7 +183,7 @@ int snect_server_create(snect_ctx* ctx, int32_t I1, int32_t I2, int32_t I3, int3
     for (auto& sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-            hipMalloc((void**)&sl.d_part, sizeof(double) * 64 * ne) != hipSuccess ||
+            hipMalloc((void**)&sl.d_part, sizeof(double) * kServeMaxParts * ne) != hipSuccess ||
             hipMalloc((void**)&sl.d_scores, sizeof(double) * (size_t)I1) != hipSuccess ||
             hipMalloc((void**)&sl.d_out, sizeof(double) * s->out_len()) != hipSuccess ||
             hipMalloc((void**)&sl.d_status, sizeof(int) * 4) != hipSuccess ||
