@@ -102,25 +102,49 @@ __global__ __launch_bounds__(256) void serve_gram(const int32_t* jj, const int32
     }
 }
 
+constexpr int kScoreLds = 6144;  // patients whose scores stay in LDS during the search
+
 // Solve and search, one workgroup per request.  out: u[J1], then for the
-// top k: scores (double), then indices (int, stored as double).
+// top k: scores (double), then indices (int, stored as double).  SL: the
+// I1 <= kScoreLds scores live in dynamic LDS, else in `scores` (global).
+template <bool SL>
 __global__ __launch_bounds__(256) void serve_solve(const double* part, int nparts, int J1, double lam, int pg_iters,
                                                    const float* A, const double* anrm, int I1, int topk,
-                                                   double* scores, double* out, int* status)
+                                                   double* gscores, double* out, int* status)
 {
     __shared__ double Q[32 * 32];
     __shared__ double L[32 * 32];
     __shared__ double r[32], u[32], g[32], d[32];
+    __shared__ double psub[576];
     __shared__ double red_s[4];
     __shared__ int red_i[4];
     __shared__ double unorm, step;
     __shared__ int bad;
+    extern __shared__ double lds_scores[];
+    double* scores = SL ? lds_scores : gscores;
     const int tid = threadIdx.x;
     const int nq = J1 * (J1 + 1) / 2, ne = nq + J1;
-    // Q and r from the partial sums, ascending workgroup order
+    // Q and r from the partial sums: G threads per entry each add a
+    // contiguous range of workgroups in ascending order (16 loads in
+    // flight), then the G range sums are added in ascending order
+    const int G = ne < 256 ? 256 / ne : 1;
+    for (int task = tid; task < ne * G; task += 256) {
+        const int e = task / G, gsub = task - e * G;
+        const int p0 = (int)(((long long)nparts * gsub) / G), p1 = (int)(((long long)nparts * (gsub + 1)) / G);
+        double acc = 0.0;
+        for (int pb = p0; pb < p1; pb += 16) {
+            double v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = pb + q < p1 ? part[(size_t)(pb + q) * ne + e] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc += v[q];
+        }
+        psub[task] = acc;
+    }
+    __syncthreads();
     for (int e = tid; e < ne; e += 256) {
-        double s = 0.0;
-        for (int p = 0; p < nparts; ++p) s += part[(size_t)p * ne + e];
+        double s = psub[e * G];
+        for (int gsub = 1; gsub < G; ++gsub) s += psub[e * G + gsub];
         if (e < nq) {
             int a = 0, rem = e;
             while (rem >= J1 - a) {
@@ -260,6 +284,12 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
 hipError_t launch_serve_setup(const float* A, const float* B, const float* C, const float* G, int I1, int I2, int I3,
                               int J1, int J2, int J3, double* W, double* anrm, hipStream_t st)
 {
+    if (I1 <= kScoreLds) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&serve_solve<true>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)(sizeof(double) * kScoreLds));
+        if (e != hipSuccess) return e;
+    }
     const long long nw = (long long)I3 * I2 * J1;
     hipLaunchKernelGGL(serve_build_w, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, B, C, G, I2, I3, J1, J2,
                        J3, W);
@@ -282,8 +312,12 @@ hipError_t launch_serve_request(const int32_t* jj, const int32_t* kk, const floa
     const int np = serve_parts(n);
     const int chunk = n > 0 ? (n + np - 1) / np : 1;
     hipLaunchKernelGGL(serve_gram, dim3(np), dim3(256), 0, st, jj, kk, xx, n, chunk, W, I2, J1, part);
-    hipLaunchKernelGGL(serve_solve, dim3(1), dim3(256), 0, st, part, np, J1, lam, pg_iters, A, anrm, I1, topk, scores,
-                       out, status);
+    if (I1 <= kScoreLds)
+        hipLaunchKernelGGL(serve_solve<true>, dim3(1), dim3(256), sizeof(double) * I1, st, part, np, J1, lam, pg_iters,
+                           A, anrm, I1, topk, scores, out, status);
+    else
+        hipLaunchKernelGGL(serve_solve<false>, dim3(1), dim3(256), 0, st, part, np, J1, lam, pg_iters, A, anrm, I1,
+                           topk, scores, out, status);
     return hipGetLastError();
 }
 
