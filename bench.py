@@ -341,6 +341,7 @@ def equal_rmse_leg(args, sn, synth, ctx, data, dims):
             rmses.append(float(rmse[0]))
             if ep == 0 or ep == args.equal_rmse_epochs - 1:
                 snaps[ep + 1] = [t.double().cpu().numpy() for t in f]
+                snaps[f"rmse_{ep + 1}"] = rmses[-1]
             if target is not None and reached is None and rmses[-1] <= target:
                 reached = (ep + 1, wall)
             if reached is not None and ep + 1 >= args.equal_rmse_epochs:
@@ -374,15 +375,19 @@ def bf16_oracle_errors(args, synth, data, dims, ranks, init, factors):
     res = {}
     cur = [np.asarray(a, np.float64) for a in init]
     done = 0
-    for ep in sorted(factors["fp32"]):
-        A, B, C, G, loss, rmse = oracle.run(prob_o, *cur, ep - done, start_epoch=done)
-        cur, done = [A, B, C, G], ep
+    for ep in sorted(e for e in factors["fp32"] if isinstance(e, int)):
+        while done < ep:  # one epoch per call, so that progress shows
+            t0 = time.perf_counter()
+            A, B, C, G, loss, rmse = oracle.run(prob_o, *cur, 1, start_epoch=done)
+            cur, done = [A, B, C, G], done + 1
+            log(f"oracle epoch {done}: rmse {rmse[-1]:.6f} ({time.perf_counter() - t0:.1f}s)", args.quiet)
         res[f"epoch_{ep}"] = {"oracle_rmse": float(rmse[-1])}
         for name in ("fp32", "bf16"):
             if ep in factors[name]:
                 res[f"epoch_{ep}"][name] = {
                     n: float(np.linalg.norm(g - o) / np.linalg.norm(o))
                     for n, g, o in zip("ABCG", factors[name][ep], cur)}
+                res[f"epoch_{ep}"][name]["rmse"] = factors[name][f"rmse_{ep}"]
     return res
 
 
