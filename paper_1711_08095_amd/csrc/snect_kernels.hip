@@ -8,21 +8,20 @@
 // gene rows sit in LDS, H_k = G x3 c_k for every platform k is built in LDS
 // from the stratum's frozen C and G, and each tile (<= 64 nonzeros of one
 // platform) is one step in which lane t of every wavefront stands for
-// nonzero t and wavefront w owns the factor columns c = w, w+NW, ...:
-//   1. every wavefront reads the tile's rows as they were before the tile;
-//      wavefront w forms w1[x] = (H_k b_j)[x] and w2[y] = (H_k^T a_i)[y] for
-//      its columns and stages a_c w1_c per column;
+// nonzero t.  Factor column c has a patient task (w1_c = (H_k b_j)_c and the
+// update of column c of a_i) and a gene task (w2_c = (H_k^T a_i)_c and the
+// update of column c of b_j), spread over the wavefronts:
+//   1. patient tasks read the tile's b rows, gene tasks its a rows, as they
+//      were before the tile; patient tasks stage a_c w1_c per column;
 //   2. after a barrier every lane sums x~ = a_i . w1 over ascending columns
-//      and forms e = x - x~; each wavefront stages e*w1 (in tile order),
-//      e*w2 (in the tile's gene-sorted slot order) and the matrix-core
-//      operands for its columns;
-//   3. after a barrier a segmented wavefront scan sums the terms of every
-//      patient run (contiguous: tiles are sorted by i) and every gene run
-//      (contiguous in slot order) in a fixed tree order; the last lane of a
-//      run writes the row's owned columns; the last four wavefronts also
-//      accumulate the block's sum of e a (x) b, each over a fixed quarter of
-//      the nonzeros, on the matrix cores;
-//   4. a barrier ends the tile.
+//      and forms e = x - x~; a segmented wavefront scan then sums the terms
+//      of every patient run (contiguous: tiles are sorted by i) and every
+//      gene run (contiguous in the tile's gene-sorted slot order) in a fixed
+//      tree order, and the last lane of a run writes the row's column;
+//      patient tasks also stage the matrix-core operands of the block's sum
+//      of e a (x) b, which four wavefronts accumulate at the start of the
+//      next tile, each over a fixed quarter of the nonzeros;
+//   3. a barrier ends the tile.
 // Every sum runs in an order fixed by the problem alone, so NW and the other
 // execution choices never change a bit of the result.  Staging arrays are
 // column-major with a pitch of 66 words, which keeps the column writes and
@@ -64,7 +63,7 @@ __device__ inline void lds_order_fence() { asm volatile("" ::: "memory"); }
 // LDS carve-up of the stratum kernels (in 4-byte words).
 // ---------------------------------------------------------------------------
 struct StratLds {
-    int a, b, ra, rb, c, g, h, sa, sb, as, es, xtp, slotj, stg, sk, mk, tco, tck, red, msum, cgt, flag, rec;
+    int a, b, ra, rb, c, g, h, sb, as, es, xtp, slotj, stg, sk, mk, tco, tck, red, msum, cgt, flag, rec;
     int hb, sw1, sw2, xts, esl, a16, e16;  // BF16 path only (zero-sized otherwise)
     int total;
 };
@@ -86,7 +85,6 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     L.g = o;     o = up4(o + j12 * J3);
     const int f32 = bf ? 0 : 1;
     L.h = o;     o = up4(o + f32 * I3 * jp * jp);
-    L.sa = o;    o = up4(o + f32 * jp * kTS);
     L.sb = o;    o = up4(o + f32 * jp * kTS);
     L.as = o;    o = up4(o + f32 * mp * kTS);
     L.es = o;    o = up4(o + f32 * mp * kTS);
@@ -272,16 +270,20 @@ template <> struct SAcc<16> {
     __device__ void zero() { v = floatx4{0.f, 0.f, 0.f, 0.f}; }
     // v_mfma_f32_16x16x4f32: step s covers nonzeros 4s..4s+3; lane l supplies
     // A[l%16][l/16] = a_{4s+l/16}[l%16] and B[l/16][l%16] = (e b)_{4s+l/16}[l%16].
-    // Matrix-core wavefront w (0..3) takes nonzeros 16w..16w+15, i.e. steps 4w..4w+3.
-    __device__ void accumulate(const float* As, const float* Es, int n, int w, int lane)
+    // Matrix-core wavefront w (0..3) takes nonzeros 16w..16w+15, i.e. steps
+    // 4w..4w+3, all four (operands past the tile's end are zero); the eight
+    // operand reads go out before the first product.
+    __device__ void accumulate_all(const float* As, const float* Es, int w, int lane)
     {
-        const int s_end = (n + 3) >> 2;
-        const int col = (lane & 15) * kTS + (lane >> 4);
+        const int col = (lane & 15) * kTS + (lane >> 4) + 16 * w;
+        float x[4], y[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int s = 4 * w + u;
-            if (s < s_end) v = __builtin_amdgcn_mfma_f32_16x16x4f32(As[col + 4 * s], Es[col + 4 * s], v, 0, 0, 0);
+            x[u] = As[col + 4 * u];
+            y[u] = Es[col + 4 * u];
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u], y[u], v, 0, 0, 0);
     }
     // output element (row 4*(l/16)+r, column l%16) sits in register r of lane l
     __device__ void store(float* St, int J1, int J2, int lane)
@@ -304,16 +306,18 @@ template <> struct SAcc<32> {
     }
     // v_mfma_f32_32x32x2f32: step s covers nonzeros 2s, 2s+1; lane l supplies
     // a_{2s+l/32}[l%32] and (e b)_{2s+l/32}[l%32].  Matrix-core wavefront w takes steps
-    // 8w..8w+7.
-    __device__ void accumulate(const float* As, const float* Es, int n, int w, int lane)
+    // 8w..8w+7, all eight (operands past the tile's end are zero).
+    __device__ void accumulate_all(const float* As, const float* Es, int w, int lane)
     {
-        const int s_end = (n + 1) >> 1;
-        const int col = (lane & 31) * kTS + (lane >> 5);
+        const int col = (lane & 31) * kTS + (lane >> 5) + 16 * w;
+        float x[8], y[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int s = 8 * w + u;
-            if (s < s_end) v = __builtin_amdgcn_mfma_f32_32x32x2f32(As[col + 2 * s], Es[col + 2 * s], v, 0, 0, 0);
+            x[u] = As[col + 2 * u];
+            y[u] = Es[col + 2 * u];
         }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v = __builtin_amdgcn_mfma_f32_32x32x2f32(x[u], y[u], v, 0, 0, 0);
     }
     // output element (row 8*(r/4) + 4*(l/32) + r%4, column l%32) in register r
     __device__ void store(float* St, int J1, int J2, int lane)
@@ -505,7 +509,7 @@ __device__ inline int run_head(unsigned long long heads, int lane)
 struct TileLds {
     float *Ab, *Bb;
     const float *rA, *rB, *Hs;
-    float *sA, *sB, *As, *Es, *xtp;
+    float *sB, *As, *Es, *xtp;
     // BF16 path: H_k and H_k^T as matrix-core B operands, raw w1 (tile order)
     // and w2 (slot order) columns, x~ per nonzero, e in slot order, staged
     // BF16 operands of the S product
@@ -549,21 +553,69 @@ __device__ inline void stage_sum(const float* St, float* Skk, int J1, int J2, in
     }
 }
 
+// Work split of a tile's factor columns between the NW wavefronts.  Column
+// c has a patient task (w1_c, its share a_c w1_c of x~, the S operands of
+// column c and the patient-run sums of e w1_c) and a gene task (w2_c and the
+// gene-run sums of e w2_c, which pass through the slot-ordered buffer and
+// cost about twice as much).  For small cores (JP <= 12) wavefronts
+// [0, NJ) take the gene tasks and [NJ, NW) the patient tasks, each kind
+// round robin, NJ minimising the largest load, so a wavefront reads only
+// one of the two rows.  Larger cores keep both tasks of column c on
+// wavefront c mod NW (fewer registers per wavefront).
+template <int JP, int NW> struct TileSplit {
+    static constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+    static constexpr int cost(int nj)
+    {
+        return cdiv(JP, NW - nj) > 2 * cdiv(JP, nj) ? cdiv(JP, NW - nj) : 2 * cdiv(JP, nj);
+    }
+    static constexpr int pick()
+    {
+        int b = 1;
+        for (int nj = 2; nj < NW; ++nj)
+            if (cost(nj) < cost(b)) b = nj;
+        return b;
+    }
+    static constexpr bool kSplit = JP <= 12;
+    static constexpr int NJ = kSplit ? pick() : NW;  // gene-task wavefronts [0, NJ)
+    static constexpr int OI = kSplit ? NJ : 0;       // patient-task wavefronts [OI, OI + NI)
+    static constexpr int NI = NW - OI;
+    static constexpr int QI = cdiv(JP, NI), QJ = cdiv(JP, NJ), QH = QI > QJ ? QI : QJ;
+};
+
 // The tiles of block (p, q), run by the whole workgroup (NW wavefronts).
 // L.Ab/L.Bb hold the block's rows; L.Sk (zeroed by the caller) receives
 // the block's per-platform sums through the staged partials of the four
 // matrix-core wavefronts; L.Mk the block's counts.  Every sum is
 // taken in an order that does not depend on NW (x~ over ascending columns,
 // S over four fixed nonzero ranges), so NW is an execution choice only.
+//
+// Two workgroup barriers per tile:
+//   1. patient tasks read the tile's b rows and form w1_c, a_c w1_c going
+//      to LDS; gene tasks read the a rows and form w2_c (all values from
+//      before the tile);
+//   -- barrier --
+//   2. every wavefront sums x~ over ascending columns and forms e; patient
+//      tasks stage the S operands and sum their runs of e w1_c in
+//      registers; gene tasks sum their runs of e w2_c through their own
+//      columns of the slot-ordered buffer; the last lane of a run writes
+//      the row;
+//   -- barrier --
+// The matrix-core wavefronts (the first four) add a tile's S operands at
+// the start of the next tile, so the product overlaps the next tile's row
+// reads.  Products are not contracted into fused multiply-adds beyond the
+// explicit fmaf.
 template <int JP, int NW>
 __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, int tid)
 {
+#pragma clang fp contract(off)
+    using SP = TileSplit<JP, NW>;
+    constexpr int NJ = SP::NJ, NI = SP::NI, OI = SP::OI, QI = SP::QI, QJ = SP::QJ, QH = SP::QH;
     constexpr int RS = strat_row_stride(JP, 0);
     constexpr int MP = mfma_dim(JP);
     constexpr int NT = 64 * NW;
-    constexpr int QN = (JP + NW - 1) / NW;  // owned factor columns per wavefront
-    constexpr int QM = (MP + NW - 1) / NW;  // owned operand columns per wavefront
     const int lane = tid & 63, w = tid >> 6;
+    const bool hj = w < NJ, hi = w >= OI;  // has gene tasks / patient tasks
+    const int rj = w, ri = w - OI;         // columns rj + NJ q, ri + NI q
     const int J1 = a.J1, J2 = a.J2, J12 = J1 * J2;
     const uint32_t mask_i = (1u << a.bits_i) - 1u, mask_j = (1u << a.bits_j) - 1u;
     const int sh_j = a.bits_i, sh_r = a.bits_i + a.bits_j;
@@ -571,18 +623,23 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
     const int t0 = a.blk_tile[blk], t1 = a.blk_tile[blk + 1];
     if (t0 >= t1) return;
 
+    // operand columns beyond the factor columns stay zero
+    for (int idx = tid; idx < (MP - JP) * kTS; idx += NT) {
+        L.As[JP * kTS + idx] = 0.f;
+        L.Es[JP * kTS + idx] = 0.f;
+    }
+
     SAcc<MP> acc;
     acc.zero();
-    // the last four wavefronts accumulate S (they own the fewest factor
-    // columns); mw numbers them 0..3
-    const int mw = w - (NW - kMfmaWaves);
-    const bool mfw = mw >= 0;
-    int curk = -1;
-    int pend = -1;  // platform whose partial S waits in L.St
-    // for small cores the owned rows and columns of H_k stay in registers
-    // while consecutive tiles share the platform k
-    constexpr bool kHreg = JP <= 12;
-    float hr[kHreg ? QN : 1][kHreg ? JP : 1], hc[kHreg ? QN : 1][kHreg ? JP : 1];
+    const bool mfw = w < kMfmaWaves;  // matrix-core wavefronts, mw = w
+    int curk = -1;   // platform of the tiles whose operands acc holds
+    int pend = -1;   // platform whose partial S waits in L.St
+    int prev = 0;    // a tile's S operands wait in L.As/L.Es
+    // small cores (one task kind per wavefront): the wavefront's rows
+    // (patient tasks) or columns (gene tasks) of H_k stay in registers while
+    // consecutive tiles share k
+    constexpr bool kHreg = SP::kSplit;
+    float hh[kHreg ? QH : 1][kHreg ? JP : 1];
     int tl = t0;
     while (tl < t1) {
         // a chunk: up to kTileCache tiles whose records fit in rec_cap,
@@ -595,14 +652,19 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         const int z0 = L.tco[0], nrec = L.tco[cend] - z0;
         load_records(L.rec, a.nz + z0, nrec, tid, NT);
         __syncthreads();
+        // each tile's records are read from LDS during the previous tile
+        uint2 wv_next = lane < L.tco[1] - z0 ? L.rec[lane] : make_uint2(0u, 0u);
         for (int u = 0; u < cend; ++u, ++tl) {
         const int off = L.tco[u];
         const int n = L.tco[u + 1] - off;
         const int k = L.tck[u];
-        const uint2 wv = lane < n ? L.rec[off - z0 + lane] : make_uint2(0u, 0u);
+        const uint2 wv = wv_next;
+        // S of the previous tile (its platform is curk); staged operands of
+        // nonzeros past the tile's end are zero
+        if (mfw && prev) acc.accumulate_all(L.As, L.Es, w, lane);
         if (k != curk) {
             if (curk >= 0) {
-                if (mfw) acc.store(L.St + mw * J12, J1, J2, lane);
+                if (mfw) acc.store(L.St + w * J12, J1, J2, lane);
                 pend = curk;
             }
             acc.zero();
@@ -610,13 +672,11 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
             if constexpr (kHreg) {
                 const float* Hk = L.Hs + k * JP * JP;
 #pragma unroll
-                for (int qq = 0; qq < QN; ++qq) {
-                    const int c = w + NW * qq < JP ? w + NW * qq : 0;
+                for (int qq = 0; qq < QH; ++qq) {
+                    const int c0 = hj ? rj + NJ * qq : ri + NI * qq;
+                    const int c = c0 < JP ? c0 : 0;
 #pragma unroll
-                    for (int y = 0; y < JP; ++y) {
-                        hr[qq][y] = Hk[c * JP + y];
-                        hc[qq][y] = Hk[y * JP + c];
-                    }
+                    for (int y = 0; y < JP; ++y) hh[qq][y] = hj ? Hk[y * JP + c] : Hk[c * JP + y];
                 }
             }
         }
@@ -626,93 +686,102 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         const int il = act ? (int)(wd & mask_i) : -1;
         const int jl = act ? (int)((wd >> sh_j) & mask_j) : 0;
         const int jrank = (int)(wd >> sh_r);
+        if (w == 0 && act) L.slotJ[jrank] = jl;
 
-        // 1. rows before the tile; owned columns of w1 and w2; share of x~
-        float av[JP], bv[JP];
-#pragma unroll
-        for (int c = 0; c < JP; ++c) {
-            av[c] = act ? L.Ab[il * RS + c] : 0.f;
-            bv[c] = act ? L.Bb[jl * RS + c] : 0.f;
-        }
+        // 1. the rows from before the tile: b_j for patient tasks
+        //    (w1 = H_k b), a_i for gene tasks (w2 = H_k^T a)
         const float* H = L.Hs + k * JP * JP;
-        float w1q[QN], w2q[QN], aq[QN];
+        float w1q[QI], aq[QI], bq[QI], w2q[QJ];
+        if (hi) {
+            float bv[JP];
 #pragma unroll
-        for (int qq = 0; qq < QN; ++qq) {
-            const int c = w + NW * qq;
-            float t1v = 0.f, t2v = 0.f, ac = 0.f;
-            if (c < JP) {
-                if constexpr (kHreg) {
+            for (int c = 0; c < JP; ++c) bv[c] = act ? L.Bb[jl * RS + c] : 0.f;
 #pragma unroll
-                    for (int y = 0; y < JP; ++y) t1v = fmaf(hr[qq][y], bv[y], t1v);
+            for (int qq = 0; qq < QI; ++qq) {
+                const int c = ri + NI * qq;
+                float t = 0.f, ac = 0.f, bc = 0.f;
+                if (c < JP) {
+                    if constexpr (kHreg) {
 #pragma unroll
-                    for (int x_ = 0; x_ < JP; ++x_) t2v = fmaf(av[x_], hc[qq][x_], t2v);
-                } else {
+                        for (int y = 0; y < JP; ++y) t = fmaf(hh[qq][y], bv[y], t);
+                    } else {
 #pragma unroll
-                    for (int y = 0; y < JP; ++y) t1v = fmaf(H[c * JP + y], bv[y], t1v);
-#pragma unroll
-                    for (int x_ = 0; x_ < JP; ++x_) t2v = fmaf(av[x_], H[x_ * JP + c], t2v);
+                        for (int y = 0; y < JP; ++y) t = fmaf(H[c * JP + y], bv[y], t);
+                    }
+                    ac = act ? L.Ab[il * RS + c] : 0.f;
+                    bc = act ? L.Bb[jl * RS + c] : 0.f;
+                    L.xtp[c * kTileMax + lane] = ac * t;
                 }
-                ac = act ? L.Ab[il * RS + c] : 0.f;
-                L.xtp[c * kTileMax + lane] = ac * t1v;
+                w1q[qq] = t;
+                aq[qq] = ac;
+                bq[qq] = bc;
+                if constexpr (JP > 16) lds_order_fence();
             }
-            w1q[qq] = t1v;
-            w2q[qq] = t2v;
-            aq[qq] = ac;
-            if constexpr (JP > 16) lds_order_fence();
         }
+        if (hj) {
+            float av[JP];
+#pragma unroll
+            for (int c = 0; c < JP; ++c) av[c] = act ? L.Ab[il * RS + c] : 0.f;
+#pragma unroll
+            for (int qq = 0; qq < QJ; ++qq) {
+                const int c = rj + NJ * qq;
+                float t = 0.f;
+                if (c < JP) {
+                    if constexpr (kHreg) {
+#pragma unroll
+                        for (int x_ = 0; x_ < JP; ++x_) t = fmaf(av[x_], hh[qq][x_], t);
+                    } else {
+#pragma unroll
+                        for (int x_ = 0; x_ < JP; ++x_) t = fmaf(av[x_], H[x_ * JP + c], t);
+                    }
+                }
+                w2q[qq] = t;
+            }
+        }
+        // patient runs (the tile is sorted by patient): heads and the
+        // regularisation weight of each run
+        const int il_up = dpp_move_i<kDppWaveShr1>(il), il_dn = dpp_move_i<kDppWaveShl1>(il);
+        const bool ifirst = act && (lane == 0 || il_up != il);
+        const bool ilast = act && (lane == 63 || il_dn != il);
+        const int ihead = run_head(__ballot(ifirst), lane);
+        const float icr = (act && hi) ? (float)(lane - ihead + 1) * L.rA[il] : 0.f;
         __syncthreads();
         if (pend >= 0) {
             stage_sum<false, MP>(L.St, L.Sk + pend * J12, J1, J2, tid, NT);
             pend = -1;
         }
+        if (u + 1 < cend) {
+            const int o2 = L.tco[u + 1], n2 = L.tco[u + 2] - o2;
+            wv_next = lane < n2 ? L.rec[o2 - z0 + lane] : make_uint2(0u, 0u);
+        }
 
-        // 2. residual (x~ summed over ascending columns); stage row terms
-        //    and matrix-core operands
+        // 2. residual (x~ summed over ascending columns); the tasks' run sums
         float xt = L.xtp[lane];
 #pragma unroll
         for (int c = 1; c < JP; ++c) xt += L.xtp[c * kTileMax + lane];
         const float e = act ? x - xt : 0.f;
+        if (hi) {
 #pragma unroll
-        for (int qq = 0; qq < QN; ++qq) {
-            const int c = w + NW * qq;
-            if (c < JP) {
-                L.sA[c * kTS + lane] = e * w1q[qq];
-                if (act) L.sB[c * kTS + jrank] = e * w2q[qq];
-            }
-        }
-#pragma unroll
-        for (int qm = 0; qm < QM; ++qm) {
-            const int c = w + NW * qm;
-            if (c >= MP) continue;
-            float av_c = 0.f, eb_c = 0.f;
-            if (c < JP && act) {
-                av_c = qm < QN ? aq[qm < QN ? qm : 0] : L.Ab[il * RS + c];
-                eb_c = e * L.Bb[jl * RS + c];
-            }
-            L.As[c * kTS + lane] = av_c;
-            L.Es[c * kTS + lane] = eb_c;
-        }
-        if (w == 0 && act) L.slotJ[jrank] = jl;
-        __syncthreads();
-
-        // 3. matrix-core sums; fixed-order run sums; owned columns of the rows
-        if (mfw) acc.accumulate(L.As, L.Es, n, mw, lane);
-        {
-            const int il_up = dpp_move_i<kDppWaveShr1>(il), il_dn = dpp_move_i<kDppWaveShl1>(il);
-            const bool ifirst = act && (lane == 0 || il_up != il);
-            const bool ilast = act && (lane == 63 || il_dn != il);
-            const int head = run_head(__ballot(ifirst), lane);
-            const float cr = act ? (float)(lane - head + 1) * L.rA[il] : 0.f;
-#pragma unroll
-            for (int qq = 0; qq < QN; ++qq) {
-                const int c = w + NW * qq;
+            for (int qq = 0; qq < QI; ++qq) {
+                const int c = ri + NI * qq;
                 if (c < JP) {
-                    const float v = seg_scan(L.sA[c * kTS + lane], lane, head);
-                    if (ilast) L.Ab[il * RS + c] = fmaf(a.lr, v - cr * aq[qq], aq[qq]);
+                    L.As[c * kTS + lane] = aq[qq];
+                    L.Es[c * kTS + lane] = e * bq[qq];
+                    const float v = seg_scan(e * w1q[qq], lane, ihead);
+                    if (ilast) L.Ab[il * RS + c] = fmaf(a.lr, v - icr * aq[qq], aq[qq]);
                 }
             }
         }
-        {
+        if (hj) {
+            // gene runs in the tile's gene-sorted slot order: the wavefront
+            // scatters e w2 of its own columns to slot order and reads it
+            // back (its own LDS columns: no barrier needed)
+#pragma unroll
+            for (int qq = 0; qq < QJ; ++qq) {
+                const int c = rj + NJ * qq;
+                if (c < JP && act) L.sB[c * kTS + jrank] = e * w2q[qq];
+            }
+            lds_order_fence();
             const int sj = lane < n ? L.slotJ[lane] : -1;
             const int sj_up = dpp_move_i<kDppWaveShr1>(sj), sj_dn = dpp_move_i<kDppWaveShl1>(sj);
             const bool jfirst = lane < n && (lane == 0 || sj_up != sj);
@@ -720,8 +789,8 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
             const int head = run_head(__ballot(jfirst), lane);
             const float cr = lane < n ? (float)(lane - head + 1) * L.rB[sj] : 0.f;
 #pragma unroll
-            for (int qq = 0; qq < QN; ++qq) {
-                const int c = w + NW * qq;
+            for (int qq = 0; qq < QJ; ++qq) {
+                const int c = rj + NJ * qq;
                 if (c < JP) {
                     const float v = seg_scan(L.sB[c * kTS + lane], lane, head);
                     if (jlast) {
@@ -732,10 +801,12 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
             }
         }
         if (tid == 0) L.Mk[k] += n;
+        prev = 1;
         __syncthreads();
         }
     }
-    if (mfw) acc.store(L.St + mw * J12, J1, J2, lane);
+    if (mfw && prev) acc.accumulate_all(L.As, L.Es, w, lane);
+    if (mfw) acc.store(L.St + w * J12, J1, J2, lane);
     __syncthreads();
     stage_sum<false, MP>(L.St, L.Sk + curk * J12, J1, J2, tid, NT);
     __syncthreads();
@@ -997,7 +1068,6 @@ __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
     L.rA = lds + S.ra;
     L.rB = lds + S.rb;
     L.Hs = lds + S.h;
-    L.sA = lds + S.sa;
     L.sB = lds + S.sb;
     L.As = lds + S.as;
     L.Es = lds + S.es;
