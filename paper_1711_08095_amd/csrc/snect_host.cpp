@@ -146,7 +146,7 @@ struct snect_problem {
     float *d_adj_w = nullptr, *d_deg = nullptr;
     float *d_Ap = nullptr, *d_Bp = nullptr, *d_Btmp = nullptr;
     float *d_Spart = nullptr, *d_Ssum = nullptr;
-    int32_t* d_Mpart = nullptr;
+    int32_t* d_scount = nullptr;
     int32_t* d_order = nullptr;  // [P]
     GridBar* d_bar = nullptr;
     double *d_sse = nullptr, *d_regp = nullptr, *d_net = nullptr, *d_lossout = nullptr;
@@ -432,6 +432,15 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         }
         tile_off[ntiles] = (int32_t)nnz;
         for (int64_t blk = 0; blk <= (int64_t)P * P; ++blk) blk_tile[blk] = (int32_t)tiles_in_bucket[blk * I3];
+        // nonzeros of stratum s (blocks (p, (p + s) mod P)) on each platform
+        std::vector<int32_t> scount((size_t)P * I3, 0);
+        for (int p = 0; p < P; ++p)
+            for (int q = 0; q < P; ++q) {
+                const int s = (q - p + P) % P;
+                const int64_t blk = (int64_t)p * P + q;
+                for (int64_t tl = blk_tile[blk]; tl < blk_tile[blk + 1]; ++tl)
+                    scount[(size_t)s * I3 + tile_k[tl]] += tile_off[tl + 1] - tile_off[tl];
+            }
         // ---------------- pack records with the tile's gene-slot order ----------------
         std::vector<uint2> nz(nnz);
         const int sh_f = bits_i + bits_j;
@@ -518,7 +527,7 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         pr->d_Btmp = pr->alloc<float>((size_t)I2 * J2, rc);
         pr->d_Spart = pr->alloc<float>((size_t)P * ni, rc);
         pr->d_Ssum = pr->alloc<float>(std::max(ni, ng), rc);
-        pr->d_Mpart = pr->alloc<int32_t>((size_t)P * I3, rc);
+        pr->d_scount = pr->alloc<int32_t>((size_t)P * I3, rc);
         pr->d_order = pr->alloc<int32_t>(P, rc);
         pr->d_bar = pr->alloc<GridBar>(1, rc);
         pr->d_sse = pr->alloc<double>((size_t)P * P, rc);
@@ -548,6 +557,7 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         he = he ? he : up(pr->d_tile_off, tile_off.data(), tile_off.size() * 4);
         he = he ? he : up(pr->d_tile_k, tile_k.data(), tile_k.size() * 4);
         he = he ? he : up(pr->d_blk_tile, blk_tile.data(), blk_tile.size() * 4);
+        he = he ? he : up(pr->d_scount, scount.data(), scount.size() * 4);
         he = he ? he : up(pr->d_perm1, pr->perm1.data(), (size_t)I1 * 4);
         he = he ? he : up(pr->d_perm2, pr->perm2.data(), (size_t)I2 * 4);
         he = he ? he : up(pr->d_start1, start1.data(), (size_t)(P + 1) * 4);
@@ -693,7 +703,7 @@ static StratArgs strat_args(const snect_problem* pr, const snect_factors* f)
     sa.start1 = pr->d_start1; sa.start2 = pr->d_start2;
     sa.reg1 = pr->d_reg1; sa.reg2 = pr->d_reg2; sa.cnt3 = pr->d_cnt3;
     sa.Ap = pr->d_Ap; sa.Bp = pr->d_Bp; sa.C = f->C; sa.G = f->G;
-    sa.Spart = pr->d_Spart; sa.Mpart = pr->d_Mpart; sa.Ssum = pr->d_Ssum;
+    sa.Spart = pr->d_Spart; sa.scount = pr->d_scount; sa.Ssum = pr->d_Ssum;
     sa.order = pr->d_order; sa.bar = pr->d_bar; sa.jp = pr->jp;
     sa.P = pr->P; sa.s = 0; sa.I3 = pr->I3; sa.J1 = pr->J1; sa.J2 = pr->J2; sa.J3 = pr->J3;
     sa.rows1_max = pr->rows1_max; sa.rows2_max = pr->rows2_max; sa.bits_i = pr->bits_i; sa.bits_j = pr->bits_j;

@@ -71,7 +71,7 @@ struct StratArgs {
     float* C;                  // [I3][J3]
     float* G;                  // [J1][J2][J3]
     float* Spart;              // [P][I3*J1*J2] per-block sums of e a (x) b
-    int32_t* Mpart;            // [P][I3] per-block nonzero counts
+    const int32_t* scount;     // [P][I3] nonzeros of stratum s on platform k (fixed by the plan)
     float* Ssum;               // [I3*J1*J2] stratum sums (persistent kernel)
     const int32_t* order;      // [P] stratum order of this epoch
     GridBar* bar;

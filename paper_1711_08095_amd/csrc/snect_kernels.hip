@@ -63,7 +63,7 @@ __device__ inline void lds_order_fence() { asm volatile("" ::: "memory"); }
 // LDS carve-up of the stratum kernels (in 4-byte words).
 // ---------------------------------------------------------------------------
 struct StratLds {
-    int a, b, ra, rb, c, g, h, sb, as, es, xtp, slotj, stg, sk, mk, tco, tck, red, msum, cgt, flag, rec;
+    int a, b, ra, rb, c, g, h, sb, as, es, xtp, slotj, stg, sk, tco, tck, red, msum, cgt, flag, rec;
     int hb, sw1, sw2, xts, esl, a16, e16;  // BF16 path only (zero-sized otherwise)
     int total;
 };
@@ -99,7 +99,6 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     L.slotj = o; o = up4(o + kTileMax);
     L.stg = o;   o = up4(o + kMfmaWaves * j12);
     L.sk = o;    o = up4(o + I3 * j12);
-    L.mk = o;    o = up4(o + I3);
     L.tco = o;   o = up4(o + kTileCache + 1);
     L.tck = o;   o = up4(o + kTileCache);
     L.red = o;   o = up4(o + (64 * nw > I3 * J3 * nch ? 64 * nw : I3 * J3 * nch));
@@ -199,18 +198,6 @@ __device__ void reduce_items(const float* Spart, int P, int ni, int i0, int i1, 
             dst[base + tid - i0] = s;
         }
     }
-    __syncthreads();
-}
-
-// m_k = sum over blocks of the per-block counts (integer adds: exact in any
-// order).  cnt is I3 ints of LDS scratch; msum receives doubles.
-__device__ void stratum_counts(const int32_t* Mpart, int P, int I3, int* cnt, double* msum, int tid, int nthr)
-{
-    for (int k = tid; k < I3; k += nthr) cnt[k] = 0;
-    __syncthreads();
-    for (int idx = tid; idx < P * I3; idx += nthr) atomicAdd(&cnt[idx % I3], Mpart[idx]);
-    __syncthreads();
-    for (int k = tid; k < I3; k += nthr) msum[k] = (double)cnt[k];
     __syncthreads();
 }
 
@@ -519,7 +506,6 @@ struct TileLds {
     int* slotJ;
     float* Sk;    // [I3*J1*J2] the block's sums of e a (x) b
     float* St;    // [kMfmaWaves][J1*J2] staged partial sums of one platform
-    int* Mk;
     int *tco, *tck;
     uint2* rec;   // [rec_cap] staged records
 };
@@ -556,17 +542,18 @@ __device__ inline void stage_sum(const float* St, float* Skk, int J1, int J2, in
 // Work split of a tile's factor columns between the NW wavefronts.  Column
 // c has a patient task (w1_c, its share a_c w1_c of x~, the S operands of
 // column c and the patient-run sums of e w1_c) and a gene task (w2_c and the
-// gene-run sums of e w2_c, which pass through the slot-ordered buffer and
-// cost about twice as much).  For small cores (JP <= 12) wavefronts
-// [0, NJ) take the gene tasks and [NJ, NW) the patient tasks, each kind
-// round robin, NJ minimising the largest load, so a wavefront reads only
-// one of the two rows.  Larger cores keep both tasks of column c on
-// wavefront c mod NW (fewer registers per wavefront).
+// gene-run sums of e w2_c through the slot-ordered buffer); the two cost
+// about the same.  For small cores (JP <= 12) wavefronts [0, NJ) take the
+// gene tasks and [NJ, NW) the patient tasks, each kind round robin, NJ
+// minimising the largest load, so a wavefront reads only one of the two
+// rows.  Larger cores keep both tasks of column c on wavefront c mod NW
+// (fewer registers per wavefront).  The four wavefronts with the fewest
+// tasks (the lower index first among equals) accumulate S.
 template <int JP, int NW> struct TileSplit {
     static constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
     static constexpr int cost(int nj)
     {
-        return cdiv(JP, NW - nj) > 2 * cdiv(JP, nj) ? cdiv(JP, NW - nj) : 2 * cdiv(JP, nj);
+        return cdiv(JP, NW - nj) > cdiv(JP, nj) ? cdiv(JP, NW - nj) : cdiv(JP, nj);
     }
     static constexpr int pick()
     {
@@ -580,12 +567,27 @@ template <int JP, int NW> struct TileSplit {
     static constexpr int OI = kSplit ? NJ : 0;       // patient-task wavefronts [OI, OI + NI)
     static constexpr int NI = NW - OI;
     static constexpr int QI = cdiv(JP, NI), QJ = cdiv(JP, NJ), QH = QI > QJ ? QI : QJ;
+    // tasks of wavefront w
+    static constexpr int tasks(int w)
+    {
+        const int tj = w < NJ ? cdiv(JP - w, NJ) : 0;
+        const int ti = w >= OI ? cdiv(JP - (w - OI), NI) : 0;
+        return (tj > 0 ? tj : 0) + (ti > 0 ? ti : 0);
+    }
+    // rank of wavefront w among the matrix-core wavefronts, or -1
+    static constexpr int mfma_rank(int w)
+    {
+        int r = 0;
+        for (int v = 0; v < NW; ++v)
+            if (tasks(v) < tasks(w) || (tasks(v) == tasks(w) && v < w)) ++r;
+        return r < kMfmaWaves ? r : -1;
+    }
 };
 
 // The tiles of block (p, q), run by the whole workgroup (NW wavefronts).
 // L.Ab/L.Bb hold the block's rows; L.Sk (zeroed by the caller) receives
 // the block's per-platform sums through the staged partials of the four
-// matrix-core wavefronts; L.Mk the block's counts.  Every sum is
+// matrix-core wavefronts.  Every sum is
 // taken in an order that does not depend on NW (x~ over ascending columns,
 // S over four fixed nonzero ranges), so NW is an execution choice only.
 //
@@ -600,8 +602,8 @@ template <int JP, int NW> struct TileSplit {
 //      columns of the slot-ordered buffer; the last lane of a run writes
 //      the row;
 //   -- barrier --
-// The matrix-core wavefronts (the first four) add a tile's S operands at
-// the start of the next tile, so the product overlaps the next tile's row
+// The matrix-core wavefronts add a tile's S operands at the start of the
+// next tile, so the product overlaps the next tile's row
 // reads.  Products are not contracted into fused multiply-adds beyond the
 // explicit fmaf.
 template <int JP, int NW>
@@ -631,7 +633,8 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
 
     SAcc<MP> acc;
     acc.zero();
-    const bool mfw = w < kMfmaWaves;  // matrix-core wavefronts, mw = w
+    const int mw = SP::mfma_rank(w);  // matrix-core wavefronts: mw = 0..3
+    const bool mfw = mw >= 0;
     int curk = -1;   // platform of the tiles whose operands acc holds
     int pend = -1;   // platform whose partial S waits in L.St
     int prev = 0;    // a tile's S operands wait in L.As/L.Es
@@ -661,10 +664,10 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         const uint2 wv = wv_next;
         // S of the previous tile (its platform is curk); staged operands of
         // nonzeros past the tile's end are zero
-        if (mfw && prev) acc.accumulate_all(L.As, L.Es, w, lane);
+        if (mfw && prev) acc.accumulate_all(L.As, L.Es, mw, lane);
         if (k != curk) {
             if (curk >= 0) {
-                if (mfw) acc.store(L.St + w * J12, J1, J2, lane);
+                if (mfw) acc.store(L.St + mw * J12, J1, J2, lane);
                 pend = curk;
             }
             acc.zero();
@@ -800,13 +803,12 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
                 }
             }
         }
-        if (tid == 0) L.Mk[k] += n;
         prev = 1;
         __syncthreads();
         }
     }
-    if (mfw && prev) acc.accumulate_all(L.As, L.Es, w, lane);
-    if (mfw) acc.store(L.St + w * J12, J1, J2, lane);
+    if (mfw && prev) acc.accumulate_all(L.As, L.Es, mw, lane);
+    if (mfw) acc.store(L.St + mw * J12, J1, J2, lane);
     __syncthreads();
     stage_sum<false, MP>(L.St, L.Sk + curk * J12, J1, J2, tid, NT);
     __syncthreads();
@@ -996,7 +998,6 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
                 }
             }
         }
-        if (tid == 0) L.Mk[k] += n;
         __syncthreads();
         }
     }
@@ -1028,18 +1029,21 @@ __device__ bool grid_sync(GridBar* bar, unsigned nblocks, unsigned& nbar, int* f
         __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         // poll with relaxed loads (no cache invalidation per poll: a waiting
         // workgroup must not keep invalidating the L2 that workgroups still
-        // running tiles share), then acquire once
+        // running tiles share), then acquire once; one load per poll, the
+        // error flag (another workgroup gave up) every 128 polls
         unsigned spins = 0;
         while (__hip_atomic_load(&bar->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(&bar->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                ok = 0;
-                break;
-            }
             __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinLimit) {
-                atomicOr(&bar->err, 1u);
-                ok = 0;
-                break;
+            if ((++spins & 127u) == 0u) {
+                if (spins > kSpinLimit) {
+                    atomicOr(&bar->err, 1u);
+                    ok = 0;
+                    break;
+                }
+                if (__hip_atomic_load(&bar->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                    ok = 0;
+                    break;
+                }
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -1082,7 +1086,6 @@ __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
     L.slotJ = reinterpret_cast<int*>(lds + S.slotj);
     L.Sk = lds + S.sk;
     L.St = lds + S.stg;
-    L.Mk = reinterpret_cast<int*>(lds + S.mk);
     L.tco = reinterpret_cast<int*>(lds + S.tco);
     L.tck = reinterpret_cast<int*>(lds + S.tck);
     L.rec = reinterpret_cast<uint2*>(lds + S.rec);
@@ -1129,6 +1132,8 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
     // contiguous slice of the per-block sums
     const int r = xcd_slot(q, P);
     const int i0 = (int)(((long long)ni * r) / P), i1 = (int)(((long long)ni * (r + 1)) / P);
+    const int nchr = (P + kRedChunk - 1) / kRedChunk;
+    const int rit = tid / nchr, rch = tid - rit * nchr;  // item and chunk of this thread's share
 
     for (int si = 0; si < P; ++si) {
         const int s = a.order[si];
@@ -1143,7 +1148,6 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
         else
             build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
         for (int idx = tid; idx < ni; idx += NT) Sk[idx] = 0.f;
-        for (int k = tid; k < I3; k += NT) L.Mk[k] = 0;
         __syncthreads();
         if constexpr (BF)
             block_tiles_bf<JP, NW>(a, p, q, L, tid);
@@ -1153,19 +1157,48 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
         __syncthreads();
         float* Sp = a.Spart + (size_t)p * ni;
         for (int idx = tid; idx < ni; idx += NT) Sp[idx] = Sk[idx];
-        for (int k = tid; k < I3; k += NT) a.Mpart[p * I3 + k] = L.Mk[k];
         if (!grid_sync(a.bar, P, nbar, flag)) return;
 
-        // every block of this stratum has stored its rows: the next
-        // stratum's patient rows are final and load while the sums reduce
+        // every block of this stratum has stored its rows and sums: this
+        // workgroup's share of the sums (one chunk of kRedChunk blocks per
+        // thread when the share allows), the stratum's counts and the next
+        // stratum's patient rows are read in one round of loads
+        const bool one = (i1 - i0) * nchr <= NT;
+        float rv[kRedChunk];
+        {
+            const bool rt = one && tid < (i1 - i0) * nchr;
+            const int p0 = rch * kRedChunk;
+#pragma unroll
+            for (int u = 0; u < kRedChunk; ++u)
+                rv[u] = rt && p0 + u < P ? a.Spart[(size_t)(p0 + u) * ni + i0 + rit] : 0.f;
+        }
+        const int cnt0 = tid < I3 ? a.scount[s * I3 + tid] : 0;
         if (si + 1 < P) {
             const int pn = (q - a.order[si + 1] + P) % P;
             const int s1n = a.start1[pn], r1n = a.start1[pn + 1] - s1n;
             load_rows(L.Ab, a.Ap, s1n, r1n, J1, RS, tid, NT);
             for (int l = tid; l < r1n; l += NT) lds[S.ra + l] = a.reg1[s1n + l];
         }
-        stratum_counts(a.Mpart, P, I3, L.Mk, msum, tid, NT);
-        reduce_items(a.Spart, P, ni, i0, i1, a.Ssum + i0, red, tid, NT);
+        if (tid < I3) msum[tid] = (double)cnt0;
+        for (int k = tid + NT; k < I3; k += NT) msum[k] = (double)a.scount[s * I3 + k];
+        if (one) {
+            // the order of reduce_items: each chunk's blocks ascending, then
+            // the chunks ascending
+            if (tid < (i1 - i0) * nchr) {
+                float cs = 0.f;
+#pragma unroll
+                for (int u = 0; u < kRedChunk; ++u) cs += rv[u];
+                red[tid] = cs;
+            }
+            __syncthreads();
+            if (tid < i1 - i0) {
+                float t = 0.f;
+                for (int ch = 0; ch < nchr; ++ch) t += red[tid * nchr + ch];
+                a.Ssum[i0 + tid] = t;
+            }
+        } else {
+            reduce_items(a.Spart, P, ni, i0, i1, a.Ssum + i0, red, tid, NT);
+        }
         if (!grid_sync(a.bar, P, nbar, flag)) return;
 
         for (int idx = tid; idx < ni; idx += NT) Sk[idx] = a.Ssum[idx];
@@ -1252,7 +1285,6 @@ __global__ __launch_bounds__(64 * NW) void block_step(StratArgs a)
     for (int idx = tid; idx < I3 * J3; idx += NT) Cs[idx] = a.C[idx];
     for (int idx = tid; idx < J12 * J3; idx += NT) Gs[idx] = a.G[idx];
     for (int idx = tid; idx < ni; idx += NT) Sk[idx] = 0.f;
-    for (int k = tid; k < I3; k += NT) L.Mk[k] = 0;
     __syncthreads();
     if constexpr (BF)
         build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Cs, Gs, I3, J1, J2, J3, tid, NT);
@@ -1268,7 +1300,6 @@ __global__ __launch_bounds__(64 * NW) void block_step(StratArgs a)
     __syncthreads();
     float* Sp = a.Spart + (size_t)p * ni;
     for (int idx = tid; idx < ni; idx += NT) Sp[idx] = Sk[idx];
-    for (int k = tid; k < I3; k += NT) a.Mpart[p * I3 + k] = L.Mk[k];
 }
 
 struct CoreLds {
@@ -1308,7 +1339,7 @@ __global__ __launch_bounds__(kCoreThreads) void core_step(StratArgs a, float* Gt
     float* cgt = lds + L.cgt;
     float* red = lds + L.red;
     double* msum = reinterpret_cast<double*>(lds + L.msum);
-    stratum_counts(a.Mpart, P, I3, reinterpret_cast<int*>(cgt), msum, tid, NT);
+    for (int k = tid; k < I3; k += NT) msum[k] = (double)a.scount[a.s * I3 + k];
     for (int idx = tid; idx < I3 * J3; idx += NT) C0[idx] = a.C[idx];
     reduce_items(a.Spart, P, ni, 0, ni, S, red, tid, NT);
     core_update(C0, a.G, S, msum, a.cnt3, I3, J12, J3, a.lam, a.etac, a.nnz, red, cgt, Gtmp, tid, NT);
