@@ -816,26 +816,29 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
 
 // The tiles of block (p, q) with BF16 matrix-core contractions (FP32
 // accumulation; factor rows, residuals and updates stay FP32).  Per tile:
-//   1. matrix-core wavefront w (the last four, w = 0..3) takes nonzeros
-//      16w..16w+15 as the rows of
-//      W1 = B_tile H_k^T and W2 = A_tile H_k (BF16 operands, one K step of
-//      32); it writes W1 in tile order and W2 in the tile's gene-sorted slot
-//      order, and x~ = a . w1 for its nonzeros (FP32 row sums);
-//   2. lane t of every wavefront forms e = x - x~, keeps its owned columns
-//      of a_i from before the tile and stages the BF16 operands a_i and
-//      e b_j of the S product;
-//   3. S on the matrix cores; the patient and gene runs are summed with the
-//      same segmented scans as the FP32 path, on e*w1 and e*w2;
-// with a barrier after each of the three steps.
+//   1. row block b = 0..3 (nonzeros 16b..16b+15) forms W1 = B_tile H_k^T
+//      and W2 = A_tile H_k on the matrix cores (BF16 operands, one K step
+//      of 32): W1 in tile order, W2 in the tile's gene-sorted slot order;
+//      the W1 wavefront also forms x~ = a . w1 (FP32 row sums) and
+//      e = x - x~ for its nonzeros, in tile order and in slot order.  With
+//      eight wavefronts, wavefronts 0..3 take W1 and 4..7 take W2 (and add
+//      the previous tile's S operands); with four, each takes both;
+//   -- barrier --
+//   2. every wavefront stages the BF16 operands a_i and e b_j of the S
+//      product for its columns and sums the patient and gene runs of e*w1
+//      and e*w2 with the segmented scans of the FP32 path;
+//   -- barrier --
 template <int JP, int NW>
 __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& L, int tid)
 {
+#pragma clang fp contract(off)
     constexpr int RS = strat_row_stride(JP, 1);
     constexpr int MP = mfma_dim(JP);
     constexpr int NB = MP / 16;
     constexpr int NT = 64 * NW;
     constexpr int QN = (JP + NW - 1) / NW;
     constexpr int QM = (MP + NW - 1) / NW;
+    constexpr bool kTwo = NW >= 2 * kMfmaWaves;  // W1 and W2 on different wavefronts
     const int lane = tid & 63, w = tid >> 6, g = lane >> 4, m = lane & 15;
     const int J1 = a.J1, J2 = a.J2, J12 = J1 * J2;
     const uint32_t mask_i = (1u << a.bits_i) - 1u, mask_j = (1u << a.bits_j) - 1u;
@@ -846,14 +849,18 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
 
     SAccB<MP> acc;
     acc.zero();
-    // the last four wavefronts (the fewest factor columns) form W1 and W2
-    // for 16 nonzeros each and accumulate S; mw numbers them 0..3
+    // the last four wavefronts accumulate S (mw = 0..3) and form W2; W1 and
+    // x~ fall to wavefronts 0..3
     const int mw = w - (NW - kMfmaWaves);
     const bool mfw = mw >= 0;
-    const bool pw = mfw;
+    const bool do1 = kTwo ? w < kMfmaWaves : true, do2 = mfw;
+    const int rb = kTwo ? (w & (kMfmaWaves - 1)) : mw;  // row block of W1 / W2
+    float* eT = L.xts;  // e in tile order
+    float* eS = L.eS;   // e in slot order
     int curk = -1;
-    int pend = -1;  // platform whose partial S waits in L.St
-    bf16x8 hb1[NB], hb2[NB];
+    int pend = -1;    // platform whose partial S waits in L.St
+    int prev_n = 0;   // nonzeros of the tile whose S operands wait in L.A16/L.E16
+    bf16x8 hb[NB];    // H_k^T (W1) or H_k (W2) operand of this wavefront
     int tl = t0;
     while (tl < t1) {
         const int base = tl;
@@ -869,6 +876,8 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
         const int n = L.tco[u + 1] - off;
         const int k = L.tck[u];
         const uint2* rec = L.rec + (off - z0);
+        // S of the previous tile (its platform is curk)
+        if (mfw && prev_n > 0) acc.accumulate(L.A16, L.E16, prev_n, mw, lane);
         if (k != curk) {
             if (curk >= 0) {
                 if (mfw) acc.store(L.St + mw * J12, J1, J2, mw, lane);
@@ -876,52 +885,88 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
             }
             acc.zero();
             curk = k;
-            if (pw) {
+        }
+        const bool act = lane < n;
+        const uint2 wv = act ? rec[lane] : make_uint2(0u, 0u);
+        const uint32_t wd = wv.x;
+        const int il = act ? (int)(wd & mask_i) : -1;
+        const int jl = act ? (int)((wd >> sh_j) & mask_j) : 0;
+        const int jrank = (int)(wd >> sh_r);
+        if (w == 0 && act) L.slotJ[jrank] = jl;
+
+        // 1. W1 with x~ and e, W2, for nonzeros 16 rb .. 16 rb + 15
+        if (do1 || do2) {
+            const int to = 16 * rb + m;
+            const bool ao = to < n;
+            const uint32_t wo = ao ? rec[to].x : 0u;
+            const floatx4 zero4 = floatx4{0.f, 0.f, 0.f, 0.f};
+            if (do1) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    hb[nb] = *reinterpret_cast<const bf16x8*>(L.Hb + ((2 * k) * MP + nb * 16 + m) * kKB + 8 * g);
+                const bf16x8 opb = row8_bf16<RS>(L.Bb + ((wo >> sh_j) & mask_j) * RS, 8 * g, ao);
+                int ilr[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int tr = 16 * rb + 4 * g + r;
+                    ilr[r] = tr < n ? (int)(rec[tr].x & mask_i) : 0;
+                }
+                float xp[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    hb1[nb] = *reinterpret_cast<const bf16x8*>(L.Hb + ((2 * k) * MP + nb * 16 + m) * kKB + 8 * g);
-                    hb2[nb] = *reinterpret_cast<const bf16x8*>(L.Hb + ((2 * k + 1) * MP + nb * 16 + m) * kKB + 8 * g);
+                    const floatx4 o1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opb, hb[nb], zero4, 0, 0, 0);
+                    const int c = nb * 16 + m;
+                    *reinterpret_cast<floatx4*>(L.sW1 + c * kTW + 16 * rb + 4 * g) = o1;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (c < JP) xp[r] = fmaf(L.Ab[ilr[r] * RS + c], o1[r], xp[r]);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) xp[r] = row_sum16(xp[r]);
+                // lane (g, m < 4) finishes nonzero 16 rb + 4 g + m
+                const int te = 16 * rb + 4 * g + m;
+                if (m < 4 && te < n) {
+                    const uint2 we = rec[te];
+                    const float xt = m == 0 ? xp[0] : (m == 1 ? xp[1] : (m == 2 ? xp[2] : xp[3]));
+                    const float ee = __uint_as_float(we.y) - xt;
+                    eT[te] = ee;
+                    eS[we.x >> sh_r] = ee;
+                }
+            }
+            if (do2) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    hb[nb] = *reinterpret_cast<const bf16x8*>(L.Hb + ((2 * k + 1) * MP + nb * 16 + m) * kKB + 8 * g);
+                const bf16x8 opa = row8_bf16<RS>(L.Ab + (wo & mask_i) * RS, 8 * g, ao);
+                int jrr[4];
+                bool actr[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int tr = 16 * rb + 4 * g + r;
+                    actr[r] = tr < n;
+                    jrr[r] = actr[r] ? (int)(rec[tr].x >> sh_r) : 0;
+                }
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const floatx4 o2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opa, hb[nb], zero4, 0, 0, 0);
+                    const int c = nb * 16 + m;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (actr[r]) L.sW2[c * kTW + jrr[r]] = o2[r];
                 }
             }
         }
-
-        // 1. W1, W2 and x~ for nonzeros 16w .. 16w+15
-        if (pw) {
-            const int to = 16 * mw + m;
-            const bool ao = to < n;
-            const uint32_t wo = ao ? rec[to].x : 0u;
-            const bf16x8 opb = row8_bf16<RS>(L.Bb + ((wo >> sh_j) & mask_j) * RS, 8 * g, ao);
-            const bf16x8 opa = row8_bf16<RS>(L.Ab + (wo & mask_i) * RS, 8 * g, ao);
-            int ilr[4], jrr[4];
-            bool actr[4];
+        // patient runs: heads and regularisation weights (records only)
+        const int il_up = dpp_move_i<kDppWaveShr1>(il), il_dn = dpp_move_i<kDppWaveShl1>(il);
+        const bool ifirst = act && (lane == 0 || il_up != il);
+        const bool ilast = act && (lane == 63 || il_dn != il);
+        const int ihead = run_head(__ballot(ifirst), lane);
+        const float icr = act ? (float)(lane - ihead + 1) * L.rA[il] : 0.f;
+        float aq[QN];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int tr = 16 * mw + 4 * g + r;
-                actr[r] = tr < n;
-                const uint32_t wr = actr[r] ? rec[tr].x : 0u;
-                ilr[r] = (int)(wr & mask_i);
-                jrr[r] = (int)(wr >> sh_r);
-            }
-            float xp[4] = {0.f, 0.f, 0.f, 0.f};
-            const floatx4 zero4 = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const floatx4 o1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opb, hb1[nb], zero4, 0, 0, 0);
-                const floatx4 o2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(opa, hb2[nb], zero4, 0, 0, 0);
-                const int c = nb * 16 + m;
-                *reinterpret_cast<floatx4*>(L.sW1 + c * kTW + 16 * mw + 4 * g) = o1;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    if (actr[r]) L.sW2[c * kTW + jrr[r]] = o2[r];
-                    if (c < JP) xp[r] = fmaf(L.Ab[ilr[r] * RS + c], o1[r], xp[r]);
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) xp[r] = row_sum16(xp[r]);
-            if (m < 4) {
-                const float v = m == 0 ? xp[0] : (m == 1 ? xp[1] : (m == 2 ? xp[2] : xp[3]));
-                L.xts[16 * mw + 4 * g + m] = v;
-            }
+        for (int qq = 0; qq < QN; ++qq) {
+            const int c = w + NW * qq;
+            aq[qq] = (c < JP && act) ? L.Ab[il * RS + c] : 0.f;
         }
         __syncthreads();
         if (pend >= 0) {
@@ -929,58 +974,31 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
             pend = -1;
         }
 
-        // 2. residual; owned columns of a_i before the tile; BF16 S operands
-        const bool act = lane < n;
-        const uint2 wv = act ? rec[lane] : make_uint2(0u, 0u);
-        const uint32_t wd = wv.x;
-        const int il = act ? (int)(wd & mask_i) : -1;
-        const int jl = act ? (int)((wd >> sh_j) & mask_j) : 0;
-        const int jrank = (int)(wd >> sh_r);
-        const float e = act ? __uint_as_float(wv.y) - L.xts[lane] : 0.f;
-        if (w == 0 && act) {
-            L.eS[jrank] = e;
-            L.slotJ[jrank] = jl;
-        }
-        float aq[QN];
-#pragma unroll
-        for (int qq = 0; qq < QN; ++qq) {
-            const int c = w + NW * qq;
-            aq[qq] = (c < JP && act) ? L.Ab[il * RS + c] : 0.f;
-        }
+        // 2. BF16 S operands; fixed-order run sums; owned columns
+        const float e = act ? eT[lane] : 0.f;
+        const float es = act ? eS[lane] : 0.f;
+        const int sj = act ? L.slotJ[lane] : -1;
 #pragma unroll
         for (int qm = 0; qm < QM; ++qm) {
             const int c = w + NW * qm;
             if (c >= MP) continue;
             float av_c = 0.f, eb_c = 0.f;
             if (c < JP && act) {
-                av_c = L.Ab[il * RS + c];
+                av_c = qm < QN ? aq[qm < QN ? qm : 0] : L.Ab[il * RS + c];
                 eb_c = e * L.Bb[jl * RS + c];
             }
             L.A16[c * kTB + lane] = (__bf16)av_c;
             L.E16[c * kTB + lane] = (__bf16)eb_c;
         }
-        __syncthreads();
-
-        // 3. S on the matrix cores; fixed-order run sums; owned row columns
-        if (mfw) acc.accumulate(L.A16, L.E16, n, mw, lane);
-        {
-            const int il_up = dpp_move_i<kDppWaveShr1>(il), il_dn = dpp_move_i<kDppWaveShl1>(il);
-            const bool ifirst = act && (lane == 0 || il_up != il);
-            const bool ilast = act && (lane == 63 || il_dn != il);
-            const int head = run_head(__ballot(ifirst), lane);
-            const float cr = act ? (float)(lane - head + 1) * L.rA[il] : 0.f;
 #pragma unroll
-            for (int qq = 0; qq < QN; ++qq) {
-                const int c = w + NW * qq;
-                if (c < JP) {
-                    const float v = seg_scan(e * L.sW1[c * kTW + lane], lane, head);
-                    if (ilast) L.Ab[il * RS + c] = fmaf(a.lr, v - cr * aq[qq], aq[qq]);
-                }
+        for (int qq = 0; qq < QN; ++qq) {
+            const int c = w + NW * qq;
+            if (c < JP) {
+                const float v = seg_scan(e * L.sW1[c * kTW + lane], lane, ihead);
+                if (ilast) L.Ab[il * RS + c] = fmaf(a.lr, v - icr * aq[qq], aq[qq]);
             }
         }
         {
-            const int sj = act ? L.slotJ[lane] : -1;
-            const float es = act ? L.eS[lane] : 0.f;
             const int sj_up = dpp_move_i<kDppWaveShr1>(sj), sj_dn = dpp_move_i<kDppWaveShl1>(sj);
             const bool jfirst = act && (lane == 0 || sj_up != sj);
             const bool jlast = act && (lane == 63 || sj_dn != sj);
@@ -998,9 +1016,11 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
                 }
             }
         }
+        prev_n = n;
         __syncthreads();
         }
     }
+    if (mfw && prev_n > 0) acc.accumulate(L.A16, L.E16, prev_n, mw, lane);
     if (mfw) acc.store(L.St + mw * J12, J1, J2, mw, lane);
     __syncthreads();
     stage_sum<true, MP>(L.St, L.Sk + curk * J12, J1, J2, tid, NT);
