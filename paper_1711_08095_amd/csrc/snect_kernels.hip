@@ -84,7 +84,7 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     L.c = o;     o = up4(o + I3 * J3);
     L.g = o;     o = up4(o + j12 * J3);
     const int f32 = bf ? 0 : 1;
-    L.h = o;     o = up4(o + f32 * I3 * jp * jp);
+    L.h = o;     o = up4(o + I3 * jp * jp);              // FP32 H_k (both paths)
     L.sb = o;    o = up4(o + f32 * jp * kTS);
     L.as = o;    o = up4(o + f32 * mp * kTS);
     L.es = o;    o = up4(o + f32 * mp * kTS);
@@ -145,19 +145,17 @@ __device__ void build_h(float* Hs, const float* Cs, const float* Gs, int I3, int
 // BF16 copies of H_k as the B operands of the matrix-core products
 // W1 = B_tile H_k^T and W2 = A_tile H_k: for platform k, Hb[(2k)(MP)(32)]
 // holds H_k[c][y] at (c, y) and Hb[(2k+1)(MP)(32)] holds H_k[x][c] at
-// (c, x), zero outside JP x JP.  Row c is read as 8 values per lane.
+// (c, x), zero outside J1 x J2.  Row c is read as 8 values per lane.  The
+// values are converted from the FP32 H_k that build_h formed.
 template <int JP>
-__device__ void build_hb(__bf16* Hb, const float* Cs, const float* Gs, int I3, int J1, int J2, int J3, int tid,
-                         int nthr)
+__device__ void build_hb(__bf16* Hb, const float* Hs, int I3, int J1, int J2, int tid, int nthr)
 {
     constexpr int MP = mfma_dim(JP);
     for (int idx = tid; idx < I3 * 2 * MP * kKB; idx += nthr) {
         const int y = idx % kKB, c = (idx / kKB) % MP, kw = idx / (kKB * MP), k = kw >> 1;
-        // entry (c, y) of H_k (kw even) or of H_k^T (kw odd), as build_h forms it
+        // entry (c, y) of H_k (kw even) or of H_k^T (kw odd)
         const int x0 = (kw & 1) ? y : c, y0 = (kw & 1) ? c : y;
-        float h = 0.f;
-        if (x0 < J1 && y0 < J2)
-            for (int t = 0; t < J3; ++t) h = fmaf(Gs[(x0 * J2 + y0) * J3 + t], Cs[k * J3 + t], h);
+        const float h = (x0 < J1 && y0 < J2) ? Hs[(k * JP + x0) * JP + y0] : 0.f;
         Hb[idx] = (__bf16)h;
     }
 }
@@ -1134,6 +1132,8 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
     float* red = lds + S.red;
     double* msum = reinterpret_cast<double*>(lds + S.msum);
     float* cgt = lds + S.cgt;
+    float* Cn = cgt;            // C and G after the stratum's core step
+    float* Gn = cgt + I3 * J3;
     int* flag = reinterpret_cast<int*>(lds + S.flag);
 
     for (int idx = tid; idx < a.rows1_max * RS; idx += NT) lds[S.a + idx] = 0.f;
@@ -1163,10 +1163,11 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
             load_rows(L.Ab, a.Ap, s1, r1, J1, RS, tid, NT);
             for (int l = tid; l < r1; l += NT) lds[S.ra + l] = a.reg1[s1 + l];
         }
-        if constexpr (BF)
-            build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Cs, Gs, I3, J1, J2, J3, tid, NT);
-        else
-            build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
+        build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
+        if constexpr (BF) {
+            __syncthreads();
+            build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Hs, I3, J1, J2, tid, NT);
+        }
         for (int idx = tid; idx < ni; idx += NT) Sk[idx] = 0.f;
         __syncthreads();
         if constexpr (BF)
@@ -1223,12 +1224,15 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
 
         for (int idx = tid; idx < ni; idx += NT) Sk[idx] = a.Ssum[idx];
         __syncthreads();
-        core_update(Cs, Gs, Sk, msum, a.cnt3, I3, J12, J3, a.lam, a.etac, a.nnz, red, cgt, cgt + I3 * J3, tid,
-                    NT);
+        core_update(Cs, Gs, Sk, msum, a.cnt3, I3, J12, J3, a.lam, a.etac, a.nnz, red, Cn, Gn, tid, NT);
         __syncthreads();
-        for (int idx = tid; idx < I3 * J3; idx += NT) Cs[idx] = cgt[idx];
-        for (int idx = tid; idx < J12 * J3; idx += NT) Gs[idx] = cgt[I3 * J3 + idx];
-        __syncthreads();
+        // the new C and G become current; the old buffers take the next step
+        float* t = Cs;
+        Cs = Cn;
+        Cn = t;
+        t = Gs;
+        Gs = Gn;
+        Gn = t;
     }
     store_rows(a.Bp, L.Bb, s2, r2, J2, RS, tid, NT);
     if (q == 0) {
@@ -1306,10 +1310,11 @@ __global__ __launch_bounds__(64 * NW) void block_step(StratArgs a)
     for (int idx = tid; idx < J12 * J3; idx += NT) Gs[idx] = a.G[idx];
     for (int idx = tid; idx < ni; idx += NT) Sk[idx] = 0.f;
     __syncthreads();
-    if constexpr (BF)
-        build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Cs, Gs, I3, J1, J2, J3, tid, NT);
-    else
-        build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
+    build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
+    if constexpr (BF) {
+        __syncthreads();
+        build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Hs, I3, J1, J2, tid, NT);
+    }
     __syncthreads();
     if constexpr (BF)
         block_tiles_bf<JP, NW>(a, p, q, L, tid);
