@@ -128,9 +128,11 @@ struct snect_problem {
     int32_t rows1_max = 0, rows2_max = 0, bits_i = 0, bits_j = 0, n_sub = 0, n_reg_wg = 0;
     double dmax = 0;
     size_t strata_lds = 0, block_lds = 0, loss_lds = 0, core_lds = 0;
+    size_t loss_cols_lds = 0;  // column-wise loss kernel (0: per-block kernel)
+    int loss_parts = 1;        // workgroups per gene block of the column-wise loss kernel
     int capacity = 0;
-    int rec_cap = 2048;       // records staged per LDS chunk
-    int rec_cap_max = 2048;   // the largest that fits
+    int rec_cap = kMaxRecCap;       // records staged per LDS chunk
+    int rec_cap_max = kMaxRecCap;   // the largest that fits
     int sweep_rec_cap = 0;    // record chunk inside a batched sweep (0: rec_cap_max)
     int nw = kDefaultWaves;   // wavefronts per stratum workgroup
     double plan_s = 0, upload_s = 0;
@@ -314,7 +316,7 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
     if ((int64_t)P * P * I3 >= (int64_t(1) << 31)) return set_err(ctx, SNECT_E_UNSUPPORTED, "too many blocks");
     const int bf = pa->precision == SNECT_PRECISION_BF16 ? 1 : 0;
     // the largest record chunk that still fits in LDS
-    int rec_cap = 2048;
+    int rec_cap = kMaxRecCap;
     while (rec_cap > kTileMax &&
            strata_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf, 8) > ctx->max_lds)
         rec_cap /= 2;
@@ -337,6 +339,13 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
     pr->seed = pa->seed;
     pr->rows1_max = rows1_max; pr->rows2_max = rows2_max; pr->bits_i = bits_i; pr->bits_j = bits_j;
     pr->strata_lds = slds; pr->block_lds = blds; pr->loss_lds = llds; pr->core_lds = clds;
+    {
+        // the column-wise loss kernel when a gene block's w1 table fits
+        // comfortably in LDS; about 1,024 workgroups in all
+        const size_t lc = loss_cols_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3);
+        pr->loss_cols_lds = (lc <= (size_t)96 * 1024 && lc <= ctx->max_lds) ? lc : 0;
+        pr->loss_parts = std::max(1, std::min(P, 1024 / P));
+    }
     pr->rec_cap = rec_cap;
     pr->rec_cap_max = rec_cap;
     pr->n_reg_wg = (I1 + 255) / 256 + (I2 + 255) / 256 + 1;
@@ -572,7 +581,7 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         he = he ? he : up(pr->d_adj_w, adj_w.data(), adj_w.size() * 4);
         he = he ? he : up(pr->d_deg, deg.data(), (size_t)I2 * 4);
         he = he ? he : hipStreamSynchronize(st);
-        he = he ? he : prepare_kernels(jp, llds, clds);
+        he = he ? he : prepare_kernels(jp, llds, clds, pr->loss_cols_lds);
         he = he ? he : configure_exec(pr, kDefaultWaves, rec_cap);
         for (int t = 0; t < 4 && he == hipSuccess; ++t) he = hipEventCreate(&pr->ev[t]);
         if (he != hipSuccess) {
@@ -659,7 +668,7 @@ static int run_loss(snect_problem* pr, const float* C, const float* G)
     la.n_reg_wg = pr->n_reg_wg;
     la.lam = pr->lam; la.lam_g = pr->lam_g;
     GraphArgs ga = graph_args(pr);
-    HIP_TRY(launch_loss(la, ga, pr->jp, pr->loss_lds, ctx->stream));
+    HIP_TRY(launch_loss(la, ga, pr->jp, pr->loss_lds, pr->loss_cols_lds, pr->loss_parts, ctx->stream));
     HIP_TRY(hipMemcpyAsync(pr->h_lossout, pr->d_lossout, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     return SNECT_OK;
 }

@@ -30,6 +30,7 @@ constexpr int kSlotBits = 6;
 constexpr int kMaxLocalBits = 32 - kSlotBits;
 constexpr int kTileMax = 64;    // one tile = one wavefront
 constexpr int kTileCache = 256; // tile metadata entries cached in LDS
+constexpr int kMaxRecCap = 2048; // largest record chunk staged in LDS
 constexpr int kRedChunk = 16;   // blocks summed per chunk in the stratum reduce
 constexpr int kCoreChunk = 16;  // core entries summed per chunk in the C step
 
@@ -127,6 +128,7 @@ struct GraphArgs {
 size_t strata_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3, int rec_cap,
                         int bf, int nw);
 size_t loss_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3);
+size_t loss_cols_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3);
 size_t core_lds_bytes(int I3, int J1, int J2, int J3, int threads);
 int jp_for(int J1, int J2);
 
@@ -142,10 +144,12 @@ hipError_t prepare_sweep(int bf, size_t lds);
 hipError_t launch_block(const StratArgs& a, int jp, int bf, int nw, size_t lds, hipStream_t st);
 hipError_t launch_core_step(const StratArgs& a, size_t lds, hipStream_t st);
 hipError_t launch_graph_step(const GraphArgs& a, int jp, hipStream_t st);
-hipError_t launch_loss(const LossArgs& a, const GraphArgs& g, int jp, size_t lds, hipStream_t st);
+// lds_cols > 0: the column-wise loss kernel on P * nparts workgroups
+hipError_t launch_loss(const LossArgs& a, const GraphArgs& g, int jp, size_t lds, size_t lds_cols, int nparts,
+                       hipStream_t st);
 hipError_t launch_permute(const float* src, float* dst, const int32_t* perm, int rows, int cols, int gather,
                           hipStream_t st);
-hipError_t prepare_kernels(int jp, size_t loss_lds, size_t core_lds);
+hipError_t prepare_kernels(int jp, size_t loss_lds, size_t core_lds, size_t loss_cols_lds);
 // Allows the stratum kernels of one variant more than 64 KB of LDS.
 hipError_t prepare_strata(int jp, int bf, int nw, size_t strata_lds);
 // Orthonormalisation of one mode (FP64 CholeskyQR2); see snect_qr.hip.

@@ -508,6 +508,21 @@ struct TileLds {
     uint2* rec;   // [rec_cap] staged records
 };
 
+// Tile metadata and records of the chunk of tiles starting at `base` (up to
+// kTileCache tiles whose records fit in rec_cap) into LDS; returns the
+// chunk's tile count.  Every thread of the workgroup calls it.
+__device__ inline int load_chunk(const StratArgs& a, const TileLds& L, int base, int t1, int tid, int nthr)
+{
+    load_tile_cache(a, L.tco, L.tck, base, t1, tid, nthr);
+    __syncthreads();
+    const int ntc = (t1 - base) < kTileCache ? (t1 - base) : kTileCache;
+    const int cend = __syncthreads_count(tid < ntc && L.tco[tid + 1] - L.tco[0] <= a.rec_cap);
+    const int z0 = L.tco[0], nrec = L.tco[cend] - z0;
+    load_records(L.rec, a.nz + z0, nrec, tid, nthr);
+    __syncthreads();
+    return cend;
+}
+
 // The block's S of one platform is staged: each matrix-core wavefront
 // stores its partial sums (St, kMfmaWaves x J1J2), and after the next
 // workgroup barrier every thread adds them up, wavefront 0 first, so the
@@ -605,7 +620,7 @@ template <int JP, int NW> struct TileSplit {
 // reads.  Products are not contracted into fused multiply-adds beyond the
 // explicit fmaf.
 template <int JP, int NW>
-__device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, int tid)
+__device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, int tid, int pre_cend)
 {
 #pragma clang fp contract(off)
     using SP = TileSplit<JP, NW>;
@@ -645,14 +660,9 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
     while (tl < t1) {
         // a chunk: up to kTileCache tiles whose records fit in rec_cap,
         // metadata and records brought into LDS with many loads in flight
-        const int base = tl;
-        load_tile_cache(a, L.tco, L.tck, base, t1, tid, NT);
-        __syncthreads();
-        const int ntc = (t1 - base) < kTileCache ? (t1 - base) : kTileCache;
-        const int cend = __syncthreads_count(tid < ntc && L.tco[tid + 1] - L.tco[0] <= a.rec_cap);
-        const int z0 = L.tco[0], nrec = L.tco[cend] - z0;
-        load_records(L.rec, a.nz + z0, nrec, tid, NT);
-        __syncthreads();
+        // (the first chunk may already be there: pre_cend tiles)
+        const int cend = (pre_cend > 0 && tl == t0) ? pre_cend : load_chunk(a, L, tl, t1, tid, NT);
+        const int z0 = L.tco[0];
         // each tile's records are read from LDS during the previous tile
         uint2 wv_next = lane < L.tco[1] - z0 ? L.rec[lane] : make_uint2(0u, 0u);
         for (int u = 0; u < cend; ++u, ++tl) {
@@ -827,7 +837,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
 //      and e*w2 with the segmented scans of the FP32 path;
 //   -- barrier --
 template <int JP, int NW>
-__device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& L, int tid)
+__device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& L, int tid, int pre_cend)
 {
 #pragma clang fp contract(off)
     constexpr int RS = strat_row_stride(JP, 1);
@@ -861,14 +871,8 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
     bf16x8 hb[NB];    // H_k^T (W1) or H_k (W2) operand of this wavefront
     int tl = t0;
     while (tl < t1) {
-        const int base = tl;
-        load_tile_cache(a, L.tco, L.tck, base, t1, tid, NT);
-        __syncthreads();
-        const int ntc = (t1 - base) < kTileCache ? (t1 - base) : kTileCache;
-        const int cend = __syncthreads_count(tid < ntc && L.tco[tid + 1] - L.tco[0] <= a.rec_cap);
-        const int z0 = L.tco[0], nrec = L.tco[cend] - z0;
-        load_records(L.rec, a.nz + z0, nrec, tid, NT);
-        __syncthreads();
+        const int cend = (pre_cend > 0 && tl == t0) ? pre_cend : load_chunk(a, L, tl, t1, tid, NT);
+        const int z0 = L.tco[0];
         for (int u = 0; u < cend; ++u, ++tl) {
         const int off = L.tco[u];
         const int n = L.tco[u + 1] - off;
@@ -1154,6 +1158,11 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
     const int i0 = (int)(((long long)ni * r) / P), i1 = (int)(((long long)ni * (r + 1)) / P);
     const int nchr = (P + kRedChunk - 1) / kRedChunk;
     const int rit = tid / nchr, rch = tid - rit * nchr;  // item and chunk of this thread's share
+    constexpr int kPreRec = (kMaxRecCap + NT - 65) / (NT - 64);  // records per thread of a prefetched chunk
+    // the next stratum's first chunk is prefetched across the second grid
+    // barrier except on the FP32 small-core path (no gain measured there)
+    constexpr bool kPrefetch = BF || !TileSplit<JP, NW>::kSplit;
+    int pre_cend = 0;  // tiles of this stratum's first chunk already in LDS
 
     for (int si = 0; si < P; ++si) {
         const int s = a.order[si];
@@ -1171,9 +1180,10 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
         for (int idx = tid; idx < ni; idx += NT) Sk[idx] = 0.f;
         __syncthreads();
         if constexpr (BF)
-            block_tiles_bf<JP, NW>(a, p, q, L, tid);
+            block_tiles_bf<JP, NW>(a, p, q, L, tid, pre_cend);
         else
-            block_tiles<JP, NW>(a, p, q, L, tid);
+            block_tiles<JP, NW>(a, p, q, L, tid, pre_cend);
+        pre_cend = 0;
         store_rows(a.Ap, L.Ab, s1, r1, J1, RS, tid, NT);
         __syncthreads();
         float* Sp = a.Spart + (size_t)p * ni;
@@ -1194,11 +1204,34 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
                 rv[u] = rt && p0 + u < P ? a.Spart[(size_t)(p0 + u) * ni + i0 + rit] : 0.f;
         }
         const int cnt0 = tid < I3 ? a.scount[s * I3 + tid] : 0;
+        int tn0 = 0, tn1 = 0;  // tiles of the next stratum's block
         if (si + 1 < P) {
             const int pn = (q - a.order[si + 1] + P) % P;
+            if constexpr (kPrefetch) {
+                tn0 = a.blk_tile[pn * P + q];
+                tn1 = a.blk_tile[pn * P + q + 1];
+            }
+            // its tile metadata (as load_tile_cache lays it out), loaded
+            // together with its patient rows
+            constexpr int kTC = (kTileCache + NT) / NT;
+            int tov[kTC], tkv[kTC];
+#pragma unroll
+            for (int h = 0; h < kTC; ++h) {
+                const int u = tid + h * NT, t = tn0 + u;
+                tov[h] = tn0 < tn1 && u <= kTileCache && t <= tn1 ? a.tile_off[t] : 0;
+                tkv[h] = tn0 < tn1 && u < kTileCache && t < tn1 ? a.tile_k[t] : 0;
+            }
             const int s1n = a.start1[pn], r1n = a.start1[pn + 1] - s1n;
             load_rows(L.Ab, a.Ap, s1n, r1n, J1, RS, tid, NT);
             for (int l = tid; l < r1n; l += NT) lds[S.ra + l] = a.reg1[s1n + l];
+            if (tn0 < tn1) {
+#pragma unroll
+                for (int h = 0; h < kTC; ++h) {
+                    const int u = tid + h * NT;
+                    if (u <= kTileCache) L.tco[u] = tov[h];
+                    if (u < kTileCache) L.tck[u] = tkv[h];
+                }
+            }
         }
         if (tid < I3) msum[tid] = (double)cnt0;
         for (int k = tid + NT; k < I3; k += NT) msum[k] = (double)a.scount[s * I3 + k];
@@ -1220,7 +1253,31 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
         } else {
             reduce_items(a.Spart, P, ni, i0, i1, a.Ssum + i0, red, tid, NT);
         }
+        // the next stratum's first chunk: its tile count now (the metadata
+        // arrived with the loads above), its records in flight across the
+        // second barrier, into LDS after it.  Wavefront 0 takes no part: its
+        // barrier arrival waits for all of its outstanding memory operations.
+        const int pt = tid - 64;
+        uint2 rr[kPreRec];
+        if (tn0 < tn1) {
+            const int ntc = (tn1 - tn0) < kTileCache ? (tn1 - tn0) : kTileCache;
+            pre_cend = __syncthreads_count(tid < ntc && L.tco[tid + 1] - L.tco[0] <= a.rec_cap);
+            const int z0 = L.tco[0], nrec = L.tco[pre_cend] - z0;
+#pragma unroll
+            for (int u = 0; u < kPreRec; ++u) {
+                const int i = pt + u * (NT - 64);
+                rr[u] = pt >= 0 && i < nrec ? a.nz[z0 + i] : make_uint2(0u, 0u);
+            }
+        }
         if (!grid_sync(a.bar, P, nbar, flag)) return;
+        if (pre_cend > 0) {
+            const int nrec = L.tco[pre_cend] - L.tco[0];
+#pragma unroll
+            for (int u = 0; u < kPreRec; ++u) {
+                const int i = pt + u * (NT - 64);
+                if (pt >= 0 && i < nrec) L.rec[i] = rr[u];
+            }
+        }
 
         for (int idx = tid; idx < ni; idx += NT) Sk[idx] = a.Ssum[idx];
         __syncthreads();
@@ -1317,9 +1374,9 @@ __global__ __launch_bounds__(64 * NW) void block_step(StratArgs a)
     }
     __syncthreads();
     if constexpr (BF)
-        block_tiles_bf<JP, NW>(a, p, q, L, tid);
+        block_tiles_bf<JP, NW>(a, p, q, L, tid, 0);
     else
-        block_tiles<JP, NW>(a, p, q, L, tid);
+        block_tiles<JP, NW>(a, p, q, L, tid, 0);
     store_rows(a.Ap, L.Ab, s1, r1, J1, RS, tid, NT);
     store_rows(a.Bp, L.Bb, s2, r2, J2, RS, tid, NT);
     __syncthreads();
@@ -1530,6 +1587,125 @@ __global__ __launch_bounds__(256) void loss_blocks(LossArgs a)
     if (tid == 0) a.sse_part[blk] = s;
 }
 
+// The same sums of squared residuals, column by column: workgroup (q, part)
+// keeps gene block q and first forms w1 = H_k b_j for every gene row of the
+// block and every platform k (the values loss_blocks forms per nonzero, in
+// the same operation order), then visits patient blocks p0..p1-1.  Per
+// nonzero only x~ = a_i . w1 remains (JP instead of JP^2 + JP fused
+// multiply-adds).  Tiles go to wavefronts and lanes as in loss_blocks and
+// each block's sum is the same tree, so sse_part is bit-identical.
+constexpr int kLossChunkTiles = 16;  // tiles whose records are staged at once
+
+struct LossColLds {
+    int w, a, u, b, h, g, c, rec, red, total;
+};
+
+__host__ __device__ inline LossColLds loss_col_layout(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2,
+                                                      int J3)
+{
+    LossColLds L;
+    int o = 0;
+    L.w = o;   o = up4(o + rows2_max * I3 * jp);      // w1 per gene row and platform
+    L.a = o;   o = up4(o + rows1_max * jp);           // patient rows of the current block
+    L.c = o;   o = up4(o + I3 * J3);
+    L.red = o; o = up4(o + 2 * 256);
+    // set-up only (gene rows, H_k, G) and then the staged records
+    const int setup = up4(rows2_max * jp) + up4(I3 * jp * jp) + up4(J1 * J2 * J3);
+    const int recs = 2 * kLossChunkTiles * kTileMax;
+    L.u = o;
+    L.b = o;
+    L.h = L.b + up4(rows2_max * jp);
+    L.g = L.h + up4(I3 * jp * jp);
+    L.rec = o;
+    o = up4(o + (setup > recs ? setup : recs));
+    L.total = o;
+    return L;
+}
+
+size_t loss_cols_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3)
+{
+    return align16(4 * (size_t)loss_col_layout(jp, rows1_max, rows2_max, I3, J1, J2, J3).total);
+}
+
+template <int JP>
+__global__ __launch_bounds__(256) void loss_cols(LossArgs a)
+{
+    constexpr int NT = 256;
+    extern __shared__ float lds[];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int P = a.P, q = blockIdx.x % P, part = blockIdx.x / P, nparts = gridDim.x / P;
+    const int p0 = (int)(((long long)P * part) / nparts), p1 = (int)(((long long)P * (part + 1)) / nparts);
+    const int I3 = a.I3, J1 = a.J1, J2 = a.J2, J3 = a.J3;
+    const LossColLds L = loss_col_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3);
+    float* W = lds + L.w;
+    float* Ab = lds + L.a;
+    float* Bt = lds + L.b;
+    float* Hs = lds + L.h;
+    float* Gs = lds + L.g;
+    float* Cs = lds + L.c;
+    uint2* rec = reinterpret_cast<uint2*>(lds + L.rec);
+    double* red = reinterpret_cast<double*>(lds + L.red);
+
+    // set-up: gene rows (zero beyond J2), H_k, then w1 for every (row, k)
+    for (int idx = tid; idx < a.rows1_max * JP; idx += NT) Ab[idx] = 0.f;
+    for (int idx = tid; idx < a.rows2_max * JP; idx += NT) Bt[idx] = 0.f;
+    for (int idx = tid; idx < I3 * J3; idx += NT) Cs[idx] = a.C[idx];
+    for (int idx = tid; idx < J1 * J2 * J3; idx += NT) Gs[idx] = a.G[idx];
+    __syncthreads();
+    const int s2 = a.start2[q], r2 = a.start2[q + 1] - s2;
+    load_rows(Bt, a.Bp, s2, r2, J2, JP, tid, NT);
+    build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
+    __syncthreads();
+    for (int idx = tid; idx < r2 * I3 * JP; idx += NT) {
+        const int l = idx / (I3 * JP), kx = idx - l * (I3 * JP), k = kx / JP, x = kx - k * JP;
+        const float* H = Hs + (k * JP + x) * JP;
+        const float* bv = Bt + l * JP;
+        float w1 = 0.f;
+#pragma unroll
+        for (int y = 0; y < JP; ++y) w1 = fmaf(H[y], bv[y], w1);
+        W[idx] = w1;
+    }
+    __syncthreads();
+
+    const uint32_t mask_i = (1u << a.bits_i) - 1u, mask_j = (1u << a.bits_j) - 1u;
+    for (int p = p0; p < p1; ++p) {
+        const int blk = p * P + q;
+        const int t0 = a.blk_tile[blk], t1 = a.blk_tile[blk + 1];
+        if (t0 >= t1) {
+            if (tid == 0) a.sse_part[blk] = 0.0;
+            continue;
+        }
+        const int s1 = a.start1[p], r1 = a.start1[p + 1] - s1;
+        load_rows(Ab, a.Ap, s1, r1, J1, JP, tid, NT);
+        double acc = 0.0;
+        // wavefront w takes the tiles t0 + w, t0 + w + 4, ... (chunks hold a
+        // multiple of four tiles)
+        for (int c0 = t0; c0 < t1; c0 += kLossChunkTiles) {
+            const int c1 = c0 + kLossChunkTiles < t1 ? c0 + kLossChunkTiles : t1;
+            const int z0 = a.tile_off[c0], nrec = a.tile_off[c1] - z0;
+            load_records(rec, a.nz + z0, nrec, tid, NT);
+            __syncthreads();
+            for (int tl = c0 + wave; tl < c1; tl += 4) {
+                const int off = a.tile_off[tl], n = a.tile_off[tl + 1] - off, k = a.tile_k[tl];
+                if (lane < n) {
+                    const uint2 wv = rec[off - z0 + lane];
+                    const int il = (int)(wv.x & mask_i), jl = (int)((wv.x >> a.bits_i) & mask_j);
+                    const float* w1 = W + (jl * I3 + k) * JP;
+                    const float* av = Ab + il * JP;
+                    float xt = 0.f;
+#pragma unroll
+                    for (int x_ = 0; x_ < JP; ++x_) xt = fmaf(av[x_], w1[x_], xt);
+                    const float e = __uint_as_float(wv.y) - xt;
+                    acc += (double)e * (double)e;
+                }
+            }
+            __syncthreads();
+        }
+        const double s = block_sum_256(acc, red, tid);
+        if (tid == 0) a.sse_part[blk] = s;
+    }
+}
+
 // L2 terms: workgroups [0, nA) take patient rows, [nA, nA+nB) gene rows, the
 // last one the platform rows and the core.
 __global__ __launch_bounds__(256) void loss_reg(LossArgs a)
@@ -1690,9 +1866,13 @@ hipError_t launch_graph_step(const GraphArgs& g, int jp, hipStream_t st)
 }
 
 template <int JP>
-static hipError_t launch_loss_t(const LossArgs& a, const GraphArgs& g, size_t lds, hipStream_t st)
+static hipError_t launch_loss_t(const LossArgs& a, const GraphArgs& g, size_t lds, size_t lds_cols, int nparts,
+                                hipStream_t st)
 {
-    hipLaunchKernelGGL(loss_blocks<JP>, dim3(a.P * a.P), dim3(256), lds, st, a);
+    if (lds_cols > 0)
+        hipLaunchKernelGGL(loss_cols<JP>, dim3(a.P * nparts), dim3(256), lds_cols, st, a);
+    else
+        hipLaunchKernelGGL(loss_blocks<JP>, dim3(a.P * a.P), dim3(256), lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(loss_reg, dim3(a.n_reg_wg), dim3(256), 0, st, a);
@@ -1706,9 +1886,10 @@ static hipError_t launch_loss_t(const LossArgs& a, const GraphArgs& g, size_t ld
     return hipGetLastError();
 }
 
-hipError_t launch_loss(const LossArgs& a, const GraphArgs& g, int jp, size_t lds, hipStream_t st)
+hipError_t launch_loss(const LossArgs& a, const GraphArgs& g, int jp, size_t lds, size_t lds_cols, int nparts,
+                       hipStream_t st)
 {
-#define CALL_L(J) launch_loss_t<J>(a, g, lds, st)
+#define CALL_L(J) launch_loss_t<J>(a, g, lds, lds_cols, nparts, st)
     SNECT_JP_SWITCH(jp, CALL_L)
 #undef CALL_L
 }
@@ -1751,22 +1932,25 @@ hipError_t prepare_strata(int jp, int bf, int nw, size_t slds)
 }
 
 template <int JP>
-static hipError_t prepare_t(size_t llds, size_t clds)
+static hipError_t prepare_t(size_t llds, size_t clds, size_t lcols)
 {
     hipError_t e = hipSuccess;
     const int limit = 65536;
     if (llds > (size_t)limit)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&loss_blocks<JP>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)llds);
+    if (e == hipSuccess && lcols > (size_t)limit)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&loss_cols<JP>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lcols);
     if (e == hipSuccess && clds > (size_t)limit)
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&core_step), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)clds);
     return e;
 }
 
-hipError_t prepare_kernels(int jp, size_t llds, size_t clds)
+hipError_t prepare_kernels(int jp, size_t llds, size_t clds, size_t lcols)
 {
-#define CALL_R(J) prepare_t<J>(llds, clds)
+#define CALL_R(J) prepare_t<J>(llds, clds, lcols)
     SNECT_JP_SWITCH(jp, CALL_R)
 #undef CALL_R
 }
