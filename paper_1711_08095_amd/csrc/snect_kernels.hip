@@ -63,7 +63,7 @@ __device__ inline void lds_order_fence() { asm volatile("" ::: "memory"); }
 // LDS carve-up of the stratum kernels (in 4-byte words).
 // ---------------------------------------------------------------------------
 struct StratLds {
-    int a, b, ra, rb, c, g, h, sb, as, es, xtp, slotj, stg, sk, tco, tck, red, msum, cgt, flag, rec;
+    int a, b, ra, rb, c, g, h, ht, sb, as, es, xtp, slotj, stg, sk, tco, tck, red, msum, cgt, flag, rec;
     int hb, sw1, sw2, xts, esl, a16, e16;  // BF16 path only (zero-sized otherwise)
     int total;
 };
@@ -85,6 +85,8 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     L.g = o;     o = up4(o + j12 * J3);
     const int f32 = bf ? 0 : 1;
     L.h = o;     o = up4(o + I3 * jp * jp);              // FP32 H_k (both paths)
+    const int tr = (!bf && jp > 12) ? 1 : 0;
+    L.ht = o;    o = up4(o + tr * I3 * jp * jp);         // H_k^T (FP32 path, JP > 12)
     L.sb = o;    o = up4(o + f32 * jp * kTS);
     L.as = o;    o = up4(o + f32 * mp * kTS);
     L.es = o;    o = up4(o + f32 * mp * kTS);
@@ -131,7 +133,7 @@ int jp_for(int J1, int J2)
 // H_k[x][y] = sum_c G[x,y,c] C[k,c], zero padded to JP x JP.
 template <int JP>
 __device__ void build_h(float* Hs, const float* Cs, const float* Gs, int I3, int J1, int J2, int J3, int tid,
-                        int nthr)
+                        int nthr, float* Ht = nullptr)
 {
     for (int idx = tid; idx < I3 * JP * JP; idx += nthr) {
         const int k = idx / (JP * JP), xy = idx - k * JP * JP, x = xy / JP, y = xy - x * JP;
@@ -139,6 +141,7 @@ __device__ void build_h(float* Hs, const float* Cs, const float* Gs, int I3, int
         if (x < J1 && y < J2)
             for (int c = 0; c < J3; ++c) h = fmaf(Gs[(x * J2 + y) * J3 + c], Cs[k * J3 + c], h);
         Hs[idx] = h;
+        if (Ht) Ht[(k * JP + y) * JP + x] = h;  // H_k^T, row y
     }
 }
 
@@ -493,7 +496,7 @@ __device__ inline int run_head(unsigned long long heads, int lane)
 
 struct TileLds {
     float *Ab, *Bb;
-    const float *rA, *rB, *Hs;
+    const float *rA, *rB, *Hs, *Ht;
     float *sB, *As, *Es, *xtp;
     // BF16 path: H_k and H_k^T as matrix-core B operands, raw w1 (tile order)
     // and w2 (slot order) columns, x~ per nonzero, e in slot order, staged
@@ -716,8 +719,14 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
 #pragma unroll
                         for (int y = 0; y < JP; ++y) t = fmaf(hh[qq][y], bv[y], t);
                     } else {
+                        // row c of H_k, four values per read
+                        const floatx4* H4 = reinterpret_cast<const floatx4*>(H + c * JP);
 #pragma unroll
-                        for (int y = 0; y < JP; ++y) t = fmaf(H[c * JP + y], bv[y], t);
+                        for (int y4 = 0; y4 < JP / 4; ++y4) {
+                            const floatx4 h4 = H4[y4];
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) t = fmaf(h4[r], bv[4 * y4 + r], t);
+                        }
                     }
                     ac = act ? L.Ab[il * RS + c] : 0.f;
                     bc = act ? L.Bb[jl * RS + c] : 0.f;
@@ -742,8 +751,14 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
 #pragma unroll
                         for (int x_ = 0; x_ < JP; ++x_) t = fmaf(av[x_], hh[qq][x_], t);
                     } else {
+                        // column c of H_k: row c of H_k^T, four values per read
+                        const floatx4* H4 = reinterpret_cast<const floatx4*>(L.Ht + (k * JP + c) * JP);
 #pragma unroll
-                        for (int x_ = 0; x_ < JP; ++x_) t = fmaf(av[x_], H[x_ * JP + c], t);
+                        for (int x4 = 0; x4 < JP / 4; ++x4) {
+                            const floatx4 h4 = H4[x4];
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) t = fmaf(av[4 * x4 + r], h4[r], t);
+                        }
                     }
                 }
                 w2q[qq] = t;
@@ -1094,6 +1109,7 @@ __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
     L.rA = lds + S.ra;
     L.rB = lds + S.rb;
     L.Hs = lds + S.h;
+    L.Ht = lds + S.ht;
     L.sB = lds + S.sb;
     L.As = lds + S.as;
     L.Es = lds + S.es;
@@ -1172,7 +1188,7 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
             load_rows(L.Ab, a.Ap, s1, r1, J1, RS, tid, NT);
             for (int l = tid; l < r1; l += NT) lds[S.ra + l] = a.reg1[s1 + l];
         }
-        build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
+        build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT, (!BF && JP > 12) ? lds + S.ht : nullptr);
         if constexpr (BF) {
             __syncthreads();
             build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Hs, I3, J1, J2, tid, NT);
@@ -1367,7 +1383,7 @@ __global__ __launch_bounds__(64 * NW) void block_step(StratArgs a)
     for (int idx = tid; idx < J12 * J3; idx += NT) Gs[idx] = a.G[idx];
     for (int idx = tid; idx < ni; idx += NT) Sk[idx] = 0.f;
     __syncthreads();
-    build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT);
+    build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT, (!BF && JP > 12) ? lds + S.ht : nullptr);
     if constexpr (BF) {
         __syncthreads();
         build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Hs, I3, J1, J2, tid, NT);
