@@ -228,11 +228,6 @@ int snect_server_submit(snect_server* s, int64_t nnz, const int32_t* j, const in
 {
     if (!s || !ticket || nnz < 0 || nnz >= (int64_t(1) << 31) || (nnz > 0 && (!j || !k || !x)))
         return srv_err(s, SNECT_E_ARG, "bad request arguments");
-    for (int64_t t = 0; t < nnz; ++t) {
-        if (j[t] < 0 || j[t] >= s->I2 || k[t] < 0 || k[t] >= s->I3)
-            return srv_err(s, SNECT_E_INDEX, "request cell out of range");
-        if (!std::isfinite(x[t])) return srv_err(s, SNECT_E_ARG, "non-finite request value");
-    }
     int free_slot = -1;
     for (size_t i = 0; i < s->slots.size(); ++i)
         if (!s->slots[i].busy) {
@@ -242,8 +237,6 @@ int snect_server_submit(snect_server* s, int64_t nnz, const int32_t* j, const in
     const size_t bj = align_up((size_t)nnz * 4), bytes = std::max<size_t>(3 * bj, kAlign);
     if (bytes > s->pool.size) return srv_err(s, SNECT_E_UNSUPPORTED, "request larger than the request pool");
     if (free_slot < 0) return srv_err(s, SNECT_E_BUSY, "no free slot");
-    size_t off = 0;
-    if (!s->pool.take(bytes, &off)) return srv_err(s, SNECT_E_BUSY, "request pool full");
     Slot& sl = s->slots[free_slot];
     (void)hipSetDevice(s->device);
     if (sl.h_in_cap < bytes) {
@@ -252,16 +245,34 @@ int snect_server_submit(snect_server* s, int64_t nnz, const int32_t* j, const in
         sl.h_in_cap = 0;
         if (hipHostMalloc((void**)&sl.h_in, bytes, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
-            s->pool.give(off, bytes);
             return srv_err(s, SNECT_E_OOM, "pinned staging allocation failed");
         }
         sl.h_in_cap = bytes;
     }
-    if (nnz > 0) {
-        std::memcpy(sl.h_in, j, (size_t)nnz * 4);
-        std::memcpy(sl.h_in + bj, k, (size_t)nnz * 4);
-        std::memcpy(sl.h_in + 2 * bj, x, (size_t)nnz * 4);
+    // copy the cells to the slot's pinned staging and check them in the same
+    // branch-free pass (vectorised)
+    {
+        int32_t* hj = reinterpret_cast<int32_t*>(sl.h_in);
+        int32_t* hk = reinterpret_cast<int32_t*>(sl.h_in + bj);
+        float* hx = reinterpret_cast<float*>(sl.h_in + 2 * bj);
+        const uint32_t I2 = (uint32_t)s->I2, I3 = (uint32_t)s->I3;
+        uint32_t bad_index = 0, bad_value = 0;
+        for (int64_t t = 0; t < nnz; ++t) {
+            const int32_t jt = j[t], kt = k[t];
+            const float xt = x[t];
+            uint32_t xb;
+            std::memcpy(&xb, &xt, 4);
+            bad_index |= (uint32_t)((uint32_t)jt >= I2) | (uint32_t)((uint32_t)kt >= I3);
+            bad_value |= (uint32_t)((xb & 0x7f800000u) == 0x7f800000u);  // Inf or NaN
+            hj[t] = jt;
+            hk[t] = kt;
+            hx[t] = xt;
+        }
+        if (bad_index) return srv_err(s, SNECT_E_INDEX, "request cell out of range");
+        if (bad_value) return srv_err(s, SNECT_E_ARG, "non-finite request value");
     }
+    size_t off = 0;
+    if (!s->pool.take(bytes, &off)) return srv_err(s, SNECT_E_BUSY, "request pool full");
     char* dbase = s->d_pool + off;
     hipError_t e = hipSuccess;
     if (nnz > 0) e = hipMemcpyAsync(dbase, sl.h_in, 3 * bj, hipMemcpyHostToDevice, sl.stream);
@@ -321,25 +332,8 @@ int snect_server_replay(snect_server* s, int64_t nreq, const double* arrival_s, 
     int64_t next = 0, done = 0;
     const double t0 = now_s();
     while (done < nreq) {
-        const double now = now_s() - t0;
-        // admit every arrived request that fits, in arrival order
-        while (next < nreq && arrival_s[next] <= now) {
-            const int64_t a = offsets[next], n = offsets[next + 1] - a;
-            int64_t tk = -1;
-            const int rc = snect_server_submit(s, n, j + a, k + a, x + a, &tk);
-            if (rc == SNECT_E_BUSY) break;  // retry after completions
-            if (rc != SNECT_OK) {           // a malformed request fails alone
-                latency_s[next] = now - arrival_s[next];
-                if (status) status[next] = rc;
-                ++next;
-                ++done;
-                continue;
-            }
-            tick[next] = tk;
-            inflight.push_back(next);
-            ++next;
-        }
-        // completions
+        // completions first, so that a finished request is timed before the
+        // host prepares the next ones
         for (size_t t = 0; t < inflight.size();) {
             const int64_t r = inflight[t];
             const int rc = snect_server_poll(s, tick[r], u ? u + r * J1 : nullptr, idx ? idx + r * K : nullptr,
@@ -353,6 +347,24 @@ int snect_server_replay(snect_server* s, int64_t nreq, const double* arrival_s, 
             ++done;
             inflight[t] = inflight.back();
             inflight.pop_back();
+        }
+        // admit every arrived request that fits, in arrival order
+        const double now = now_s() - t0;
+        while (next < nreq && arrival_s[next] <= now) {
+            const int64_t a = offsets[next], n = offsets[next + 1] - a;
+            int64_t tk = -1;
+            const int rc = snect_server_submit(s, n, j + a, k + a, x + a, &tk);
+            if (rc == SNECT_E_BUSY) break;  // retry after completions
+            if (rc != SNECT_OK) {           // a malformed request fails alone
+                latency_s[next] = (now_s() - t0) - arrival_s[next];
+                if (status) status[next] = rc;
+                ++next;
+                ++done;
+                continue;
+            }
+            tick[next] = tk;
+            inflight.push_back(next);
+            ++next;
         }
     }
     if (wall_s) *wall_s = now_s() - t0;
