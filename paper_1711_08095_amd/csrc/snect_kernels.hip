@@ -63,7 +63,7 @@ __device__ inline void lds_order_fence() { asm volatile("" ::: "memory"); }
 // LDS carve-up of the stratum kernels (in 4-byte words).
 // ---------------------------------------------------------------------------
 struct StratLds {
-    int a, b, ra, rb, c, g, h, ht, sb, as, es, xtp, slotj, stg, sk, tco, tck, red, msum, cgt, flag, rec;
+    int a, b, ra, rb, c, g, h, ht, as, es, xtp, slotj, stg, sk, tco, tck, red, msum, cgt, flag, rec;
     int hb, sw1, sw2, xts, esl, a16, e16;  // BF16 path only (zero-sized otherwise)
     int total;
 };
@@ -87,7 +87,6 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     L.h = o;     o = up4(o + I3 * jp * jp);              // FP32 H_k (both paths)
     const int tr = (!bf && jp > 12) ? 1 : 0;
     L.ht = o;    o = up4(o + tr * I3 * jp * jp);         // H_k^T (FP32 path, JP > 12)
-    L.sb = o;    o = up4(o + f32 * jp * kTS);
     L.as = o;    o = up4(o + f32 * mp * kTS);
     L.es = o;    o = up4(o + f32 * mp * kTS);
     L.xtp = o;   o = up4(o + f32 * jp * kTileMax);          // a_c w1_c per column
@@ -497,7 +496,7 @@ __device__ inline int run_head(unsigned long long heads, int lane)
 struct TileLds {
     float *Ab, *Bb;
     const float *rA, *rB, *Hs, *Ht;
-    float *sB, *As, *Es, *xtp;
+    float *As, *Es, *xtp;
     // BF16 path: H_k and H_k^T as matrix-core B operands, raw w1 (tile order)
     // and w2 (slot order) columns, x~ per nonzero, e in slot order, staged
     // BF16 operands of the S product
@@ -614,9 +613,9 @@ template <int JP, int NW> struct TileSplit {
 //   -- barrier --
 //   2. every wavefront sums x~ over ascending columns and forms e; patient
 //      tasks stage the S operands and sum their runs of e w1_c in
-//      registers; gene tasks sum their runs of e w2_c through their own
-//      columns of the slot-ordered buffer; the last lane of a run writes
-//      the row;
+//      registers; gene tasks push e w2_c to slot order within the
+//      wavefront (ds_permute) and sum their runs there; the last lane of a
+//      run writes the row;
 //   -- barrier --
 // The matrix-core wavefronts add a tile's S operands at the start of the
 // next tile, so the product overlaps the next tile's row
@@ -700,7 +699,6 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
         const int il = act ? (int)(wd & mask_i) : -1;
         const int jl = act ? (int)((wd >> sh_j) & mask_j) : 0;
         const int jrank = (int)(wd >> sh_r);
-        if (w == 0 && act) L.slotJ[jrank] = jl;
 
         // 1. the rows from before the tile: b_j for patient tasks
         //    (w1 = H_k b), a_i for gene tasks (w2 = H_k^T a)
@@ -736,6 +734,28 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
                 aq[qq] = ac;
                 bq[qq] = bc;
                 if constexpr (JP > 16) lds_order_fence();
+            }
+        }
+        // gene runs, in the tile's gene-sorted slot order: slot s learns its
+        // gene row from the lane that holds it (inactive lanes push to their
+        // own slot, so the 64 pushes form a permutation), then the run heads,
+        // the regularisation weights and the rows' values before the tile
+        const int jr = act ? jrank : lane;
+        int sj = -1, jhead = 0;
+        bool jlast = false;
+        float jcr = 0.f, bp[QJ];
+        if (hj) {
+            sj = __builtin_amdgcn_ds_permute(jr << 2, act ? jl : -1);
+            const bool sact = lane < n;
+            const int sj_up = dpp_move_i<kDppWaveShr1>(sj), sj_dn = dpp_move_i<kDppWaveShl1>(sj);
+            const bool jfirst = sact && (lane == 0 || sj_up != sj);
+            jlast = sact && (lane == 63 || sj_dn != sj);
+            jhead = run_head(__ballot(jfirst), lane);
+            jcr = sact ? (float)(lane - jhead + 1) * L.rB[sj] : 0.f;
+#pragma unroll
+            for (int qq = 0; qq < QJ; ++qq) {
+                const int c = rj + NJ * qq;
+                bp[qq] = (sact && c < JP) ? L.Bb[sj * RS + c] : 0.f;
             }
         }
         if (hj) {
@@ -799,30 +819,14 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
             }
         }
         if (hj) {
-            // gene runs in the tile's gene-sorted slot order: the wavefront
-            // scatters e w2 of its own columns to slot order and reads it
-            // back (its own LDS columns: no barrier needed)
-#pragma unroll
-            for (int qq = 0; qq < QJ; ++qq) {
-                const int c = rj + NJ * qq;
-                if (c < JP && act) L.sB[c * kTS + jrank] = e * w2q[qq];
-            }
-            lds_order_fence();
-            const int sj = lane < n ? L.slotJ[lane] : -1;
-            const int sj_up = dpp_move_i<kDppWaveShr1>(sj), sj_dn = dpp_move_i<kDppWaveShl1>(sj);
-            const bool jfirst = lane < n && (lane == 0 || sj_up != sj);
-            const bool jlast = lane < n && (lane == 63 || sj_dn != sj);
-            const int head = run_head(__ballot(jfirst), lane);
-            const float cr = lane < n ? (float)(lane - head + 1) * L.rB[sj] : 0.f;
+            // e w2 of the wavefront's columns pushed to slot order
 #pragma unroll
             for (int qq = 0; qq < QJ; ++qq) {
                 const int c = rj + NJ * qq;
                 if (c < JP) {
-                    const float v = seg_scan(L.sB[c * kTS + lane], lane, head);
-                    if (jlast) {
-                        const float bp = L.Bb[sj * RS + c];
-                        L.Bb[sj * RS + c] = fmaf(a.lr, v - cr * bp, bp);
-                    }
+                    const float ws = __int_as_float(__builtin_amdgcn_ds_permute(jr << 2, __float_as_int(e * w2q[qq])));
+                    const float v = seg_scan(ws, lane, jhead);
+                    if (jlast) L.Bb[sj * RS + c] = fmaf(a.lr, v - jcr * bp[qq], bp[qq]);
                 }
             }
         }
@@ -1110,7 +1114,6 @@ __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
     L.rB = lds + S.rb;
     L.Hs = lds + S.h;
     L.Ht = lds + S.ht;
-    L.sB = lds + S.sb;
     L.As = lds + S.as;
     L.Es = lds + S.es;
     L.xtp = lds + S.xtp;
