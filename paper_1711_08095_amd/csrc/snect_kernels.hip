@@ -63,7 +63,7 @@ __device__ inline void lds_order_fence() { asm volatile("" ::: "memory"); }
 // LDS carve-up of the stratum kernels (in 4-byte words).
 // ---------------------------------------------------------------------------
 struct StratLds {
-    int a, b, ra, rb, c, g, h, ht, as, es, xtp, slotj, stg, sk, tco, tck, red, msum, cgt, flag, rec;
+    int a, b, ra, rb, c, g, h, ht, as, es, xtp, stg, sk, tco, tck, red, msum, cgt, flag, rec;
     int hb, sw1, sw2, xts, esl, a16, e16;  // BF16 path only (zero-sized otherwise)
     int total;
 };
@@ -97,7 +97,6 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     L.esl = o;   o = up4(o + bf * kTileMax);
     L.a16 = o;   o = up4(o + bf * mp * kTB / 2);
     L.e16 = o;   o = up4(o + bf * mp * kTB / 2);
-    L.slotj = o; o = up4(o + kTileMax);
     L.stg = o;   o = up4(o + kMfmaWaves * j12);
     L.sk = o;    o = up4(o + I3 * j12);
     L.tco = o;   o = up4(o + kTileCache + 1);
@@ -503,7 +502,6 @@ struct TileLds {
     const __bf16* Hb;
     float *sW1, *sW2, *xts, *eS;
     __bf16 *A16, *E16;
-    int* slotJ;
     float* Sk;    // [I3*J1*J2] the block's sums of e a (x) b
     float* St;    // [kMfmaWaves][J1*J2] staged partial sums of one platform
     int *tco, *tck;
@@ -913,7 +911,6 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
         const int il = act ? (int)(wd & mask_i) : -1;
         const int jl = act ? (int)((wd >> sh_j) & mask_j) : 0;
         const int jrank = (int)(wd >> sh_r);
-        if (w == 0 && act) L.slotJ[jrank] = jl;
 
         // 1. W1 with x~ and e, W2, for nonzeros 16 rb .. 16 rb + 15
         if (do1 || do2) {
@@ -989,6 +986,21 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
             const int c = w + NW * qq;
             aq[qq] = (c < JP && act) ? L.Ab[il * RS + c] : 0.f;
         }
+        // gene runs in slot order: slot s learns its gene row from the lane
+        // that holds it (inactive lanes push to their own slot), then the run
+        // heads, the regularisation weights and the rows' values before the tile
+        const int sj = __builtin_amdgcn_ds_permute((act ? jrank : lane) << 2, act ? jl : -1);
+        const int sj_up = dpp_move_i<kDppWaveShr1>(sj), sj_dn = dpp_move_i<kDppWaveShl1>(sj);
+        const bool jfirst = act && (lane == 0 || sj_up != sj);
+        const bool jlast = act && (lane == 63 || sj_dn != sj);
+        const int jhead = run_head(__ballot(jfirst), lane);
+        const float jcr = act ? (float)(lane - jhead + 1) * L.rB[sj] : 0.f;
+        float bp[QN];
+#pragma unroll
+        for (int qq = 0; qq < QN; ++qq) {
+            const int c = w + NW * qq;
+            bp[qq] = (c < JP && act) ? L.Bb[sj * RS + c] : 0.f;
+        }
         __syncthreads();
         if (pend >= 0) {
             stage_sum<true, MP>(L.St, L.Sk + pend * J12, J1, J2, tid, NT);
@@ -998,7 +1010,6 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
         // 2. BF16 S operands; fixed-order run sums; owned columns
         const float e = act ? eT[lane] : 0.f;
         const float es = act ? eS[lane] : 0.f;
-        const int sj = act ? L.slotJ[lane] : -1;
 #pragma unroll
         for (int qm = 0; qm < QM; ++qm) {
             const int c = w + NW * qm;
@@ -1019,22 +1030,12 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
                 if (ilast) L.Ab[il * RS + c] = fmaf(a.lr, v - icr * aq[qq], aq[qq]);
             }
         }
-        {
-            const int sj_up = dpp_move_i<kDppWaveShr1>(sj), sj_dn = dpp_move_i<kDppWaveShl1>(sj);
-            const bool jfirst = act && (lane == 0 || sj_up != sj);
-            const bool jlast = act && (lane == 63 || sj_dn != sj);
-            const int head = run_head(__ballot(jfirst), lane);
-            const float cr = act ? (float)(lane - head + 1) * L.rB[sj] : 0.f;
 #pragma unroll
-            for (int qq = 0; qq < QN; ++qq) {
-                const int c = w + NW * qq;
-                if (c < JP) {
-                    const float v = seg_scan(es * L.sW2[c * kTW + lane], lane, head);
-                    if (jlast) {
-                        const float bp = L.Bb[sj * RS + c];
-                        L.Bb[sj * RS + c] = fmaf(a.lr, v - cr * bp, bp);
-                    }
-                }
+        for (int qq = 0; qq < QN; ++qq) {
+            const int c = w + NW * qq;
+            if (c < JP) {
+                const float v = seg_scan(es * L.sW2[c * kTW + lane], lane, jhead);
+                if (jlast) L.Bb[sj * RS + c] = fmaf(a.lr, v - jcr * bp[qq], bp[qq]);
             }
         }
         prev_n = n;
@@ -1124,7 +1125,6 @@ __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
     L.eS = lds + S.esl;
     L.A16 = reinterpret_cast<__bf16*>(lds + S.a16);
     L.E16 = reinterpret_cast<__bf16*>(lds + S.e16);
-    L.slotJ = reinterpret_cast<int*>(lds + S.slotj);
     L.Sk = lds + S.sk;
     L.St = lds + S.stg;
     L.tco = reinterpret_cast<int*>(lds + S.tco);
