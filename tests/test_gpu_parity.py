@@ -152,6 +152,27 @@ def test_evaluate_matches_oracle_loss(ctx):
     assert rmse == pytest.approx(ro, rel=1e-5)
 
 
+def test_evaluate_per_block_loss_kernel(ctx):
+    """A gene block whose w1 table (600 rows x 24 platforms x 10 columns,
+    576 KB) cannot sit in LDS: the loss pass falls back to the per-block
+    kernel, which must agree with the oracle as the column-wise one does."""
+    print("per-block loss kernel: (60, 1200, 24), ranks (10, 8, 3), P=2", flush=True)
+    case = planted_case(seed=5, dims=(60, 1200, 24), ranks=(10, 8, 3), nnz=6000, edges=900, P=2, T=64)
+    prob = gpu_problem(ctx, case)
+    f = gpu_factors(case)
+    loss, rmse = prob.evaluate(*f)
+    A, B, C, G = (np.asarray(a, np.float64) for a in case["init"])
+    from helpers import oracle_problem
+    fo, ro, _ = oracle.loss(oracle_problem(case), A, B, C, G)
+    assert loss == pytest.approx(fo, rel=1e-5)
+    assert rmse == pytest.approx(ro, rel=1e-5)
+    # and one training epoch through the same problem
+    orc = run_oracle(case, 1)
+    gpu, loss1, _, _ = run_gpu(ctx, case, 1)
+    _check_factors(gpu, orc[:4])
+    assert abs(loss1[0] - orc[4][0]) <= LOSS_TOL * abs(orc[4][0])
+
+
 def test_divergence_returns_last_finite(ctx):
     import paper_1711_08095_amd as sn
     case = planted_case(lr=5.0, P=4, T=16)
