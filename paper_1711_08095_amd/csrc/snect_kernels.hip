@@ -221,13 +221,16 @@ __device__ void core_update(const float* C0, const float* G0, const float* S, co
     const float inv_m = (float)(1.0 / m);
     const int nch = (J12 + kCoreChunk - 1) / kCoreChunk;
     const int nc = I3 * J3;
+    // lanes take consecutive items of one chunk (neighbouring G columns and
+    // platforms: few LDS bank conflicts); every chunk is summed in ascending
+    // ab order whatever the lane
     for (int u = tid; u < nc * nch; u += nthr) {
-        const int item = u / nch, ch = u - item * nch;
+        const int ch = u / nc, item = u - ch * nc;
         const int k = item / J3, c = item - k * J3;
         const int ab1 = (ch + 1) * kCoreChunk < J12 ? (ch + 1) * kCoreChunk : J12;
         float g = 0.f;
         for (int ab = ch * kCoreChunk; ab < ab1; ++ab) g = fmaf(-G0[ab * J3 + c], S[k * J12 + ab], g);
-        red[u] = g;
+        red[item * nch + ch] = g;
     }
     const float greg = lam * (float)(m / nnz);
     for (int idx = tid; idx < J12 * J3; idx += nthr) {
