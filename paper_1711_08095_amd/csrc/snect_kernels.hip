@@ -1179,7 +1179,10 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
     const int r = xcd_slot(q, P);
     const int i0 = (int)(((long long)ni * r) / P), i1 = (int)(((long long)ni * (r + 1)) / P);
     const int nchr = (P + kRedChunk - 1) / kRedChunk;
-    const int rit = tid / nchr, rch = tid - rit * nchr;  // item and chunk of this thread's share
+    // item and chunk of this thread's share: consecutive lanes take
+    // consecutive items of one chunk (coalesced loads)
+    const int nitems = i1 - i0 > 0 ? i1 - i0 : 1;
+    const int rch = tid / nitems, rit = tid - rch * nitems;
     constexpr int kPreRec = (kMaxRecCap + NT - 65) / (NT - 64);  // records per thread of a prefetched chunk
     // the next stratum's first chunk is prefetched across the second grid
     // barrier except on the FP32 small-core path (no gain measured there)
@@ -1264,7 +1267,7 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
                 float cs = 0.f;
 #pragma unroll
                 for (int u = 0; u < kRedChunk; ++u) cs += rv[u];
-                red[tid] = cs;
+                red[rit * nchr + rch] = cs;
             }
             __syncthreads();
             if (tid < i1 - i0) {
