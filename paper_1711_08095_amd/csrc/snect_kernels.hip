@@ -1701,14 +1701,52 @@ __global__ __launch_bounds__(256) void loss_cols(LossArgs a)
             continue;
         }
         const int s1 = a.start1[p], r1 = a.start1[p + 1] - s1;
-        load_rows(Ab, a.Ap, s1, r1, J1, JP, tid, NT);
+        // the block's patient rows and its first chunk's records in one
+        // round of loads
+        constexpr int kRowRegs = 4, kRecRegs = kLossChunkTiles * kTileMax / NT;
+        const int nrow = r1 * J1;
+        const bool rows_fit = nrow <= kRowRegs * NT;
+        float rowv[kRowRegs];
+        uint2 recv[kRecRegs];
+        {
+            const float* src = a.Ap + (size_t)s1 * J1;
+#pragma unroll
+            for (int h = 0; h < kRowRegs; ++h) {
+                const int idx = tid + h * NT;
+                rowv[h] = rows_fit && idx < nrow ? src[idx] : 0.f;
+            }
+            const int c1 = t0 + kLossChunkTiles < t1 ? t0 + kLossChunkTiles : t1;
+            const int z0 = a.tile_off[t0], nrec = a.tile_off[c1] - z0;
+#pragma unroll
+            for (int h = 0; h < kRecRegs; ++h) {
+                const int i = tid + h * NT;
+                recv[h] = i < nrec ? a.nz[z0 + i] : make_uint2(0u, 0u);
+            }
+            if (rows_fit) {
+#pragma unroll
+                for (int h = 0; h < kRowRegs; ++h) {
+                    const int idx = tid + h * NT;
+                    if (idx < nrow) {
+                        const int l = idx / J1, c = idx - l * J1;
+                        Ab[l * JP + c] = rowv[h];
+                    }
+                }
+            } else {
+                load_rows(Ab, a.Ap, s1, r1, J1, JP, tid, NT);
+            }
+#pragma unroll
+            for (int h = 0; h < kRecRegs; ++h) {
+                const int i = tid + h * NT;
+                if (i < nrec) rec[i] = recv[h];
+            }
+        }
         double acc = 0.0;
         // wavefront w takes the tiles t0 + w, t0 + w + 4, ... (chunks hold a
         // multiple of four tiles)
         for (int c0 = t0; c0 < t1; c0 += kLossChunkTiles) {
             const int c1 = c0 + kLossChunkTiles < t1 ? c0 + kLossChunkTiles : t1;
             const int z0 = a.tile_off[c0], nrec = a.tile_off[c1] - z0;
-            load_records(rec, a.nz + z0, nrec, tid, NT);
+            if (c0 > t0) load_records(rec, a.nz + z0, nrec, tid, NT);
             __syncthreads();
             for (int tl = c0 + wave; tl < c1; tl += 4) {
                 const int off = a.tile_off[tl], n = a.tile_off[tl + 1] - off, k = a.tile_k[tl];
