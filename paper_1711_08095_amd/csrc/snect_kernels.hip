@@ -559,7 +559,7 @@ __device__ inline void stage_sum(const float* St, float* Skk, int J1, int J2, in
 // c has a patient task (w1_c, its share a_c w1_c of x~, the S operands of
 // column c and the patient-run sums of e w1_c) and a gene task (w2_c and the
 // gene-run sums of e w2_c through the slot-ordered buffer); the two cost
-// about the same.  For small cores (JP <= 12) wavefronts [0, NJ) take the
+// about the same.  For cores up to JP = 20 wavefronts [0, NJ) take the
 // gene tasks and [NJ, NW) the patient tasks, each kind round robin, NJ
 // minimising the largest load, so a wavefront reads only one of the two
 // rows.  Larger cores keep both tasks of column c on wavefront c mod NW
@@ -578,7 +578,7 @@ template <int JP, int NW> struct TileSplit {
             if (cost(nj) < cost(b)) b = nj;
         return b;
     }
-    static constexpr bool kSplit = JP <= 12;
+    static constexpr bool kSplit = JP <= 20;
     static constexpr int NJ = kSplit ? pick() : NW;  // gene-task wavefronts [0, NJ)
     static constexpr int OI = kSplit ? NJ : 0;       // patient-task wavefronts [OI, OI + NI)
     static constexpr int NI = NW - OI;
@@ -654,10 +654,10 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
     int curk = -1;   // platform of the tiles whose operands acc holds
     int pend = -1;   // platform whose partial S waits in L.St
     int prev = 0;    // a tile's S operands wait in L.As/L.Es
-    // small cores (one task kind per wavefront): the wavefront's rows
-    // (patient tasks) or columns (gene tasks) of H_k stay in registers while
-    // consecutive tiles share k
-    constexpr bool kHreg = SP::kSplit;
+    // small cores (JP <= 12, one task kind per wavefront): the wavefront's
+    // rows (patient tasks) or columns (gene tasks) of H_k stay in registers
+    // while consecutive tiles share k; larger ones read H_k and H_k^T from LDS
+    constexpr bool kHreg = SP::kSplit && JP <= 12;
     float hh[kHreg ? QH : 1][kHreg ? JP : 1];
     int tl = t0;
     while (tl < t1) {
@@ -1186,7 +1186,7 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
     constexpr int kPreRec = (kMaxRecCap + NT - 65) / (NT - 64);  // records per thread of a prefetched chunk
     // the next stratum's first chunk is prefetched across the second grid
     // barrier except on the FP32 small-core path (no gain measured there)
-    constexpr bool kPrefetch = BF || !TileSplit<JP, NW>::kSplit;
+    constexpr bool kPrefetch = BF || JP > 12;
     int pre_cend = 0;  // tiles of this stratum's first chunk already in LDS
 
     for (int si = 0; si < P; ++si) {
