@@ -852,9 +852,10 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
 //      eight wavefronts, wavefronts 0..3 take W1 and 4..7 take W2 (and add
 //      the previous tile's S operands); with four, each takes both;
 //   -- barrier --
-//   2. every wavefront stages the BF16 operands a_i and e b_j of the S
-//      product for its columns and sums the patient and gene runs of e*w1
-//      and e*w2 with the segmented scans of the FP32 path;
+//   2. patient tasks stage the BF16 operands a_i and e b_j of the S product
+//      for their columns and sum the patient runs of e*w1, gene tasks sum
+//      the gene runs of e*w2, with the segmented scans of the FP32 path
+//      (with eight wavefronts gene tasks on 0..3, patient tasks on 4..7);
 //   -- barrier --
 template <int JP, int NW>
 __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& L, int tid, int pre_cend)
@@ -864,9 +865,12 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
     constexpr int MP = mfma_dim(JP);
     constexpr int NB = MP / 16;
     constexpr int NT = 64 * NW;
-    constexpr int QN = (JP + NW - 1) / NW;
-    constexpr int QM = (MP + NW - 1) / NW;
     constexpr bool kTwo = NW >= 2 * kMfmaWaves;  // W1 and W2 on different wavefronts
+    // column tasks: with eight wavefronts the gene tasks go to wavefronts
+    // 0..3 and the patient tasks (with the S operands of their columns) to
+    // 4..7; with four, each wavefront takes both tasks of its columns
+    constexpr int NJ = kTwo ? NW / 2 : NW, OI = kTwo ? NW / 2 : 0, NI = NW - OI;
+    constexpr int QI = (JP + NI - 1) / NI, QJ = (JP + NJ - 1) / NJ;
     const int lane = tid & 63, w = tid >> 6, g = lane >> 4, m = lane & 15;
     const int J1 = a.J1, J2 = a.J2, J12 = J1 * J2;
     const uint32_t mask_i = (1u << a.bits_i) - 1u, mask_j = (1u << a.bits_j) - 1u;
@@ -874,6 +878,14 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
     const int blk = p * a.P + q;
     const int t0 = a.blk_tile[blk], t1 = a.blk_tile[blk + 1];
     if (t0 >= t1) return;
+    const bool hj = w < NJ, hi = w >= OI;
+    const int rj = w, ri = w - OI;
+
+    // operand columns beyond the factor columns stay zero
+    for (int idx = tid; idx < (MP - JP) * kTB; idx += NT) {
+        L.A16[JP * kTB + idx] = (__bf16)0.f;
+        L.E16[JP * kTB + idx] = (__bf16)0.f;
+    }
 
     SAccB<MP> acc;
     acc.zero();
@@ -983,11 +995,12 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
         const bool ilast = act && (lane == 63 || il_dn != il);
         const int ihead = run_head(__ballot(ifirst), lane);
         const float icr = act ? (float)(lane - ihead + 1) * L.rA[il] : 0.f;
-        float aq[QN];
+        float aq[QI], bq[QI];
 #pragma unroll
-        for (int qq = 0; qq < QN; ++qq) {
-            const int c = w + NW * qq;
-            aq[qq] = (c < JP && act) ? L.Ab[il * RS + c] : 0.f;
+        for (int qq = 0; qq < QI; ++qq) {
+            const int c = ri + NI * qq;
+            aq[qq] = (hi && c < JP && act) ? L.Ab[il * RS + c] : 0.f;
+            bq[qq] = (hi && c < JP && act) ? L.Bb[jl * RS + c] : 0.f;
         }
         // gene runs in slot order: slot s learns its gene row from the lane
         // that holds it (inactive lanes push to their own slot), then the run
@@ -998,11 +1011,11 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
         const bool jlast = act && (lane == 63 || sj_dn != sj);
         const int jhead = run_head(__ballot(jfirst), lane);
         const float jcr = act ? (float)(lane - jhead + 1) * L.rB[sj] : 0.f;
-        float bp[QN];
+        float bp[QJ];
 #pragma unroll
-        for (int qq = 0; qq < QN; ++qq) {
-            const int c = w + NW * qq;
-            bp[qq] = (c < JP && act) ? L.Bb[sj * RS + c] : 0.f;
+        for (int qq = 0; qq < QJ; ++qq) {
+            const int c = rj + NJ * qq;
+            bp[qq] = (hj && c < JP && act) ? L.Bb[sj * RS + c] : 0.f;
         }
         __syncthreads();
         if (pend >= 0) {
@@ -1013,32 +1026,26 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
         // 2. BF16 S operands; fixed-order run sums; owned columns
         const float e = act ? eT[lane] : 0.f;
         const float es = act ? eS[lane] : 0.f;
+        if (hi) {
 #pragma unroll
-        for (int qm = 0; qm < QM; ++qm) {
-            const int c = w + NW * qm;
-            if (c >= MP) continue;
-            float av_c = 0.f, eb_c = 0.f;
-            if (c < JP && act) {
-                av_c = qm < QN ? aq[qm < QN ? qm : 0] : L.Ab[il * RS + c];
-                eb_c = e * L.Bb[jl * RS + c];
-            }
-            L.A16[c * kTB + lane] = (__bf16)av_c;
-            L.E16[c * kTB + lane] = (__bf16)eb_c;
-        }
-#pragma unroll
-        for (int qq = 0; qq < QN; ++qq) {
-            const int c = w + NW * qq;
-            if (c < JP) {
-                const float v = seg_scan(e * L.sW1[c * kTW + lane], lane, ihead);
-                if (ilast) L.Ab[il * RS + c] = fmaf(a.lr, v - icr * aq[qq], aq[qq]);
+            for (int qq = 0; qq < QI; ++qq) {
+                const int c = ri + NI * qq;
+                if (c < JP) {
+                    L.A16[c * kTB + lane] = (__bf16)aq[qq];
+                    L.E16[c * kTB + lane] = (__bf16)(e * bq[qq]);
+                    const float v = seg_scan(e * L.sW1[c * kTW + lane], lane, ihead);
+                    if (ilast) L.Ab[il * RS + c] = fmaf(a.lr, v - icr * aq[qq], aq[qq]);
+                }
             }
         }
+        if (hj) {
 #pragma unroll
-        for (int qq = 0; qq < QN; ++qq) {
-            const int c = w + NW * qq;
-            if (c < JP) {
-                const float v = seg_scan(es * L.sW2[c * kTW + lane], lane, jhead);
-                if (jlast) L.Bb[sj * RS + c] = fmaf(a.lr, v - jcr * bp[qq], bp[qq]);
+            for (int qq = 0; qq < QJ; ++qq) {
+                const int c = rj + NJ * qq;
+                if (c < JP) {
+                    const float v = seg_scan(es * L.sW2[c * kTW + lane], lane, jhead);
+                    if (jlast) L.Bb[sj * RS + c] = fmaf(a.lr, v - jcr * bp[qq], bp[qq]);
+                }
             }
         }
         prev_n = n;
