@@ -115,6 +115,12 @@ def test_admission_and_errors(setup):
     with pytest.raises(sn.SnectError) as e:
         srv.submit(np.array([900], np.int32), np.array([0], np.int32), np.ones(1, np.float32))
     assert e.value.code == -2
+    with pytest.raises(sn.SnectError) as e:
+        srv.submit(np.array([3, 4], np.int32), np.array([0, 1], np.int32), np.array([1.0, np.nan], np.float32))
+    assert e.value.code == -1  # non-finite value
+    with pytest.raises(sn.SnectError) as e:
+        srv.submit(np.array([3, 4], np.int32), np.array([0, -1], np.int32), np.ones(2, np.float32))
+    assert e.value.code == -2  # negative platform
     # lambda = 0 and a single cell: the system is singular, that request fails alone
     tk_bad = srv.submit(np.array([3], np.int32), np.array([1], np.int32), np.ones(1, np.float32))
     r = reqs[1]
