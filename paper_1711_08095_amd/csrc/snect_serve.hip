@@ -107,6 +107,14 @@ constexpr int kScoreLds = 6144;  // patients whose scores stay in LDS during the
 // Solve and search, one workgroup per request.  out: u[J1], then for the
 // top k: scores (double), then indices (int, stored as double).  SL: the
 // I1 <= kScoreLds scores live in dynamic LDS, else in `scores` (global).
+// Orders a wavefront's LDS exchanges between its lanes: a wavefront-scope
+// barrier and a compiler memory fence (every later read is a new load).
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+}
+
 template <bool SL>
 __global__ __launch_bounds__(256) void serve_solve(const double* part, int nparts, int J1, double lam, int pg_iters,
                                                    const float* A, const double* anrm, int I1, int topk,
@@ -161,63 +169,87 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
     if (tid < J1) u[tid] = 0.0;
     if (tid == 0) bad = 0;
     __syncthreads();
-    if (tid == 0) {
-        double f = 0.0;
-        for (int e = 0; e < J1 * J1; ++e) f += Q[e] * Q[e];
-        step = f > 0.0 ? 1.0 / sqrt(f) : 0.0;
-    }
-    __syncthreads();
-    // projected-gradient steps (identity projection)
-    for (int it = 0; it < pg_iters; ++it) {
-        if (tid < J1) {
-            double s = -r[tid];
-            for (int b = 0; b < J1; ++b) s += Q[tid * J1 + b] * u[b];
-            g[tid] = s;
+    // The J1 x J1 algebra runs in wavefront 0 alone (lane a holds row a).
+    // Lanes exchange values through LDS: the wavefront executes in lockstep
+    // and its LDS operations complete in order, and wave_sync() after every
+    // exchange stops the compiler from reusing a value read before it.
+    if (tid < 64) {
+        const int a = tid;
+        if (a == 0) {
+            double f = 0.0;
+            for (int e = 0; e < J1 * J1; ++e) f += Q[e] * Q[e];
+            step = f > 0.0 ? 1.0 / sqrt(f) : 0.0;
         }
-        __syncthreads();
-        if (tid < J1) u[tid] -= step * g[tid];
-        __syncthreads();
-    }
-    // refinement through Q = L L^T
-    if (tid < J1) {
-        double s = r[tid];
-        for (int b = 0; b < J1; ++b) s -= Q[tid * J1 + b] * u[b];
-        g[tid] = s;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        for (int e = 0; e < J1 * J1; ++e) L[e] = 0.0;
-        for (int c = 0; c < J1 && !bad; ++c) {
-            double dd = Q[c * J1 + c];
-            for (int t = 0; t < c; ++t) dd -= L[c * J1 + t] * L[c * J1 + t];
-            if (!(dd > 0.0)) {
-                bad = 1;
-                break;
+        wave_sync();
+        const double stp = step;
+        // projected-gradient steps (identity projection)
+        for (int it = 0; it < pg_iters; ++it) {
+            double s = 0.0;
+            if (a < J1) {
+                s = -r[a];
+                for (int b = 0; b < J1; ++b) s += Q[a * J1 + b] * u[b];
             }
-            L[c * J1 + c] = sqrt(dd);
-            for (int rr = c + 1; rr < J1; ++rr) {
-                double v = Q[rr * J1 + c];
-                for (int t = 0; t < c; ++t) v -= L[rr * J1 + t] * L[c * J1 + t];
-                L[rr * J1 + c] = v / L[c * J1 + c];
-            }
+            wave_sync();
+            if (a < J1) u[a] -= stp * s;
+            wave_sync();
         }
-        if (!bad) {
-            for (int a = 0; a < J1; ++a) {  // L y = g
-                double v = g[a];
-                for (int t = 0; t < a; ++t) v -= L[a * J1 + t] * d[t];
-                d[a] = v / L[a * J1 + a];
-            }
-            for (int a = J1 - 1; a >= 0; --a) {  // L^T z = y
-                double v = d[a];
-                for (int t = a + 1; t < J1; ++t) v -= L[t * J1 + a] * d[t];
-                d[a] = v / L[a * J1 + a];
-            }
-            for (int a = 0; a < J1; ++a) u[a] += d[a];
+        // refinement through Q = L L^T: residual g = r - Q u
+        if (a < J1) {
+            double s = r[a];
+            for (int b = 0; b < J1; ++b) s -= Q[a * J1 + b] * u[b];
+            g[a] = s;
         }
-        double s = 0.0;
-        for (int a = 0; a < J1; ++a) s += u[a] * u[a];
-        unorm = sqrt(s);
-        status[0] = bad;
+        for (int e = a; e < J1 * J1; e += 64) L[e] = 0.0;
+        wave_sync();
+        // Cholesky column by column; lane rr forms L[rr][c] for rr > c,
+        // every entry in the order of the textbook row loop
+        bool failed = false;
+        for (int c = 0; c < J1; ++c) {
+            double dd = 1.0;
+            if (a == c) {
+                dd = Q[c * J1 + c];
+                for (int t = 0; t < c; ++t) dd -= L[c * J1 + t] * L[c * J1 + t];
+                L[c * J1 + c] = dd > 0.0 ? sqrt(dd) : 1.0;
+            }
+            failed = __ballot(a == c && !(dd > 0.0)) != 0ull;  // uniform
+            wave_sync();
+            if (failed) break;
+            if (a > c && a < J1) {
+                double v = Q[a * J1 + c];
+                for (int t = 0; t < c; ++t) v -= L[a * J1 + t] * L[c * J1 + t];
+                L[a * J1 + c] = v / L[c * J1 + c];
+            }
+            wave_sync();
+        }
+        if (!failed) {
+            // L y = g: y[t] final at step t, then lanes a > t subtract in
+            // ascending t (the order of the row loop)
+            double v = a < J1 ? g[a] : 0.0;
+            for (int t = 0; t < J1; ++t) {
+                if (a == t) d[t] = v / L[t * J1 + t];
+                wave_sync();
+                if (a > t && a < J1) v -= L[a * J1 + t] * d[t];
+            }
+            wave_sync();
+            // L^T z = y: z[t] final at step t (descending), lanes a < t subtract
+            v = a < J1 ? d[a] : 0.0;
+            wave_sync();
+            for (int t = J1 - 1; t >= 0; --t) {
+                if (a == t) d[t] = v / L[t * J1 + t];
+                wave_sync();
+                if (a < t) v -= L[t * J1 + a] * d[t];
+            }
+            wave_sync();
+            if (a < J1) u[a] += d[a];
+            wave_sync();
+        }
+        if (a == 0) {
+            double s = 0.0;
+            for (int e = 0; e < J1; ++e) s += u[e] * u[e];
+            unorm = sqrt(s);
+            bad = failed ? 1 : 0;
+            status[0] = bad;
+        }
     }
     __syncthreads();
     // cosine scores; rows of zero norm are excluded (NaN), a zero u scores
