@@ -104,9 +104,6 @@ __global__ __launch_bounds__(256) void serve_gram(const int32_t* jj, const int32
 
 constexpr int kScoreLds = 6144;  // patients whose scores stay in LDS during the search
 
-// Solve and search, one workgroup per request.  out: u[J1], then for the
-// top k: scores (double), then indices (int, stored as double).  SL: the
-// I1 <= kScoreLds scores live in dynamic LDS, else in `scores` (global).
 // Orders a wavefront's LDS exchanges between its lanes: a wavefront-scope
 // barrier and a compiler memory fence (every later read is a new load).
 __device__ inline void wave_sync()
@@ -115,6 +112,12 @@ __device__ inline void wave_sync()
     asm volatile("" ::: "memory");
 }
 
+// Solve and search, one workgroup per request.  out: u[J1], then for the
+// top k: scores (double), then indices (int, stored as double); status[0]:
+// 1 if Q is not positive definite.  Both are stored once, at the end (a
+// store to host memory would hold up every later barrier), so out and
+// status may be device mappings of pinned host memory.  SL: the I1 <= kScoreLds
+// scores live in dynamic LDS, else in `scores` (global).
 template <bool SL>
 __global__ __launch_bounds__(256) void serve_solve(const double* part, int nparts, int J1, double lam, int pg_iters,
                                                    const float* A, const double* anrm, int I1, int topk,
@@ -124,35 +127,39 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
     __shared__ double L[32 * 32];
     __shared__ double r[32], u[32], g[32], d[32];
     __shared__ double psub[576];
-    __shared__ double red_s[4];
-    __shared__ int red_i[4];
+    __shared__ double red_s[8];  // per wavefront, two rounds
+    __shared__ int red_i[8];
     __shared__ double unorm, step;
     __shared__ int bad;
+    __shared__ double top_s[64];  // topk <= 64
+    __shared__ int top_i[64];
     extern __shared__ double lds_scores[];
     double* scores = SL ? lds_scores : gscores;
     const int tid = threadIdx.x;
     const int nq = J1 * (J1 + 1) / 2, ne = nq + J1;
     // Q and r from the partial sums: G threads per entry each add a
-    // contiguous range of workgroups in ascending order (16 loads in
-    // flight), then the G range sums are added in ascending order
+    // contiguous range of workgroups in ascending order (32 loads in
+    // flight), then the G range sums are added in ascending order.
+    // Consecutive threads take consecutive entries of one range, so a
+    // wavefront reads whole rows of the partials.
     const int G = ne < 256 ? 256 / ne : 1;
     for (int task = tid; task < ne * G; task += 256) {
-        const int e = task / G, gsub = task - e * G;
+        const int gsub = task / ne, e = task - gsub * ne;
         const int p0 = (int)(((long long)nparts * gsub) / G), p1 = (int)(((long long)nparts * (gsub + 1)) / G);
         double acc = 0.0;
-        for (int pb = p0; pb < p1; pb += 16) {
-            double v[16];
+        for (int pb = p0; pb < p1; pb += 32) {
+            double v[32];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = pb + q < p1 ? part[(size_t)(pb + q) * ne + e] : 0.0;
+            for (int q = 0; q < 32; ++q) v[q] = pb + q < p1 ? part[(size_t)(pb + q) * ne + e] : 0.0;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) acc += v[q];
+            for (int q = 0; q < 32; ++q) acc += v[q];
         }
         psub[task] = acc;
     }
     __syncthreads();
     for (int e = tid; e < ne; e += 256) {
-        double s = psub[e * G];
-        for (int gsub = 1; gsub < G; ++gsub) s += psub[e * G + gsub];
+        double s = psub[e];
+        for (int gsub = 1; gsub < G; ++gsub) s += psub[gsub * ne + e];
         if (e < nq) {
             int a = 0, rem = e;
             while (rem >= J1 - a) {
@@ -248,69 +255,120 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
             for (int e = 0; e < J1; ++e) s += u[e] * u[e];
             unorm = sqrt(s);
             bad = failed ? 1 : 0;
-            status[0] = bad;
         }
     }
     __syncthreads();
     // cosine scores; rows of zero norm are excluded (NaN), a zero u scores
-    // every other row -inf
-    for (int i = tid; i < I1; i += 256) {
-        double s = anrm[i] > 0.0 ? -INFINITY : NAN;
-        if (anrm[i] > 0.0 && unorm > 0.0) {
-            double dot = 0.0;
-            for (int a = 0; a < J1; ++a) dot += (double)A[(size_t)i * J1 + a] * u[a];
-            s = dot / (anrm[i] * unorm);
+    // every other row -inf.  A thread takes kCosRows rows per pass and
+    // issues the loads of kCosCols columns of each before any product, so
+    // one pass waits on memory once per kCosCols columns.
+    constexpr int kCosRows = 9, kCosCols = 12;
+    for (int i0 = tid; i0 < I1; i0 += 256 * kCosRows) {
+        const float* ar[kCosRows];
+        const double* np[kCosRows];
+        double nr[kCosRows], dot[kCosRows];
+#pragma unroll
+        for (int q = 0; q < kCosRows; ++q) {
+            const int i = i0 + 256 * q < I1 ? i0 + 256 * q : I1 - 1;
+            ar[q] = A + (size_t)i * J1;
+            np[q] = anrm + i;
+            dot[q] = 0.0;
         }
-        scores[i] = s;
-    }
-    __syncthreads();
-    // top k by repeated arg-max: larger score first, lower index on ties;
-    // a taken row is marked with NaN.  Each round reduces within every
-    // wavefront by lane exchanges, then over the four wavefronts.
-    const int lane = tid & 63, wv = tid >> 6;
-    for (int t = 0; t < topk; ++t) {
-        double bs = -INFINITY;
-        int bi = -1;
-        for (int i = tid; i < I1; i += 256) {
-            const double s = scores[i];
-            if (s != s) continue;
-            if (bi < 0 || s > bs) {
-                bs = s;
-                bi = i;
+        for (int c0 = 0; c0 < J1; c0 += kCosCols) {
+            float v[kCosRows][kCosCols];
+#pragma unroll
+            for (int q = 0; q < kCosRows; ++q)
+#pragma unroll
+                for (int c = 0; c < kCosCols; ++c) v[q][c] = ar[q][c0 + c < J1 ? c0 + c : J1 - 1];  // unused past J1
+#pragma unroll
+            for (int q = 0; q < kCosRows; ++q) nr[q] = *np[q];  // with the first columns' loads
+            __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the products
+#pragma unroll
+            for (int c = 0; c < kCosCols; ++c) {
+                if (c0 + c >= J1) break;
+                const double uc = u[c0 + c];
+#pragma unroll
+                for (int q = 0; q < kCosRows; ++q) dot[q] += (double)v[q][c] * uc;
             }
         }
 #pragma unroll
+        for (int q = 0; q < kCosRows; ++q) {
+            const int i = i0 + 256 * q;
+            if (i >= I1) break;
+            double sc = nr[q] > 0.0 ? -INFINITY : NAN;
+            if (nr[q] > 0.0 && unorm > 0.0) sc = dot[q] / (nr[q] * unorm);
+            scores[i] = sc;
+        }
+    }
+    // top k by repeated arg-max: larger score first, lower index on ties;
+    // a taken row is marked with NaN.  Every thread keeps the best of its
+    // own rows (tid, tid + 256, ...); a round reduces these within each
+    // wavefront by lane exchanges, then every thread reduces the four
+    // wavefront results, and only the thread owning the winner rescans.
+    const int lane = tid & 63, wv = tid >> 6;
+    double bs = -INFINITY;
+    int bi = -1;
+    for (int i = tid; i < I1; i += 256) {
+        const double sc = scores[i];
+        if (sc != sc) continue;
+        if (bi < 0 || sc > bs) {
+            bs = sc;
+            bi = i;
+        }
+    }
+    for (int t = 0; t < topk; ++t) {
+        double ws = bs;
+        int wi = bi;
+#pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
-            const double s2 = __shfl_xor(bs, o);
-            const int i2 = __shfl_xor(bi, o);
-            if (i2 >= 0 && (bi < 0 || s2 > bs || (s2 == bs && i2 < bi))) {
-                bs = s2;
-                bi = i2;
+            const double s2 = __shfl_xor(ws, o);
+            const int i2 = __shfl_xor(wi, o);
+            if (i2 >= 0 && (wi < 0 || s2 > ws || (s2 == ws && i2 < wi))) {
+                ws = s2;
+                wi = i2;
             }
         }
+        const int rb = (t & 1) * 4;  // a buffer is rewritten two rounds later, past one more barrier
         if (lane == 0) {
-            red_s[wv] = bs;
-            red_i[wv] = bi;
+            red_s[rb + wv] = ws;
+            red_i[rb + wv] = wi;
         }
         __syncthreads();
+        double s1 = red_s[rb];
+        int i1 = red_i[rb];
+        for (int w = 1; w < 4; ++w) {
+            const double s2 = red_s[rb + w];
+            const int i2 = red_i[rb + w];
+            if (i2 >= 0 && (i1 < 0 || s2 > s1 || (s2 == s1 && i2 < i1))) {
+                s1 = s2;
+                i1 = i2;
+            }
+        }
         if (tid == 0) {
-            double s1 = red_s[0];
-            int i1 = red_i[0];
-            for (int w = 1; w < 4; ++w) {
-                const double s2 = red_s[w];
-                const int i2 = red_i[w];
-                if (i2 >= 0 && (i1 < 0 || s2 > s1 || (s2 == s1 && i2 < i1))) {
-                    s1 = s2;
-                    i1 = i2;
+            top_s[t] = s1;
+            top_i[t] = i1;
+        }
+        if (i1 >= 0 && (i1 & 255) == tid) {
+            scores[i1] = NAN;
+            bs = -INFINITY;
+            bi = -1;
+            for (int i = tid; i < I1; i += 256) {
+                const double sc = scores[i];
+                if (sc != sc) continue;
+                if (bi < 0 || sc > bs) {
+                    bs = sc;
+                    bi = i;
                 }
             }
-            out[J1 + t] = s1;
-            out[J1 + topk + t] = (double)i1;
-            if (i1 >= 0) scores[i1] = NAN;
         }
-        __syncthreads();
     }
+    __syncthreads();
     if (tid < J1) out[tid] = u[tid];
+    if (tid < topk) {
+        out[J1 + tid] = top_s[tid];
+        out[J1 + topk + tid] = (double)top_i[tid];
+    }
+    if (tid == 0) status[0] = bad;
 }
 
 hipError_t launch_serve_setup(const float* A, const float* B, const float* C, const float* G, int I1, int I2, int I3,

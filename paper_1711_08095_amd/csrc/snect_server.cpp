@@ -85,16 +85,16 @@ struct Slot {
     bool busy = false;
     int64_t ticket = -1;
     size_t off = 0, bytes = 0;
-    // pinned host staging: request upload and result download
+    // pinned host staging of the request upload
     char* h_in = nullptr;
     size_t h_in_cap = 0;
+    // results: out_len() doubles, then the status word in one more double,
+    // on the device and in pinned host memory (one download per request)
     double* h_out = nullptr;
-    int* h_status = nullptr;
     // per-slot device scratch
     double* d_part = nullptr;
     double* d_scores = nullptr;
     double* d_out = nullptr;
-    int* d_status = nullptr;
 };
 
 double now_s()
@@ -185,10 +185,8 @@ int snect_server_create(snect_ctx* ctx, int32_t I1, int32_t I2, int32_t I3, int3
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
             hipMalloc((void**)&sl.d_part, sizeof(double) * kServeMaxParts * ne) != hipSuccess ||
             hipMalloc((void**)&sl.d_scores, sizeof(double) * (size_t)I1) != hipSuccess ||
-            hipMalloc((void**)&sl.d_out, sizeof(double) * s->out_len()) != hipSuccess ||
-            hipMalloc((void**)&sl.d_status, sizeof(int) * 4) != hipSuccess ||
-            hipHostMalloc((void**)&sl.h_out, sizeof(double) * s->out_len(), hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void**)&sl.h_status, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
+            hipMalloc((void**)&sl.d_out, sizeof(double) * (s->out_len() + 1)) != hipSuccess ||
+            hipHostMalloc((void**)&sl.h_out, sizeof(double) * (s->out_len() + 1), hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             return fail(SNECT_E_OOM, "server slot allocation failed");
         }
@@ -211,10 +209,8 @@ int snect_server_destroy(snect_server* s)
         if (sl.d_part) (void)hipFree(sl.d_part);
         if (sl.d_scores) (void)hipFree(sl.d_scores);
         if (sl.d_out) (void)hipFree(sl.d_out);
-        if (sl.d_status) (void)hipFree(sl.d_status);
         if (sl.h_in) (void)hipHostFree(sl.h_in);
         if (sl.h_out) (void)hipHostFree(sl.h_out);
-        if (sl.h_status) (void)hipHostFree(sl.h_status);
     }
     if (s->d_W) (void)hipFree(s->d_W);
     if (s->d_anrm) (void)hipFree(s->d_anrm);
@@ -280,10 +276,9 @@ int snect_server_submit(snect_server* s, int64_t nnz, const int32_t* j, const in
         e = launch_serve_request(reinterpret_cast<const int32_t*>(dbase), reinterpret_cast<const int32_t*>(dbase + bj),
                                  reinterpret_cast<const float*>(dbase + 2 * bj), (int)nnz, s->d_W, s->I2, s->J1,
                                  s->cfg.lambda, s->cfg.pg_iters, s->A, s->d_anrm, s->I1, s->cfg.topk, sl.d_part,
-                                 sl.d_scores, sl.d_out, sl.d_status, sl.stream);
+                                 sl.d_scores, sl.d_out, reinterpret_cast<int*>(sl.d_out + s->out_len()), sl.stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(sl.h_out, sl.d_out, sizeof(double) * s->out_len(), hipMemcpyDeviceToHost, sl.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(sl.h_status, sl.d_status, sizeof(int), hipMemcpyDeviceToHost, sl.stream);
+        e = hipMemcpyAsync(sl.h_out, sl.d_out, sizeof(double) * (s->out_len() + 1), hipMemcpyDeviceToHost, sl.stream);
     if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
     if (e != hipSuccess) {
         (void)hipStreamSynchronize(sl.stream);
@@ -313,7 +308,7 @@ int snect_server_poll(snect_server* s, int64_t ticket, double* u, int32_t* idx, 
     if (score) std::memcpy(score, sl.h_out + J1, sizeof(double) * K);
     if (idx)
         for (int t = 0; t < K; ++t) idx[t] = (int32_t)sl.h_out[J1 + K + t];
-    const int bad = sl.h_status[0];
+    const int bad = *reinterpret_cast<const int*>(sl.h_out + s->out_len());
     s->pool.give(sl.off, sl.bytes);
     sl.busy = false;
     s->where.erase(it);
