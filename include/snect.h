@@ -284,9 +284,10 @@ typedef struct {
 } snect_server_config;
 
 /* A, B, C, G: device factors (row-major FP32, A is I1 x J1, ...).  The
- * server precomputes the rows w for every (gene, platform) cell and the row
- * norms of A, and keeps reading A: the factors must stay alive and unchanged
- * while the server exists.  Errors: E_ARG, E_RANK, E_OOM, E_HIP. */
+ * server precomputes the rows w for every (gene, platform) cell, the row
+ * norms of A and a transposed copy of A before it returns, and reads the
+ * factors no more: later changes to them are not seen by the server.
+ * Errors: E_ARG, E_RANK, E_OOM, E_HIP. */
 int snect_server_create(snect_ctx *ctx, int32_t I1, int32_t I2, int32_t I3, int32_t J1, int32_t J2, int32_t J3,
                         const snect_factors *f, const snect_server_config *cfg, snect_server **srv);
 

@@ -40,12 +40,19 @@ __global__ __launch_bounds__(256) void serve_build_w(const float* B, const float
     W[idx] = s;
 }
 
-__global__ __launch_bounds__(256) void serve_row_norms(const float* A, int I1, int J1, double* nrm)
+// Row norms of A and its transpose At[c * I1 + r] = A[r][c] (FP32), so
+// that the cosine pass reads columns with consecutive threads on
+// consecutive rows.
+__global__ __launch_bounds__(256) void serve_rows(const float* A, int I1, int J1, double* nrm, float* At)
 {
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= I1) return;
     double s = 0.0;
-    for (int c = 0; c < J1; ++c) s += (double)A[(size_t)r * J1 + c] * (double)A[(size_t)r * J1 + c];
+    for (int c = 0; c < J1; ++c) {
+        const float v = A[(size_t)r * J1 + c];
+        s += (double)v * (double)v;
+        At[(size_t)c * I1 + r] = v;
+    }
     nrm[r] = sqrt(s);
 }
 
@@ -102,7 +109,7 @@ __global__ __launch_bounds__(256) void serve_gram(const int32_t* jj, const int32
     }
 }
 
-constexpr int kScoreLds = 6144;  // patients whose scores stay in LDS during the search
+constexpr int kRegRows = 24;  // scores per thread kept in registers: I1 <= 256 * kRegRows
 
 // Orders a wavefront's LDS exchanges between its lanes: a wavefront-scope
 // barrier and a compiler memory fence (every later read is a new load).
@@ -112,29 +119,84 @@ __device__ inline void wave_sync()
     asm volatile("" ::: "memory");
 }
 
+// Value of v in lane l of the wavefront (l uniform).
+__device__ inline double lane_d(double v, int l)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Cosine scores of the eight rows i0 + 256 q (q < 8): the loads of up to
+// twelve columns of all eight rows are issued before any product.  Rows
+// past I1 are computed on row I1 - 1 and must not be used.
+__device__ inline void cosine8(const float* At, const double* anrm, const double* u, double un, int I1, int J1,
+                               int i0, double sc[8])
+{
+    constexpr int kCols = 12;
+    int row[8];
+    double nr[8], dot[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        row[q] = i0 + 256 * q < I1 ? i0 + 256 * q : I1 - 1;
+        dot[q] = 0.0;
+    }
+    for (int c0 = 0; c0 < J1; c0 += kCols) {
+        float v[8][kCols];
+#pragma unroll
+        for (int c = 0; c < kCols; ++c) {
+            const float* col = At + (size_t)(c0 + c < J1 ? c0 + c : J1 - 1) * I1;  // unused past J1
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q][c] = col[row[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) nr[q] = anrm[row[q]];
+        __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the products
+#pragma unroll
+        for (int c = 0; c < kCols; ++c) {
+            if (c0 + c >= J1) break;
+            const double uc = u[c0 + c];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) dot[q] += (double)v[q][c] * uc;
+        }
+    }
+    // rows of zero norm are excluded (NaN); a zero u scores every other row -inf
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        double x = nr[q] > 0.0 ? -INFINITY : NAN;
+        if (nr[q] > 0.0 && un > 0.0) x = dot[q] / (nr[q] * un);
+        sc[q] = x;
+    }
+}
+
+// Larger score first, lower row index on ties; an index < 0 is no candidate.
+__device__ inline bool better(double s2, int i2, double s1, int i1)
+{
+    return i2 >= 0 && (i1 < 0 || s2 > s1 || (s2 == s1 && i2 < i1));
+}
+
 // Solve and search, one workgroup per request.  out: u[J1], then for the
 // top k: scores (double), then indices (int, stored as double); status[0]:
 // 1 if Q is not positive definite.  Both are stored once, at the end (a
 // store to host memory would hold up every later barrier), so out and
-// status may be device mappings of pinned host memory.  SL: the I1 <= kScoreLds
-// scores live in dynamic LDS, else in `scores` (global).
-template <bool SL>
+// status may be device mappings of pinned host memory.  RS: a thread's
+// scores (rows tid + 256 q) stay in registers (I1 <= 256 * kRegRows), else
+// they go to `gscores` (global, I1 entries).
+template <bool RS>
 __global__ __launch_bounds__(256) void serve_solve(const double* part, int nparts, int J1, double lam, int pg_iters,
-                                                   const float* A, const double* anrm, int I1, int topk,
+                                                   const float* At, const double* anrm, int I1, int topk,
                                                    double* gscores, double* out, int* status)
 {
-    __shared__ double Q[32 * 32];
-    __shared__ double L[32 * 32];
-    __shared__ double r[32], u[32], g[32], d[32];
+    __shared__ double Q[32 * 32];  // Q, then the rows of L
+    __shared__ double r[32], u[32];
     __shared__ double psub[576];
     __shared__ double red_s[8];  // per wavefront, two rounds
     __shared__ int red_i[8];
-    __shared__ double unorm, step;
+    __shared__ double unorm;
     __shared__ int bad;
     __shared__ double top_s[64];  // topk <= 64
     __shared__ int top_i[64];
-    extern __shared__ double lds_scores[];
-    double* scores = SL ? lds_scores : gscores;
     const int tid = threadIdx.x;
     const int nq = J1 * (J1 + 1) / 2, ne = nq + J1;
     // Q and r from the partial sums: G threads per entry each add a
@@ -173,149 +235,148 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
             r[e - nq] = s;
         }
     }
-    if (tid < J1) u[tid] = 0.0;
-    if (tid == 0) bad = 0;
     __syncthreads();
-    // The J1 x J1 algebra runs in wavefront 0 alone (lane a holds row a).
-    // Lanes exchange values through LDS: the wavefront executes in lockstep
-    // and its LDS operations complete in order, and wave_sync() after every
-    // exchange stops the compiler from reusing a value read before it.
+    // The J1 x J1 algebra runs in wavefront 0 alone: lane a holds row a of
+    // Q and of L in registers and reads other lanes' values by readlane.
     if (tid < 64) {
         const int a = tid;
-        if (a == 0) {
-            double f = 0.0;
-            for (int e = 0; e < J1 * J1; ++e) f += Q[e] * Q[e];
-            step = f > 0.0 ? 1.0 / sqrt(f) : 0.0;
+        const bool own = a < J1;
+        double qa[32], la[32];
+#pragma unroll
+        for (int b = 0; b < 32; ++b) {
+            qa[b] = (own && b < J1) ? Q[a * J1 + b] : 0.0;
+            la[b] = 0.0;
         }
-        wave_sync();
-        const double stp = step;
-        // projected-gradient steps (identity projection)
+        // PG step 1/|Q|_F: row sums of squares, added in row order
+        double fa = 0.0;
+#pragma unroll
+        for (int b = 0; b < 32; ++b) fa += qa[b] * qa[b];
+        double f = 0.0;
+        for (int b = 0; b < J1; ++b) f += lane_d(fa, b);
+        const double stp = f > 0.0 ? 1.0 / sqrt(f) : 0.0;
+        const double ra = own ? r[a] : 0.0;
+        // projected-gradient steps from u = 0 (identity projection)
+        double ua = 0.0;
         for (int it = 0; it < pg_iters; ++it) {
-            double s = 0.0;
-            if (a < J1) {
-                s = -r[a];
-                for (int b = 0; b < J1; ++b) s += Q[a * J1 + b] * u[b];
-            }
-            wave_sync();
-            if (a < J1) u[a] -= stp * s;
-            wave_sync();
+            double s = -ra;
+#pragma unroll
+            for (int b = 0; b < 32; ++b)
+                if (b < J1) s += qa[b] * lane_d(ua, b);
+            if (own) ua -= stp * s;
         }
         // refinement through Q = L L^T: residual g = r - Q u
-        if (a < J1) {
-            double s = r[a];
-            for (int b = 0; b < J1; ++b) s -= Q[a * J1 + b] * u[b];
-            g[a] = s;
-        }
-        for (int e = a; e < J1 * J1; e += 64) L[e] = 0.0;
-        wave_sync();
-        // Cholesky column by column; lane rr forms L[rr][c] for rr > c,
-        // every entry in the order of the textbook row loop
+        double ga = ra;
+#pragma unroll
+        for (int b = 0; b < 32; ++b)
+            if (b < J1) ga -= qa[b] * lane_d(ua, b);
+        // Cholesky column by column; every entry in the order of the
+        // textbook row loop (lane c forms the pivot, lanes below it L[a][c]).
+        // After a pivot <= 0 the factor is not used: the loop carries on
+        // with a unit pivot, so that every loop here has a fixed trip count
+        // and the register arrays keep static indices.
         bool failed = false;
-        for (int c = 0; c < J1; ++c) {
-            double dd = 1.0;
-            if (a == c) {
-                dd = Q[c * J1 + c];
-                for (int t = 0; t < c; ++t) dd -= L[c * J1 + t] * L[c * J1 + t];
-                L[c * J1 + c] = dd > 0.0 ? sqrt(dd) : 1.0;
+#pragma unroll
+        for (int c = 0; c < 32; ++c) {
+            if (c < J1) {
+                double v = qa[c];
+#pragma unroll
+                for (int t = 0; t < c; ++t) v -= la[t] * lane_d(la[t], c);
+                const double dd = lane_d(v, c);
+                failed |= !(dd > 0.0);
+                const double lcc = dd > 0.0 ? sqrt(dd) : 1.0;
+                if (a == c)
+                    la[c] = lcc;
+                else if (a > c && own)
+                    la[c] = v / lcc;
             }
-            failed = __ballot(a == c && !(dd > 0.0)) != 0ull;  // uniform
-            wave_sync();
-            if (failed) break;
-            if (a > c && a < J1) {
-                double v = Q[a * J1 + c];
-                for (int t = 0; t < c; ++t) v -= L[a * J1 + t] * L[c * J1 + t];
-                L[a * J1 + c] = v / L[c * J1 + c];
-            }
-            wave_sync();
         }
+        double za = 0.0;
         if (!failed) {
-            // L y = g: y[t] final at step t, then lanes a > t subtract in
-            // ascending t (the order of the row loop)
-            double v = a < J1 ? g[a] : 0.0;
-            for (int t = 0; t < J1; ++t) {
-                if (a == t) d[t] = v / L[t * J1 + t];
-                wave_sync();
-                if (a > t && a < J1) v -= L[a * J1 + t] * d[t];
+            // L y = g: y_t final at step t, then lanes a > t subtract (ascending t)
+            double va = ga, ya = 0.0;
+#pragma unroll
+            for (int t = 0; t < 32; ++t) {
+                if (t < J1) {
+                    const double yt = lane_d(va / la[t], t);
+                    if (a == t) ya = yt;
+                    if (a > t) va -= la[t] * yt;
+                }
+            }
+            // L^T z = y needs column a of L in lane a: through LDS (Q is no
+            // longer needed)
+            wave_sync();
+            if (own) {
+#pragma unroll
+                for (int t = 0; t < 32; ++t) Q[a * 32 + t] = la[t];
             }
             wave_sync();
-            // L^T z = y: z[t] final at step t (descending), lanes a < t subtract
-            v = a < J1 ? d[a] : 0.0;
-            wave_sync();
-            for (int t = J1 - 1; t >= 0; --t) {
-                if (a == t) d[t] = v / L[t * J1 + t];
-                wave_sync();
-                if (a < t) v -= L[t * J1 + a] * d[t];
+            double lc[32];
+#pragma unroll
+            for (int t = 0; t < 32; ++t) lc[t] = (own && t < J1) ? Q[t * 32 + a] : 0.0;
+            // z_t final at step t (descending), lanes a < t subtract
+            double wa = ya;
+#pragma unroll
+            for (int t = 31; t >= 0; --t) {
+                if (t < J1) {
+                    const double zt = lane_d(wa / la[t], t);
+                    if (a == t) za = zt;
+                    if (a < t) wa -= lc[t] * zt;
+                }
             }
-            wave_sync();
-            if (a < J1) u[a] += d[a];
-            wave_sync();
         }
+        ua += za;
+        double s = 0.0;
+        for (int e = 0; e < J1; ++e) {
+            const double ue = lane_d(ua, e);
+            s += ue * ue;
+        }
+        if (own) u[a] = ua;
         if (a == 0) {
-            double s = 0.0;
-            for (int e = 0; e < J1; ++e) s += u[e] * u[e];
             unorm = sqrt(s);
             bad = failed ? 1 : 0;
         }
     }
     __syncthreads();
-    // cosine scores; rows of zero norm are excluded (NaN), a zero u scores
-    // every other row -inf.  A thread takes kCosRows rows per pass and
-    // issues the loads of kCosCols columns of each before any product, so
-    // one pass waits on memory once per kCosCols columns.
-    constexpr int kCosRows = 9, kCosCols = 12;
-    for (int i0 = tid; i0 < I1; i0 += 256 * kCosRows) {
-        const float* ar[kCosRows];
-        const double* np[kCosRows];
-        double nr[kCosRows], dot[kCosRows];
-#pragma unroll
-        for (int q = 0; q < kCosRows; ++q) {
-            const int i = i0 + 256 * q < I1 ? i0 + 256 * q : I1 - 1;
-            ar[q] = A + (size_t)i * J1;
-            np[q] = anrm + i;
-            dot[q] = 0.0;
-        }
-        for (int c0 = 0; c0 < J1; c0 += kCosCols) {
-            float v[kCosRows][kCosCols];
-#pragma unroll
-            for (int q = 0; q < kCosRows; ++q)
-#pragma unroll
-                for (int c = 0; c < kCosCols; ++c) v[q][c] = ar[q][c0 + c < J1 ? c0 + c : J1 - 1];  // unused past J1
-#pragma unroll
-            for (int q = 0; q < kCosRows; ++q) nr[q] = *np[q];  // with the first columns' loads
-            __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the products
-#pragma unroll
-            for (int c = 0; c < kCosCols; ++c) {
-                if (c0 + c >= J1) break;
-                const double uc = u[c0 + c];
-#pragma unroll
-                for (int q = 0; q < kCosRows; ++q) dot[q] += (double)v[q][c] * uc;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kCosRows; ++q) {
-            const int i = i0 + 256 * q;
-            if (i >= I1) break;
-            double sc = nr[q] > 0.0 ? -INFINITY : NAN;
-            if (nr[q] > 0.0 && unorm > 0.0) sc = dot[q] / (nr[q] * unorm);
-            scores[i] = sc;
-        }
-    }
-    // top k by repeated arg-max: larger score first, lower index on ties;
-    // a taken row is marked with NaN.  Every thread keeps the best of its
-    // own rows (tid, tid + 256, ...); a round reduces these within each
-    // wavefront by lane exchanges, then every thread reduces the four
-    // wavefront results, and only the thread owning the winner rescans.
-    const int lane = tid & 63, wv = tid >> 6;
+    const double un = unorm;
+    // cosine scores, then top k by repeated arg-max (a taken row becomes
+    // NaN).  Every thread keeps the best of its own rows (tid, tid + 256,
+    // ...); a round reduces these within each wavefront by lane exchanges,
+    // then every thread reduces the four wavefront results, and only the
+    // thread owning the winner rescans its rows.
+    double sc[RS ? kRegRows : 1];
     double bs = -INFINITY;
     int bi = -1;
-    for (int i = tid; i < I1; i += 256) {
-        const double sc = scores[i];
-        if (sc != sc) continue;
-        if (bi < 0 || sc > bs) {
-            bs = sc;
-            bi = i;
+    if constexpr (RS) {
+#pragma unroll
+        for (int p = 0; p < kRegRows / 8; ++p) {
+            if (p * 2048 >= I1) break;
+            cosine8(At, anrm, u, un, I1, J1, tid + p * 2048, sc + 8 * p);
+        }
+#pragma unroll
+        for (int q = 0; q < kRegRows; ++q) {
+            const int i = tid + 256 * q;
+            if (i < I1 && sc[q] == sc[q] && (bi < 0 || sc[q] > bs)) {
+                bs = sc[q];
+                bi = i;
+            }
+        }
+    } else {
+        for (int i0 = tid; i0 < I1; i0 += 2048) {
+            double x[8];
+            cosine8(At, anrm, u, un, I1, J1, i0, x);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int i = i0 + 256 * q;
+                if (i >= I1) break;
+                gscores[i] = x[q];
+                if (x[q] == x[q] && (bi < 0 || x[q] > bs)) {
+                    bs = x[q];
+                    bi = i;
+                }
+            }
         }
     }
+    const int lane = tid & 63, wv = tid >> 6;
     for (int t = 0; t < topk; ++t) {
         double ws = bs;
         int wi = bi;
@@ -323,7 +384,7 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
         for (int o = 32; o > 0; o >>= 1) {
             const double s2 = __shfl_xor(ws, o);
             const int i2 = __shfl_xor(wi, o);
-            if (i2 >= 0 && (wi < 0 || s2 > ws || (s2 == ws && i2 < wi))) {
+            if (better(s2, i2, ws, wi)) {
                 ws = s2;
                 wi = i2;
             }
@@ -337,11 +398,9 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
         double s1 = red_s[rb];
         int i1 = red_i[rb];
         for (int w = 1; w < 4; ++w) {
-            const double s2 = red_s[rb + w];
-            const int i2 = red_i[rb + w];
-            if (i2 >= 0 && (i1 < 0 || s2 > s1 || (s2 == s1 && i2 < i1))) {
-                s1 = s2;
-                i1 = i2;
+            if (better(red_s[rb + w], red_i[rb + w], s1, i1)) {
+                s1 = red_s[rb + w];
+                i1 = red_i[rb + w];
             }
         }
         if (tid == 0) {
@@ -349,15 +408,26 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
             top_i[t] = i1;
         }
         if (i1 >= 0 && (i1 & 255) == tid) {
-            scores[i1] = NAN;
             bs = -INFINITY;
             bi = -1;
-            for (int i = tid; i < I1; i += 256) {
-                const double sc = scores[i];
-                if (sc != sc) continue;
-                if (bi < 0 || sc > bs) {
-                    bs = sc;
-                    bi = i;
+            if constexpr (RS) {
+#pragma unroll
+                for (int q = 0; q < kRegRows; ++q) {
+                    const int i = tid + 256 * q;
+                    if (i == i1) sc[q] = NAN;
+                    if (i < I1 && sc[q] == sc[q] && (bi < 0 || sc[q] > bs)) {
+                        bs = sc[q];
+                        bi = i;
+                    }
+                }
+            } else {
+                gscores[i1] = NAN;
+                for (int i = tid; i < I1; i += 256) {
+                    const double x = gscores[i];
+                    if (x == x && (bi < 0 || x > bs)) {
+                        bs = x;
+                        bi = i;
+                    }
                 }
             }
         }
@@ -372,18 +442,12 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
 }
 
 hipError_t launch_serve_setup(const float* A, const float* B, const float* C, const float* G, int I1, int I2, int I3,
-                              int J1, int J2, int J3, double* W, double* anrm, hipStream_t st)
+                              int J1, int J2, int J3, double* W, double* anrm, float* At, hipStream_t st)
 {
-    if (I1 <= kScoreLds) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&serve_solve<true>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 (int)(sizeof(double) * kScoreLds));
-        if (e != hipSuccess) return e;
-    }
     const long long nw = (long long)I3 * I2 * J1;
     hipLaunchKernelGGL(serve_build_w, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, B, C, G, I2, I3, J1, J2,
                        J3, W);
-    hipLaunchKernelGGL(serve_row_norms, dim3((I1 + 255) / 256), dim3(256), 0, st, A, I1, J1, anrm);
+    hipLaunchKernelGGL(serve_rows, dim3((I1 + 255) / 256), dim3(256), 0, st, A, I1, J1, anrm, At);
     return hipGetLastError();
 }
 
@@ -396,17 +460,17 @@ int serve_parts(int n)
 }
 
 hipError_t launch_serve_request(const int32_t* jj, const int32_t* kk, const float* xx, int n, const double* W, int I2,
-                                int J1, double lam, int pg_iters, const float* A, const double* anrm, int I1,
+                                int J1, double lam, int pg_iters, const float* At, const double* anrm, int I1,
                                 int topk, double* part, double* scores, double* out, int* status, hipStream_t st)
 {
     const int np = serve_parts(n);
     const int chunk = n > 0 ? (n + np - 1) / np : 1;
     hipLaunchKernelGGL(serve_gram, dim3(np), dim3(256), 0, st, jj, kk, xx, n, chunk, W, I2, J1, part);
-    if (I1 <= kScoreLds)
-        hipLaunchKernelGGL(serve_solve<true>, dim3(1), dim3(256), sizeof(double) * I1, st, part, np, J1, lam, pg_iters,
-                           A, anrm, I1, topk, scores, out, status);
+    if (I1 <= 256 * kRegRows)
+        hipLaunchKernelGGL(serve_solve<true>, dim3(1), dim3(256), 0, st, part, np, J1, lam, pg_iters, At, anrm, I1,
+                           topk, scores, out, status);
     else
-        hipLaunchKernelGGL(serve_solve<false>, dim3(1), dim3(256), 0, st, part, np, J1, lam, pg_iters, A, anrm, I1,
+        hipLaunchKernelGGL(serve_solve<false>, dim3(1), dim3(256), 0, st, part, np, J1, lam, pg_iters, At, anrm, I1,
                            topk, scores, out, status);
     return hipGetLastError();
 }

@@ -23,9 +23,9 @@
 
 namespace snect {
 hipError_t launch_serve_setup(const float* A, const float* B, const float* C, const float* G, int I1, int I2, int I3,
-                              int J1, int J2, int J3, double* W, double* anrm, hipStream_t st);
+                              int J1, int J2, int J3, double* W, double* anrm, float* At, hipStream_t st);
 hipError_t launch_serve_request(const int32_t* jj, const int32_t* kk, const float* xx, int n, const double* W, int I2,
-                                int J1, double lam, int pg_iters, const float* A, const double* anrm, int I1,
+                                int J1, double lam, int pg_iters, const float* At, const double* anrm, int I1,
                                 int topk, double* part, double* scores, double* out, int* status, hipStream_t st);
 int serve_parts(int n);
 }  // namespace snect
@@ -110,9 +110,9 @@ struct snect_server {
     std::string* err = nullptr;  // the owning context's message
     int32_t I1 = 0, I2 = 0, I3 = 0, J1 = 0;
     snect_server_config cfg{};
-    const float* A = nullptr;   // caller's device factor (read only)
     double* d_W = nullptr;      // [I3][I2][J1]
     double* d_anrm = nullptr;   // [I1]
+    float* d_At = nullptr;      // [J1][I1], A transposed
     char* d_pool = nullptr;
     PoolAlloc pool;
     std::vector<Slot> slots;
@@ -161,7 +161,6 @@ int snect_server_create(snect_ctx* ctx, int32_t I1, int32_t I2, int32_t I3, int3
     s->err = err;
     s->I1 = I1; s->I2 = I2; s->I3 = I3; s->J1 = J1;
     s->cfg = *cfg;
-    s->A = f->A;
     auto fail = [&](int code, const std::string& m) {
         snect_server_destroy(s);
         *err = m;
@@ -169,13 +168,14 @@ int snect_server_create(snect_ctx* ctx, int32_t I1, int32_t I2, int32_t I3, int3
     };
     if (hipMalloc((void**)&s->d_W, sizeof(double) * (size_t)I3 * I2 * J1) != hipSuccess ||
         hipMalloc((void**)&s->d_anrm, sizeof(double) * (size_t)I1) != hipSuccess ||
+        hipMalloc((void**)&s->d_At, sizeof(float) * (size_t)J1 * I1) != hipSuccess ||
         hipMalloc((void**)&s->d_pool, (size_t)cfg->pool_bytes) != hipSuccess) {
         (void)hipGetLastError();
         return fail(SNECT_E_OOM, "server device allocation failed");
     }
     s->pool.init((size_t)cfg->pool_bytes);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (launch_serve_setup(f->A, f->B, f->C, f->G, I1, I2, I3, J1, J2, J3, s->d_W, s->d_anrm, st) != hipSuccess ||
+    if (launch_serve_setup(f->A, f->B, f->C, f->G, I1, I2, I3, J1, J2, J3, s->d_W, s->d_anrm, s->d_At, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return fail(SNECT_E_HIP, "server setup kernels failed");
     s->slots.resize(cfg->max_slots);
@@ -214,6 +214,7 @@ int snect_server_destroy(snect_server* s)
     }
     if (s->d_W) (void)hipFree(s->d_W);
     if (s->d_anrm) (void)hipFree(s->d_anrm);
+    if (s->d_At) (void)hipFree(s->d_At);
     if (s->d_pool) (void)hipFree(s->d_pool);
     delete s;
     return SNECT_OK;
@@ -275,7 +276,7 @@ int snect_server_submit(snect_server* s, int64_t nnz, const int32_t* j, const in
     if (e == hipSuccess)
         e = launch_serve_request(reinterpret_cast<const int32_t*>(dbase), reinterpret_cast<const int32_t*>(dbase + bj),
                                  reinterpret_cast<const float*>(dbase + 2 * bj), (int)nnz, s->d_W, s->I2, s->J1,
-                                 s->cfg.lambda, s->cfg.pg_iters, s->A, s->d_anrm, s->I1, s->cfg.topk, sl.d_part,
+                                 s->cfg.lambda, s->cfg.pg_iters, s->d_At, s->d_anrm, s->I1, s->cfg.topk, sl.d_part,
                                  sl.d_scores, sl.d_out, reinterpret_cast<int*>(sl.d_out + s->out_len()), sl.stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(sl.h_out, sl.d_out, sizeof(double) * (s->out_len() + 1), hipMemcpyDeviceToHost, sl.stream);

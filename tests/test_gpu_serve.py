@@ -57,6 +57,31 @@ def test_fold_in_and_topk_match_oracle(setup):
     srv.close()
 
 
+@pytest.mark.parametrize("I1,J", [(7000, (20, 8, 3)), (300, (32, 6, 2))])
+def test_many_patients_and_full_rank(I1, J):
+    """More patients than the scores kept in registers (global scores path),
+    and the largest supported patient rank."""
+    import torch
+    import paper_1711_08095_amd as sn
+    rng = np.random.default_rng(11)
+    I2, I3 = 400, 3
+    f = [rng.standard_normal((I1, J[0])) * 0.5, rng.standard_normal((I2, J[1])) * 0.5,
+         rng.standard_normal((I3, J[2])) * 0.5, rng.standard_normal(J) * 0.5]
+    f[0][I1 - 2] = 0.0
+    f = [a.astype(np.float32) for a in f]
+    ctx = sn.Context(0)
+    t = [torch.tensor(a, device="cuda") for a in f]
+    srv = sn.Server(ctx, *t, max_slots=2, pg_iters=20, topk=10, lam=0.01)
+    for r in synth.fold_in_requests(seed=78, count=4, I2=I2, I3=I3, nnz_lo=200, nnz_hi=1200):
+        tk = srv.submit(r["j"], r["k"], r["x"])
+        got = None
+        while got is None:
+            got = srv.poll(tk)
+        _check(f, r, got, 0.01)
+    srv.close()
+    ctx.close()
+
+
 def test_alone_equals_in_the_mix(setup):
     import paper_1711_08095_amd as sn
     ctx, f, t, reqs = setup
