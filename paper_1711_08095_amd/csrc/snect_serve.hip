@@ -176,6 +176,26 @@ __device__ inline bool better(double s2, int i2, double s1, int i1)
     return i2 >= 0 && (i1 < 0 || s2 > s1 || (s2 == s1 && i2 < i1));
 }
 
+// A thread's best (bs, bi) and runner-up (cs, ci) among the rows offered.
+struct Best2 {
+    double bs, cs;
+    int bi, ci;
+};
+
+__device__ __attribute__((always_inline)) inline void offer(Best2& c, double x, int i)
+{
+    if (x != x) return;
+    if (better(x, i, c.bs, c.bi)) {
+        c.cs = c.bs;
+        c.ci = c.bi;
+        c.bs = x;
+        c.bi = i;
+    } else if (better(x, i, c.cs, c.ci)) {
+        c.cs = x;
+        c.ci = i;
+    }
+}
+
 // Solve and search, one workgroup per request.  out: u[J1], then for the
 // top k: scores (double), then indices (int, stored as double); status[0]:
 // 1 if Q is not positive definite.  Both are stored once, at the end (a
@@ -255,14 +275,23 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
         for (int b = 0; b < J1; ++b) f += lane_d(fa, b);
         const double stp = f > 0.0 ? 1.0 / sqrt(f) : 0.0;
         const double ra = own ? r[a] : 0.0;
-        // projected-gradient steps from u = 0 (identity projection)
+        // projected-gradient steps from u = 0 (identity projection); the
+        // row-times-u sum runs on four accumulators (columns b mod 4), as
+        // the FP64 multiply-add chain bounds these steps.  Columns J1..
+        // and lanes J1.. hold zeros, so blocks of four need no inner guard.
         double ua = 0.0;
         for (int it = 0; it < pg_iters; ++it) {
-            double s = -ra;
+            double s0 = -ra, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-            for (int b = 0; b < 32; ++b)
-                if (b < J1) s += qa[b] * lane_d(ua, b);
-            if (own) ua -= stp * s;
+            for (int b = 0; b < 32; b += 4) {
+                if (b < J1) {
+                    s0 += qa[b] * lane_d(ua, b);
+                    s1 += qa[b + 1] * lane_d(ua, b + 1);
+                    s2 += qa[b + 2] * lane_d(ua, b + 2);
+                    s3 += qa[b + 3] * lane_d(ua, b + 3);
+                }
+            }
+            if (own) ua -= stp * ((s0 + s1) + (s2 + s3));
         }
         // refinement through Q = L L^T: residual g = r - Q u
         double ga = ra;
@@ -339,13 +368,14 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
     __syncthreads();
     const double un = unorm;
     // cosine scores, then top k by repeated arg-max (a taken row becomes
-    // NaN).  Every thread keeps the best of its own rows (tid, tid + 256,
-    // ...); a round reduces these within each wavefront by lane exchanges,
-    // then every thread reduces the four wavefront results, and only the
-    // thread owning the winner rescans its rows.
+    // NaN).  Every thread keeps the best and the runner-up of its own rows
+    // (tid, tid + 256, ...); a round reduces the bests within each
+    // wavefront by lane exchanges, then every thread reduces the four
+    // wavefront results.  The thread owning the winner promotes its
+    // runner-up, and rescans its rows only when it has none (it won before).
     double sc[RS ? kRegRows : 1];
-    double bs = -INFINITY;
-    int bi = -1;
+    Best2 cb{-INFINITY, -INFINITY, -1, -1};
+    bool have2 = true;  // cb.cs, cb.ci is the runner-up of the remaining rows
     if constexpr (RS) {
 #pragma unroll
         for (int p = 0; p < kRegRows / 8; ++p) {
@@ -353,13 +383,8 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
             cosine8(At, anrm, u, un, I1, J1, tid + p * 2048, sc + 8 * p);
         }
 #pragma unroll
-        for (int q = 0; q < kRegRows; ++q) {
-            const int i = tid + 256 * q;
-            if (i < I1 && sc[q] == sc[q] && (bi < 0 || sc[q] > bs)) {
-                bs = sc[q];
-                bi = i;
-            }
-        }
+        for (int q = 0; q < kRegRows; ++q)
+            if (tid + 256 * q < I1) offer(cb, sc[q], tid + 256 * q);
     } else {
         for (int i0 = tid; i0 < I1; i0 += 2048) {
             double x[8];
@@ -369,17 +394,14 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
                 const int i = i0 + 256 * q;
                 if (i >= I1) break;
                 gscores[i] = x[q];
-                if (x[q] == x[q] && (bi < 0 || x[q] > bs)) {
-                    bs = x[q];
-                    bi = i;
-                }
+                offer(cb, x[q], i);
             }
         }
     }
     const int lane = tid & 63, wv = tid >> 6;
     for (int t = 0; t < topk; ++t) {
-        double ws = bs;
-        int wi = bi;
+        double ws = cb.bs;
+        int wi = cb.bi;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             const double s2 = __shfl_xor(ws, o);
@@ -408,26 +430,26 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
             top_i[t] = i1;
         }
         if (i1 >= 0 && (i1 & 255) == tid) {
-            bs = -INFINITY;
-            bi = -1;
             if constexpr (RS) {
 #pragma unroll
-                for (int q = 0; q < kRegRows; ++q) {
-                    const int i = tid + 256 * q;
-                    if (i == i1) sc[q] = NAN;
-                    if (i < I1 && sc[q] == sc[q] && (bi < 0 || sc[q] > bs)) {
-                        bs = sc[q];
-                        bi = i;
-                    }
-                }
+                for (int q = 0; q < kRegRows; ++q)
+                    if (tid + 256 * q == i1) sc[q] = NAN;
             } else {
                 gscores[i1] = NAN;
-                for (int i = tid; i < I1; i += 256) {
-                    const double x = gscores[i];
-                    if (x == x && (bi < 0 || x > bs)) {
-                        bs = x;
-                        bi = i;
-                    }
+            }
+            if (have2) {
+                cb.bs = cb.cs;
+                cb.bi = cb.ci;
+                have2 = false;
+            } else {
+                cb = Best2{-INFINITY, -INFINITY, -1, -1};
+                have2 = true;
+                if constexpr (RS) {
+#pragma unroll
+                    for (int q = 0; q < kRegRows; ++q)
+                        if (tid + 256 * q < I1) offer(cb, sc[q], tid + 256 * q);
+                } else {
+                    for (int i = tid; i < I1; i += 256) offer(cb, gscores[i], i);
                 }
             }
         }
