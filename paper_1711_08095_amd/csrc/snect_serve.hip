@@ -182,6 +182,46 @@ struct Best2 {
     int bi, ci;
 };
 
+// Best candidate of the wavefront in every lane: four DPP exchange steps
+// within rows of 16 lanes (quad_perm xor 1, xor 2, row_ror 4, row_ror 8),
+// then exchanges across rows.  `better` is a strict total order on
+// candidates, so the order of the steps does not change the result.
+template <int CTRL>
+__device__ inline int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+
+template <int CTRL>
+__device__ inline void best_step_dpp(double& s, int& i)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, s);
+    const unsigned lo = (unsigned)dpp_i<CTRL>((int)(unsigned)b), hi = (unsigned)dpp_i<CTRL>((int)(unsigned)(b >> 32));
+    const double s2 = __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+    const int i2 = dpp_i<CTRL>(i);
+    if (better(s2, i2, s, i)) {
+        s = s2;
+        i = i2;
+    }
+}
+
+__device__ inline void wave_best(double& s, int& i)
+{
+    best_step_dpp<0xB1>(s, i);   // quad_perm [1,0,3,2]
+    best_step_dpp<0x4E>(s, i);   // quad_perm [2,3,0,1]
+    best_step_dpp<0x124>(s, i);  // row_ror 4
+    best_step_dpp<0x128>(s, i);  // row_ror 8
+#pragma unroll
+    for (int o = 16; o <= 32; o <<= 1) {
+        const double s2 = __shfl_xor(s, o);
+        const int i2 = __shfl_xor(i, o);
+        if (better(s2, i2, s, i)) {
+            s = s2;
+            i = i2;
+        }
+    }
+}
+
 __device__ __attribute__((always_inline)) inline void offer(Best2& c, double x, int i)
 {
     if (x != x) return;
@@ -402,15 +442,7 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
     for (int t = 0; t < topk; ++t) {
         double ws = cb.bs;
         int wi = cb.bi;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const double s2 = __shfl_xor(ws, o);
-            const int i2 = __shfl_xor(wi, o);
-            if (better(s2, i2, ws, wi)) {
-                ws = s2;
-                wi = i2;
-            }
-        }
+        wave_best(ws, wi);
         const int rb = (t & 1) * 4;  // a buffer is rewritten two rounds later, past one more barrier
         if (lane == 0) {
             red_s[rb + wv] = ws;
