@@ -264,7 +264,9 @@ def sweep_autotune(ctx: "Context", problems, factors, trials: int = 1) -> float:
 
 class Server:
     """snect_server_*: fold-in and top-k search for new patients against
-    fixed device factors, with continuous batching."""
+    fixed device factors, with continuous batching.  The server derives what
+    it needs from the factors before the constructor returns and does not
+    read them afterwards."""
 
     def __init__(self, ctx: "Context", A, B, C, G, max_slots: int = 16, pool_bytes: int = 256 << 20,
                  pg_iters: int = 20, topk: int = 10, lam: float = 0.01):
@@ -273,7 +275,6 @@ class Server:
         I3, J3 = C.shape
         self.ctx = ctx
         self.J1, self.topk = int(J1), int(topk)
-        self._keep = (A, B, C, G)  # the server reads A while it lives
         f = Factors()
         f.A = _dev_ptr(A, (I1, J1), "A")
         f.B = _dev_ptr(B, (I2, J2), "B")
