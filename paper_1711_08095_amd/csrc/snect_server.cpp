@@ -18,6 +18,8 @@
 #include <string>
 #include <vector>
 
+#include <emmintrin.h>
+
 #include "../../include/snect.h"
 #include "snect_internal.h"
 
@@ -247,24 +249,44 @@ int snect_server_submit(snect_server* s, int64_t nnz, const int32_t* j, const in
         sl.h_in_cap = bytes;
     }
     // copy the cells to the slot's pinned staging and check them in the same
-    // branch-free pass (vectorised)
+    // branch-free pass, four cells per step.  The staging is written with
+    // non-temporal stores (no read of the destination lines, nothing of it
+    // left in the caches; its three arrays start 256-byte aligned); the store
+    // fence after the pass orders them before the upload is queued.
     {
         int32_t* hj = reinterpret_cast<int32_t*>(sl.h_in);
         int32_t* hk = reinterpret_cast<int32_t*>(sl.h_in + bj);
         float* hx = reinterpret_cast<float*>(sl.h_in + 2 * bj);
         const uint32_t I2 = (uint32_t)s->I2, I3 = (uint32_t)s->I3;
-        uint32_t bad_index = 0, bad_value = 0;
-        for (int64_t t = 0; t < nnz; ++t) {
+        // unsigned v < I: (v ^ 2^31) < (I ^ 2^31) as signed 32-bit integers
+        const __m128i bias = _mm_set1_epi32(INT32_MIN), expo = _mm_set1_epi32(0x7f800000);
+        const __m128i lim2 = _mm_set1_epi32((int32_t)(I2 ^ 0x80000000u)), lim3 = _mm_set1_epi32((int32_t)(I3 ^ 0x80000000u));
+        __m128i ok = _mm_set1_epi32(-1), inf = _mm_setzero_si128();
+        int64_t t = 0;
+        for (; t + 4 <= nnz; t += 4) {
+            const __m128i vj = _mm_loadu_si128(reinterpret_cast<const __m128i*>(j + t));
+            const __m128i vk = _mm_loadu_si128(reinterpret_cast<const __m128i*>(k + t));
+            const __m128i vx = _mm_loadu_si128(reinterpret_cast<const __m128i*>(x + t));
+            ok = _mm_and_si128(ok, _mm_and_si128(_mm_cmpgt_epi32(lim2, _mm_xor_si128(vj, bias)),
+                                                 _mm_cmpgt_epi32(lim3, _mm_xor_si128(vk, bias))));
+            inf = _mm_or_si128(inf, _mm_cmpeq_epi32(_mm_and_si128(vx, expo), expo));  // Inf or NaN
+            _mm_stream_si128(reinterpret_cast<__m128i*>(hj + t), vj);
+            _mm_stream_si128(reinterpret_cast<__m128i*>(hk + t), vk);
+            _mm_stream_si128(reinterpret_cast<__m128i*>(hx + t), vx);
+        }
+        uint32_t bad_index = _mm_movemask_epi8(ok) != 0xffff, bad_value = _mm_movemask_epi8(inf) != 0;
+        for (; t < nnz; ++t) {
             const int32_t jt = j[t], kt = k[t];
             const float xt = x[t];
             uint32_t xb;
             std::memcpy(&xb, &xt, 4);
             bad_index |= (uint32_t)((uint32_t)jt >= I2) | (uint32_t)((uint32_t)kt >= I3);
-            bad_value |= (uint32_t)((xb & 0x7f800000u) == 0x7f800000u);  // Inf or NaN
+            bad_value |= (uint32_t)((xb & 0x7f800000u) == 0x7f800000u);
             hj[t] = jt;
             hk[t] = kt;
             hx[t] = xt;
         }
+        _mm_sfence();
         if (bad_index) return srv_err(s, SNECT_E_INDEX, "request cell out of range");
         if (bad_value) return srv_err(s, SNECT_E_ARG, "non-finite request value");
     }

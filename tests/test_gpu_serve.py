@@ -146,6 +146,23 @@ def test_admission_and_errors(setup):
     with pytest.raises(sn.SnectError) as e:
         srv.submit(np.array([3, 4], np.int32), np.array([0, -1], np.int32), np.ones(2, np.float32))
     assert e.value.code == -2  # negative platform
+    # the same checks on cells inside the four-wide part of the pass and in its tail
+    for pos in (0, 3, 6, 9):
+        for field, bad, code in (("j", 900, -2), ("j", -5, -2), ("k", 5, -2), ("k", -1, -2), ("x", np.inf, -1),
+                                 ("x", np.nan, -1)):
+            cells = {"j": np.arange(11, dtype=np.int32) * 80, "k": np.arange(11, dtype=np.int32) % 5,
+                     "x": np.ones(11, np.float32)}
+            cells[field][pos] = bad
+            with pytest.raises(sn.SnectError) as e:
+                srv.submit(cells["j"], cells["k"], cells["x"])
+            assert e.value.code == code, (pos, field, bad)
+    # cells at the upper limits are admitted (with lam = 0 and five distinct
+    # cells the system is singular, which the poll reports)
+    tk = srv.submit(np.full(11, 899, np.int32), np.arange(11, dtype=np.int32) % 5, np.ones(11, np.float32))
+    with pytest.raises(sn.SnectError) as e:
+        while srv.poll(tk) is None:
+            pass
+    assert e.value.code == -1
     # lambda = 0 and a single cell: the system is singular, that request fails alone
     tk_bad = srv.submit(np.array([3], np.int32), np.array([1], np.int32), np.ones(1, np.float32))
     r = reqs[1]
