@@ -61,51 +61,83 @@ constexpr int kFoldBatch = 128;  // nonzeros staged per pass (34 KB of LDS)
 // Partial Gram sums: workgroup g takes nonzeros [g*chunk, (g+1)*chunk)
 // (at most kServeMaxParts workgroups per request).
 // Entry e < J1(J1+1)/2 is Q[a][b] (a <= b, row-major upper triangle); entry
-// NQ + a is r[a].
+// NQ + a is r[a].  G = floor(256 / ne) threads share an entry (G = 1 when
+// ne > 256, a thread then taking entries tid, tid + 256, tid + 512): slice
+// s of a batch's nb nonzeros is [s*nb/G, (s+1)*nb/G), and the G sums of an
+// entry are added in slice order at the end.
 __global__ __launch_bounds__(256) void serve_gram(const int32_t* jj, const int32_t* kk, const float* xx, int n,
                                                   int chunk, const double* W, int I2, int J1, double* part)
 {
     __shared__ double wb[kFoldBatch * 33];
     __shared__ double xb[kFoldBatch];
+    __shared__ long long rbase[kFoldBatch];
+    __shared__ double psum[576];
     const int tid = threadIdx.x, g = blockIdx.x;
     const int nq = J1 * (J1 + 1) / 2, ne = nq + J1;
+    const int G = ne < 256 ? 256 / ne : 1;
     const int z0 = g * chunk, z1 = (z0 + chunk) < n ? (z0 + chunk) : n;
-    double acc[3] = {0.0, 0.0, 0.0};  // entries tid, tid+256, tid+512 (ne <= 560)
+    // this thread's tasks (entry, slice) and the operands of each entry
+    int ta[3], tb[3], tsl[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        const int task = tid + 256 * u;
+        const int e = task % ne, sl = task / ne;
+        tsl[u] = task < ne * G ? sl : -1;
+        if (e < nq) {
+            // row a of the upper triangle starts at a*J1 - a(a-1)/2
+            int aa = 0, rem = e;
+            while (rem >= J1 - aa) {
+                rem -= J1 - aa;
+                ++aa;
+            }
+            ta[u] = aa;
+            tb[u] = aa + rem;
+        } else {
+            ta[u] = e - nq;
+            tb[u] = -1;  // r[a]: the value times w_a
+        }
+    }
+    double acc[3] = {0.0, 0.0, 0.0};
     for (int b0 = z0; b0 < z1; b0 += kFoldBatch) {
         const int nb = (z1 - b0) < kFoldBatch ? (z1 - b0) : kFoldBatch;
         __syncthreads();
-        // the batch's rows of W, every thread gathering (independent loads)
-        for (int idx = tid; idx < nb * J1; idx += 256) {
-            const int t = idx / J1, a = idx - t * J1, z = b0 + t;
-            wb[t * 33 + a] = W[((size_t)kk[z] * I2 + jj[z]) * J1 + a];
+        if (tid < nb) {
+            const int z = b0 + tid;
+            rbase[tid] = ((long long)kk[z] * I2 + jj[z]) * J1;
+            xb[tid] = (double)xx[z];
         }
-        if (tid < nb) xb[tid] = (double)xx[b0 + tid];
+        __syncthreads();
+        // the batch's rows of W, every thread gathering (independent loads)
+#pragma unroll 4
+        for (int idx = tid; idx < nb * J1; idx += 256) {
+            const int t = idx / J1, c = idx - t * J1;
+            wb[t * 33 + c] = W[rbase[t] + c];
+        }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < 3; ++u) {
-            const int e = tid + 256 * u;
-            if (e >= ne) continue;
+            if (tsl[u] < 0) continue;
+            const int t0 = (int)(((long long)nb * tsl[u]) / G), t1 = (int)(((long long)nb * (tsl[u] + 1)) / G);
+            const int aa = ta[u], bb = tb[u];
             double s = acc[u];
-            if (e < nq) {
-                // row a of the upper triangle starts at a*J1 - a(a-1)/2
-                int a = 0, rem = e;
-                while (rem >= J1 - a) {
-                    rem -= J1 - a;
-                    ++a;
-                }
-                const int b = a + rem;
-                for (int t = 0; t < nb; ++t) s += wb[t * 33 + a] * wb[t * 33 + b];
+            if (bb >= 0) {
+#pragma unroll 4
+                for (int t = t0; t < t1; ++t) s += wb[t * 33 + aa] * wb[t * 33 + bb];
             } else {
-                const int a = e - nq;
-                for (int t = 0; t < nb; ++t) s += xb[t] * wb[t * 33 + a];
+#pragma unroll 4
+                for (int t = t0; t < t1; ++t) s += xb[t] * wb[t * 33 + aa];
             }
             acc[u] = s;
         }
     }
 #pragma unroll
-    for (int u = 0; u < 3; ++u) {
-        const int e = tid + 256 * u;
-        if (e < ne) part[(size_t)g * ne + e] = acc[u];
+    for (int u = 0; u < 3; ++u)
+        if (tsl[u] >= 0) psum[tid + 256 * u] = acc[u];
+    __syncthreads();
+    for (int e = tid; e < ne; e += 256) {
+        double s = psum[e];
+        for (int sl = 1; sl < G; ++sl) s += psum[sl * ne + e];
+        part[(size_t)g * ne + e] = s;
     }
 }
 
