@@ -439,15 +439,18 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
     }
     __syncthreads();
     const double un = unorm;
-    // cosine scores, then top k by repeated arg-max (a taken row becomes
-    // NaN).  Every thread keeps the best and the runner-up of its own rows
-    // (tid, tid + 256, ...); a round reduces the bests within each
-    // wavefront by lane exchanges, then every thread reduces the four
-    // wavefront results.  The thread owning the winner promotes its
-    // runner-up, and rescans its rows only when it has none (it won before).
+    // cosine scores, then top k by repeated arg-max.  Every thread keeps the
+    // best and the runner-up of its own rows (tid, tid + 256, ...); a round
+    // reduces the bests within each wavefront by lane exchanges, then every
+    // thread reduces the four wavefront results.  The thread owning the
+    // winner promotes its runner-up, and rescans its rows only when it has
+    // none (it won before).  A thread's rows go in decreasing order, so the
+    // rows it has left are those worse than the last one taken.
     double sc[RS ? kRegRows : 1];
     Best2 cb{-INFINITY, -INFINITY, -1, -1};
     bool have2 = true;  // cb.cs, cb.ci is the runner-up of the remaining rows
+    double lt_s = 0.0;  // the last row this thread gave up (none while lt_i < 0)
+    int lt_i = -1;
     if constexpr (RS) {
 #pragma unroll
         for (int p = 0; p < kRegRows / 8; ++p) {
@@ -494,13 +497,8 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
             top_i[t] = i1;
         }
         if (i1 >= 0 && (i1 & 255) == tid) {
-            if constexpr (RS) {
-#pragma unroll
-                for (int q = 0; q < kRegRows; ++q)
-                    if (tid + 256 * q == i1) sc[q] = NAN;
-            } else {
-                gscores[i1] = NAN;
-            }
+            lt_s = s1;
+            lt_i = i1;
             if (have2) {
                 cb.bs = cb.cs;
                 cb.bi = cb.ci;
@@ -511,9 +509,11 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
                 if constexpr (RS) {
 #pragma unroll
                     for (int q = 0; q < kRegRows; ++q)
-                        if (tid + 256 * q < I1) offer(cb, sc[q], tid + 256 * q);
+                        if (tid + 256 * q < I1 && better(lt_s, lt_i, sc[q], tid + 256 * q))
+                            offer(cb, sc[q], tid + 256 * q);
                 } else {
-                    for (int i = tid; i < I1; i += 256) offer(cb, gscores[i], i);
+                    for (int i = tid; i < I1; i += 256)
+                        if (better(lt_s, lt_i, gscores[i], i)) offer(cb, gscores[i], i);
                 }
             }
         }
