@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_MFMA_PEAK_TFLOPS = 157.3  # dense FP32 matrix-core peak
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
@@ -82,6 +83,26 @@ def measured_traffic(kernel: str):
     if vals.get("kernel_source_sha256") != sha or vals.get("traffic_kernel") != kernel:
         return None
     return float(vals["traffic_bytes_per_launch"])
+
+
+MFMA_COUNTERS = os.path.join(ROOT, "profiles", "strata_persistent_pancan_25M_mfma_counters.md")
+
+
+def measured_mfma(kernel: str):
+    """Matrix-core flops per launch and busy-cycle utilisation (percent) of
+    `kernel` from the committed rocprofv3 summary (MfmaFlopsF32, MfmaUtil),
+    or None when that summary was taken on another kernel or on other kernel
+    source."""
+    try:
+        text = open(MFMA_COUNTERS).read()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = dict(re.findall(r"^\s*(mfma_kernel|mfma_flops_per_launch|mfma_util_pct|kernel_source_sha256):\s*(.+?)\s*$",
+                           text, re.M))
+    if vals.get("kernel_source_sha256") != sha or vals.get("mfma_kernel") != kernel:
+        return None
+    return float(vals["mfma_flops_per_launch"]), float(vals["mfma_util_pct"])
 
 
 def log(msg, quiet=False):
@@ -167,6 +188,7 @@ def main():
     # the counter summary covers the default workload only
     default_workload = (nnz == 25_000_000 and ranks == (10, 10, 5) and P == 128 and args.tile == 64)
     traffic = measured_traffic(kernel) if default_workload else None
+    mfma = measured_mfma(kernel) if default_workload else None
     achieved_tf = flops_per_nnz * nnz_per_launch / avg_launch_s / 1e12 if avg_launch_s > 0 else 0.0
 
     out = {
@@ -190,7 +212,12 @@ def main():
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel,
                      "avg_launch_us": avg_launch_s * 1e6, "bytes_per_launch": bytes_per_launch,
-                     "alu_tflops": achieved_tf, "alu_frac": achieved_tf / FP32_VECTOR_PEAK_TFLOPS},
+                     "alu_tflops": achieved_tf, "alu_frac": achieved_tf / FP32_VECTOR_PEAK_TFLOPS,
+                     # counter-measured matrix-core work (padded tiles) over the live launch time
+                     "mfma": None if mfma is None or avg_launch_s <= 0 else {
+                         "flops_per_launch": mfma[0], "tflops": mfma[0] / avg_launch_s / 1e12,
+                         "peak": FP32_MFMA_PEAK_TFLOPS, "frac": mfma[0] / avg_launch_s / 1e12 / FP32_MFMA_PEAK_TFLOPS,
+                         "busy_util_pct": mfma[1]}},
         "phases_ms_per_step": {"graph": tm["graph_ms"] / args.steps,
                                "strata": tm["strata_ms"] / args.steps,
                                "loss": tm["loss_ms"] / args.steps},
