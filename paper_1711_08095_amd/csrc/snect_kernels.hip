@@ -1635,10 +1635,11 @@ struct LossColLds {
 __host__ __device__ inline LossColLds loss_col_layout(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2,
                                                       int J3)
 {
+    const int rl = up4(jp);  // row pitch: whole 16-byte vectors
     LossColLds L;
     int o = 0;
-    L.w = o;   o = up4(o + rows2_max * I3 * jp);      // w1 per gene row and platform
-    L.a = o;   o = up4(o + rows1_max * jp);           // patient rows of the current block
+    L.w = o;   o = up4(o + rows2_max * I3 * rl);      // w1 per gene row and platform
+    L.a = o;   o = up4(o + rows1_max * rl);           // patient rows of the current block
     L.c = o;   o = up4(o + I3 * J3);
     L.red = o; o = up4(o + 2 * 256);
     // set-up only (gene rows, H_k, G) and then the staged records
@@ -1663,6 +1664,7 @@ template <int JP>
 __global__ __launch_bounds__(256) void loss_cols(LossArgs a)
 {
     constexpr int NT = 256;
+    constexpr int RL = (JP + 3) & ~3;  // pitch of the w1 and patient rows (float4 reads)
     extern __shared__ float lds[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int P = a.P, q = blockIdx.x % P, part = blockIdx.x / P, nparts = gridDim.x / P;
@@ -1679,7 +1681,7 @@ __global__ __launch_bounds__(256) void loss_cols(LossArgs a)
     double* red = reinterpret_cast<double*>(lds + L.red);
 
     // set-up: gene rows (zero beyond J2), H_k, then w1 for every (row, k)
-    for (int idx = tid; idx < a.rows1_max * JP; idx += NT) Ab[idx] = 0.f;
+    for (int idx = tid; idx < a.rows1_max * RL; idx += NT) Ab[idx] = 0.f;
     for (int idx = tid; idx < a.rows2_max * JP; idx += NT) Bt[idx] = 0.f;
     for (int idx = tid; idx < I3 * J3; idx += NT) Cs[idx] = a.C[idx];
     for (int idx = tid; idx < J1 * J2 * J3; idx += NT) Gs[idx] = a.G[idx];
@@ -1695,7 +1697,7 @@ __global__ __launch_bounds__(256) void loss_cols(LossArgs a)
         float w1 = 0.f;
 #pragma unroll
         for (int y = 0; y < JP; ++y) w1 = fmaf(H[y], bv[y], w1);
-        W[idx] = w1;
+        W[(l * I3 + k) * RL + x] = w1;
     }
     __syncthreads();
 
@@ -1735,11 +1737,11 @@ __global__ __launch_bounds__(256) void loss_cols(LossArgs a)
                     const int idx = tid + h * NT;
                     if (idx < nrow) {
                         const int l = idx / J1, c = idx - l * J1;
-                        Ab[l * JP + c] = rowv[h];
+                        Ab[l * RL + c] = rowv[h];
                     }
                 }
             } else {
-                load_rows(Ab, a.Ap, s1, r1, J1, JP, tid, NT);
+                load_rows(Ab, a.Ap, s1, r1, J1, RL, tid, NT);
             }
 #pragma unroll
             for (int h = 0; h < kRecRegs; ++h) {
@@ -1760,8 +1762,15 @@ __global__ __launch_bounds__(256) void loss_cols(LossArgs a)
                 if (lane < n) {
                     const uint2 wv = rec[off - z0 + lane];
                     const int il = (int)(wv.x & mask_i), jl = (int)((wv.x >> a.bits_i) & mask_j);
-                    const float* w1 = W + (jl * I3 + k) * JP;
-                    const float* av = Ab + il * JP;
+                    const float4* w4 = reinterpret_cast<const float4*>(W + (jl * I3 + k) * RL);
+                    const float4* a4 = reinterpret_cast<const float4*>(Ab + il * RL);
+                    float w1[RL], av[RL];
+#pragma unroll
+                    for (int v = 0; v < RL / 4; ++v) {
+                        const float4 wq = w4[v], aq = a4[v];
+                        w1[4 * v] = wq.x; w1[4 * v + 1] = wq.y; w1[4 * v + 2] = wq.z; w1[4 * v + 3] = wq.w;
+                        av[4 * v] = aq.x; av[4 * v + 1] = aq.y; av[4 * v + 2] = aq.z; av[4 * v + 3] = aq.w;
+                    }
                     float xt = 0.f;
 #pragma unroll
                     for (int x_ = 0; x_ < JP; ++x_) xt = fmaf(av[x_], w1[x_], xt);
