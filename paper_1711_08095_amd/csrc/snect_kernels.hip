@@ -1629,7 +1629,7 @@ __global__ __launch_bounds__(256) void loss_blocks(LossArgs a)
 constexpr int kLossChunkTiles = 16;  // tiles whose records are staged at once
 
 struct LossColLds {
-    int w, a, u, b, h, g, c, rec, red, total;
+    int w, a, u, b, h, g, c, to, tk, rec, red, total;
 };
 
 __host__ __device__ inline LossColLds loss_col_layout(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2,
@@ -1642,6 +1642,8 @@ __host__ __device__ inline LossColLds loss_col_layout(int jp, int rows1_max, int
     L.a = o;   o = up4(o + rows1_max * rl);           // patient rows of the current block
     L.c = o;   o = up4(o + I3 * J3);
     L.red = o; o = up4(o + 2 * 256);
+    L.to = o;  o = up4(o + kLossChunkTiles + 1);      // the chunk's tile offsets
+    L.tk = o;  o = up4(o + kLossChunkTiles);          // and platforms
     // set-up only (gene rows, H_k, G) and then the staged records
     const int setup = up4(rows2_max * jp) + up4(I3 * jp * jp) + up4(J1 * J2 * J3);
     const int recs = 2 * kLossChunkTiles * kTileMax;
@@ -1679,6 +1681,8 @@ __global__ __launch_bounds__(256) void loss_cols(LossArgs a)
     float* Cs = lds + L.c;
     uint2* rec = reinterpret_cast<uint2*>(lds + L.rec);
     double* red = reinterpret_cast<double*>(lds + L.red);
+    int* toff = reinterpret_cast<int*>(lds + L.to);
+    int* tkk = reinterpret_cast<int*>(lds + L.tk);
 
     // set-up: gene rows (zero beyond J2), H_k, then w1 for every (row, k)
     for (int idx = tid; idx < a.rows1_max * RL; idx += NT) Ab[idx] = 0.f;
@@ -1717,6 +1721,7 @@ __global__ __launch_bounds__(256) void loss_cols(LossArgs a)
         const bool rows_fit = nrow <= kRowRegs * NT;
         float rowv[kRowRegs];
         uint2 recv[kRecRegs];
+        int tov = 0, tkv = 0;
         {
             const float* src = a.Ap + (size_t)s1 * J1;
 #pragma unroll
@@ -1731,6 +1736,8 @@ __global__ __launch_bounds__(256) void loss_cols(LossArgs a)
                 const int i = tid + h * NT;
                 recv[h] = i < nrec ? a.nz[z0 + i] : make_uint2(0u, 0u);
             }
+            if (tid <= c1 - t0) tov = a.tile_off[t0 + tid];
+            if (tid < c1 - t0) tkv = a.tile_k[t0 + tid];
             if (rows_fit) {
 #pragma unroll
                 for (int h = 0; h < kRowRegs; ++h) {
@@ -1748,6 +1755,8 @@ __global__ __launch_bounds__(256) void loss_cols(LossArgs a)
                 const int i = tid + h * NT;
                 if (i < nrec) rec[i] = recv[h];
             }
+            if (tid <= c1 - t0) toff[tid] = tov;
+            if (tid < c1 - t0) tkk[tid] = tkv;
         }
         double acc = 0.0;
         // wavefront w takes the tiles t0 + w, t0 + w + 4, ... (chunks hold a
@@ -1755,10 +1764,17 @@ __global__ __launch_bounds__(256) void loss_cols(LossArgs a)
         for (int c0 = t0; c0 < t1; c0 += kLossChunkTiles) {
             const int c1 = c0 + kLossChunkTiles < t1 ? c0 + kLossChunkTiles : t1;
             const int z0 = a.tile_off[c0], nrec = a.tile_off[c1] - z0;
-            if (c0 > t0) load_records(rec, a.nz + z0, nrec, tid, NT);
+            if (c0 > t0) {
+                // the chunk's tile offsets and platforms in the same round as its records
+                const int to_ = tid <= c1 - c0 ? a.tile_off[c0 + tid] : 0;
+                const int tk_ = tid < c1 - c0 ? a.tile_k[c0 + tid] : 0;
+                load_records(rec, a.nz + z0, nrec, tid, NT);
+                if (tid <= c1 - c0) toff[tid] = to_;
+                if (tid < c1 - c0) tkk[tid] = tk_;
+            }
             __syncthreads();
             for (int tl = c0 + wave; tl < c1; tl += 4) {
-                const int off = a.tile_off[tl], n = a.tile_off[tl + 1] - off, k = a.tile_k[tl];
+                const int off = toff[tl - c0], n = toff[tl - c0 + 1] - off, k = tkk[tl - c0];
                 if (lane < n) {
                     const uint2 wv = rec[off - z0 + lane];
                     const int il = (int)(wv.x & mask_i), jl = (int)((wv.x >> a.bits_i) & mask_j);
