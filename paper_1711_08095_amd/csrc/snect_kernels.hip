@@ -1547,15 +1547,16 @@ size_t loss_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int 
     return align16(4 * (size_t)loss_lds_layout(jp, rows1_max, rows2_max, I3, J1, J2, J3).total);
 }
 
+// Sum over a 256-thread workgroup in a fixed order: a butterfly within each
+// wavefront (both partners of a step add the same two values, so every lane
+// ends with the same bits), then (w0 + w1) + (w2 + w3).
 __device__ inline double block_sum_256(double v, double* red, int tid)
 {
-    red[tid] = v;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
-        __syncthreads();
-    }
-    const double r = red[0];
+    const double r = (red[0] + red[1]) + (red[2] + red[3]);
     __syncthreads();
     return r;
 }
