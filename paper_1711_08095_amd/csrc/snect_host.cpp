@@ -341,10 +341,14 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
     pr->strata_lds = slds; pr->block_lds = blds; pr->loss_lds = llds; pr->core_lds = clds;
     {
         // the column-wise loss kernel when a gene block's w1 table fits
-        // comfortably in LDS; about 1,024 workgroups in all
+        // comfortably in LDS; as many workgroups as are resident at once (at
+        // most 4 per CU, 1,024 in all), so each gene block's table is built
+        // no more often than the workgroups can run together
         const size_t lc = loss_cols_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3);
         pr->loss_cols_lds = (lc <= (size_t)96 * 1024 && lc <= ctx->max_lds) ? lc : 0;
-        pr->loss_parts = std::max(1, std::min(P, 1024 / P));
+        const int per_cu = lc > 0 ? std::max(1, std::min(4, (int)(ctx->max_lds / lc))) : 4;
+        const int resident = ctx->num_cu > 0 ? std::min(1024, ctx->num_cu * per_cu) : 1024;
+        pr->loss_parts = std::max(1, std::min(P, resident / P));
     }
     pr->rec_cap = rec_cap;
     pr->rec_cap_max = rec_cap;
