@@ -109,6 +109,7 @@ typedef struct {
 typedef struct {
     int64_t nnz, ntiles, edges_csr;
     int32_t P, T, rows1_max, rows2_max;
+    int32_t bits_i, bits_j;   /* widths of the row fields of a packed record */
     int32_t n_sub;            /* network sub-steps per epoch                 */
     double d_max;             /* largest weighted gene degree                */
     int64_t device_bytes;     /* device memory held by the problem           */
@@ -158,9 +159,25 @@ int snect_train(snect_problem *prob, snect_factors *f, int32_t start_epoch, int3
  * the given factors, without changing them.  Errors: E_ARG, E_HIP. */
 int snect_evaluate(snect_problem *prob, const snect_factors *f, double *loss, double *rmse);
 
-/* One-shot form: create the problem, copy `init` into `out` (device
- * buffers; they may be the same), train `epochs` epochs from start_epoch,
- * destroy the problem. */
+/* One-shot form of Algorithm 1 (REQUIRE: X, Y, ranks, lambda, lambda_g,
+ * eta; ENSURE: A, B, C, G): create the problem, set the starting factors in
+ * `out` (device buffers), train `epochs` epochs from start_epoch, destroy
+ * the problem.  loss and rmse are as in snect_train.
+ *
+ * init != NULL: the starting factors are copied from `init` (device
+ * buffers; init and out may be the same).
+ * init == NULL: Algorithm 1 starts from random factors.  This library draws
+ * every entry of A, B, C and G (in that order, each row-major) i.i.d. from
+ * N(0, sigma^2) with sigma = (mean of x^2 / (J1 J2 J3))^(1/8), so that the
+ * model values start at the scale of the data (sigma = 1 when nnz = 0 or
+ * every x is 0).  The normals come from the Box-Muller transform
+ * (Box & Muller 1958) of pairs of uniforms (u1, u2) in (0, 1), each
+ * u = (floor(r / 2^11) + 1/2) 2^-53 for a 64-bit draw r of the SplitMix64
+ * stream 2^40 of params->seed (the same stream construction as the plan);
+ * a pair gives sqrt(-2 ln u1) cos(2 pi u2), then sqrt(-2 ln u1)
+ * sin(2 pi u2).  The draw runs on the host in double precision and is
+ * rounded once to float.  The same seed gives the same factors.
+ * Errors: those of snect_problem_create and snect_train. */
 int snect_decompose(snect_ctx *ctx, const snect_tensor *X, const snect_graph *Y,
                     const snect_params *params, const snect_factors *init, snect_factors *out,
                     int32_t start_epoch, int32_t epochs, double *loss, double *rmse);
@@ -181,6 +198,26 @@ int snect_orthonormalize(snect_ctx *ctx, int32_t I1, int32_t I2, int32_t I3, int
  * may be NULL.  Host memory. */
 int snect_plan_export(const snect_problem *prob, int32_t epoch, int32_t *perm1, int32_t *perm2,
                       int32_t *strata);
+
+/* The plan exactly as the stratum kernels read it, copied back from the
+ * device (the random order of Algorithm 1 replaced by the seeded plan), for
+ * bit-exact cross-checks of the index work.  Host buffers, any may be NULL:
+ *   word[nnz], x[nnz]  the packed nonzero records in plan order: block
+ *                      (p, q) = (b / P, b % P) for b = 0 .. P*P-1 in turn,
+ *                      inside a block ascending (k, i, j).  word holds, from
+ *                      bit 0 up, the patient row inside its block (bits_i
+ *                      bits; the row's position in perm1 minus
+ *                      ceil(p I1 / P)), the gene row inside its block
+ *                      (bits_j bits, likewise with perm2 and q) and 6 bits of
+ *                      slot: the record's rank in its tile when the tile is
+ *                      stably ordered by that gene row.  x is the value.
+ *   tile_off[ntiles+1] first record of each tile (and nnz at the end);
+ *   tile_k[ntiles]     platform of each tile (a tile never spans two);
+ *   blk_tile[P*P+1]    first tile of each block (and ntiles at the end).
+ * bits_i, bits_j and ntiles are in snect_info.  Synchronises the stream.
+ * Errors: E_ARG, E_HIP. */
+int snect_plan_layout(const snect_problem *prob, uint32_t *word, float *x, int32_t *tile_off, int32_t *tile_k,
+                      int32_t *blk_tile);
 
 /* Device time of the last snect_train call (milliseconds, summed over its
  * epochs), measured with HIP events on the library stream: [0] network step,

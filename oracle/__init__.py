@@ -67,6 +67,8 @@ def _load():
     lib.oracle_model_values.argtypes = [ctypes.c_void_p] * 6
     lib.oracle_plan_export.restype = ctypes.c_int
     lib.oracle_plan_export.argtypes = [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 7
+    lib.oracle_random_start.restype = None
+    lib.oracle_random_start.argtypes = [ctypes.c_void_p] * 5
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     _lib = lib
@@ -223,6 +225,19 @@ def plan_export(prob: Problem, epoch: int = 0):
     n = nt.value
     return dict(perm1=perm1, perm2=perm2, order=order[:prob.nnz], tile_start=tile_start[: n + 1],
                 block_tile=block_tile, strata=strata)
+
+
+def random_start(prob: Problem):
+    """Algorithm 1's random start as read here: A, B, C, G i.i.d.
+    N(0, sigma^2), sigma = (mean x^2 / (J1 J2 J3))^(1/8), Box-Muller normals
+    from stream 2^40 of the plan seed (see oracle_random_start)."""
+    lib = _load()
+    I1, I2, I3 = prob.dims
+    J1, J2, J3 = prob.ranks
+    A = np.zeros((I1, J1)); B = np.zeros((I2, J2)); C = np.zeros((I3, J3)); G = np.zeros((J1, J2, J3))
+    s = prob._c()
+    lib.oracle_random_start(ctypes.byref(s), A.ctypes.data, B.ctypes.data, C.ctypes.data, G.ctypes.data)
+    return A, B, C, G
 
 
 def splitmix64_at(seed: int, n: int) -> int:

@@ -74,13 +74,13 @@ static uint64_t orc_sm64(uint64_t *s)
     return z ^ (z >> 31);
 }
 
-/* n-th output (0-based) of SplitMix64 seeded with `seed`. */
+/* n-th output (0-based) of SplitMix64 seeded with `seed`.  The generator's
+   state only ever grows by the increment, so before output n it holds
+   seed + n * increment (mod 2^64); one step from there gives output n. */
 uint64_t oracle_splitmix64_at(uint64_t seed, uint64_t n)
 {
-    uint64_t s = seed;
-    uint64_t r = 0;
-    for (uint64_t t = 0; t <= n; ++t) r = orc_sm64(&s);
-    return r;
+    uint64_t s = seed + n * 0x9e3779b97f4a7c15ULL;
+    return orc_sm64(&s);
 }
 
 uint64_t oracle_stream_state(uint64_t seed, uint64_t stream)
@@ -698,6 +698,46 @@ int oracle_plan_export(const oracle_problem *pr, int32_t epoch, int32_t *perm1, 
     if (ntiles) *ntiles = pl->ntiles;
     oracle_plan_free(pl);
     return ORC_OK;
+}
+
+/* Default random start of Algorithm 1 (its first step initialises the
+ * factors randomly; the paper names no distribution).  Reading: every entry
+ * of A, B, C and G, in that order and each row-major, is drawn i.i.d. from
+ * N(0, sigma^2) with sigma = (mean of x^2 / (J1 J2 J3))^(1/8), so that a
+ * model value, a sum of J1 J2 J3 products of four such entries, starts with
+ * the second moment of the data; sigma = 1 when there are no nonzeros or
+ * every value is 0.  Normal deviates by the Box-Muller transform (Box &
+ * Muller, Ann. Math. Statist. 29, 1958): a pair of uniforms (u1, u2) on
+ * (0, 1) gives sqrt(-2 ln u1) cos(2 pi u2), then sqrt(-2 ln u1) sin(2 pi u2).
+ * Uniforms take the top 53 bits of consecutive 64-bit draws r of stream
+ * 2^40 of the seed, u = (floor(r / 2^11) + 1/2) 2^-53. */
+#define ORC_INIT_STREAM (1ULL << 40)
+
+void oracle_random_start(const oracle_problem *pr, double *A, double *B, double *C, double *G)
+{
+    double ss = 0.0;
+    for (int64_t t = 0; t < pr->nnz; ++t) ss += pr->x[t] * pr->x[t];
+    const double ms = pr->nnz > 0 ? ss / (double)pr->nnz : 0.0;
+    const double sigma = ms > 0.0 ? pow(ms / ((double)pr->J1 * pr->J2 * pr->J3), 0.125) : 1.0;
+    const int64_t nA = (int64_t)pr->I1 * pr->J1, nB = (int64_t)pr->I2 * pr->J2;
+    const int64_t nC = (int64_t)pr->I3 * pr->J3, nG = (int64_t)pr->J1 * pr->J2 * pr->J3;
+    double *out[4] = {A, B, C, G};
+    const int64_t len[4] = {nA, nB, nC, nG};
+    uint64_t st = oracle_stream_state(pr->seed, ORC_INIT_STREAM);
+    const double pi = 3.14159265358979323846264338327950288;
+    int part = 0;
+    int64_t at = 0;
+    const int64_t n = nA + nB + nC + nG;
+    for (int64_t t = 0; t < n; t += 2) {
+        const double u1 = ((double)(orc_sm64(&st) >> 11) + 0.5) / 9007199254740992.0;
+        const double u2 = ((double)(orc_sm64(&st) >> 11) + 0.5) / 9007199254740992.0;
+        const double rad = sqrt(-2.0 * log(u1));
+        const double z[2] = {rad * cos(2.0 * pi * u2), rad * sin(2.0 * pi * u2)};
+        for (int h = 0; h < 2 && t + h < n; ++h) {
+            while (at >= len[part]) { ++part; at = 0; }
+            out[part][at++] = sigma * z[h];
+        }
+    }
 }
 
 int oracle_num_threads(void)

@@ -37,7 +37,7 @@ EXPORTS = (
     "snect_decompose", "snect_plan_export", "snect_last_timing", "snect_set_exec",
     "snect_exec_path", "snect_orthonormalize", "snect_server_create", "snect_server_destroy",
     "snect_server_submit", "snect_server_poll", "snect_server_replay", "snect_sweep_train",
-    "snect_autotune", "snect_sweep_autotune",
+    "snect_autotune", "snect_sweep_autotune", "snect_plan_layout",
 )
 PATH_AUTO, PATH_PERSISTENT, PATH_MULTI = 0, 1, 2
 
@@ -86,7 +86,8 @@ class ServerConfig(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("nnz", ctypes.c_int64), ("ntiles", ctypes.c_int64), ("edges_csr", ctypes.c_int64),
                 ("P", ctypes.c_int32), ("T", ctypes.c_int32), ("rows1_max", ctypes.c_int32),
-                ("rows2_max", ctypes.c_int32), ("n_sub", ctypes.c_int32), ("d_max", ctypes.c_double),
+                ("rows2_max", ctypes.c_int32), ("bits_i", ctypes.c_int32), ("bits_j", ctypes.c_int32),
+                ("n_sub", ctypes.c_int32), ("d_max", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("plan_seconds", ctypes.c_double),
                 ("upload_seconds", ctypes.c_double)]
 
@@ -120,6 +121,7 @@ def load(path: str = LIB_PATH):
                                            ctypes.POINTER(Params), ctypes.POINTER(Factors),
                                            ctypes.POINTER(Factors), i32, i32, vp, vp]),
         "snect_plan_export": (ctypes.c_int, [vp, i32, vp, vp, vp]),
+        "snect_plan_layout": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
         "snect_last_timing": (ctypes.c_int, [vp, vp]),
         "snect_set_exec": (ctypes.c_int, [vp, ctypes.POINTER(Exec)]),
         "snect_exec_path": (ctypes.c_int, [vp]),
@@ -230,6 +232,46 @@ def orthonormalize(ctx: "Context", A, B, C, G):
     f.C = _dev_ptr(C, (I3, J3), "C")
     f.G = _dev_ptr(G, (J1, J2, J3), "G")
     _check(load().snect_orthonormalize(ctx.h, I1, I2, I3, J1, J2, J3, ctypes.byref(f)), ctx.h)
+
+
+def decompose(ctx: "Context", dims, i, j, k, x, eu, ev, ew, hyper: "Hyper", out, init=None, epochs: int = 1,
+              start_epoch: int = 0):
+    """snect_decompose: plan, train `epochs` epochs and release the plan in
+    one call.  out = (A, B, C, G) torch device tensors receive the result;
+    init = (A, B, C, G) device tensors, or None for the library's seeded
+    N(0, sigma^2) start.  Returns (loss, rmse)."""
+    lib = load()
+    I1, I2, I3 = (int(d) for d in dims)
+    J1, J2, J3 = (int(r) for r in hyper.ranks)
+    shapes = ((I1, J1), (I2, J2), (I3, J3), (J1, J2, J3))
+
+    def fac(ts, what):
+        f = Factors()
+        f.A, f.B, f.C, f.G = (_dev_ptr(t, sh, f"{what}.{n}") for t, sh, n in zip(ts, shapes, "ABCG"))
+        return f
+
+    keep = [np.ascontiguousarray(a, dtype=np.int32) for a in (i, j, k)]
+    keep.append(np.ascontiguousarray(x, dtype=np.float32))
+    t = Tensor()
+    t.I1, t.I2, t.I3 = I1, I2, I3
+    t.nnz = int(keep[0].shape[0])
+    t.i, t.j, t.k, t.x = (a.ctypes.data for a in keep)
+    eu = np.ascontiguousarray(np.zeros(0) if eu is None else eu, dtype=np.int32)
+    ev = np.ascontiguousarray(np.zeros(0) if ev is None else ev, dtype=np.int32)
+    ewa = None if ew is None else np.ascontiguousarray(ew, dtype=np.float32)
+    g = Graph()
+    g.E = int(eu.shape[0])
+    g.u, g.v = eu.ctypes.data, ev.ctypes.data
+    g.w = None if ewa is None else ewa.ctypes.data
+    p = hyper.c()
+    fo = fac(out, "out")
+    fi = None if init is None else fac(init, "init")
+    loss = np.zeros(max(epochs, 1))
+    rmse = np.zeros(max(epochs, 1))
+    _check(lib.snect_decompose(ctx.h, ctypes.byref(t), ctypes.byref(g), ctypes.byref(p),
+                               None if fi is None else ctypes.byref(fi), ctypes.byref(fo), int(start_epoch),
+                               int(epochs), loss.ctypes.data, rmse.ctypes.data), ctx.h)
+    return loss[:epochs], rmse[:epochs]
 
 
 def _sweep_args(problems, factors):
@@ -420,6 +462,22 @@ class Problem:
                                         strata.ctypes.data), self.ctx.h)
         return dict(perm1=perm1, perm2=perm2, strata=strata)
 
+    def plan_layout(self):
+        """snect_plan_layout: the packed records (word, x), tile offsets and
+        platforms and block -> tile ranges exactly as they sit on the device,
+        with the field widths bits_i, bits_j."""
+        inf = self.info()
+        nnz, nt, P = int(inf["nnz"]), int(inf["ntiles"]), int(inf["P"])
+        word = np.zeros(max(nnz, 1), np.uint32)
+        x = np.zeros(max(nnz, 1), np.float32)
+        tile_off = np.zeros(nt + 1, np.int32)
+        tile_k = np.zeros(max(nt, 1), np.int32)
+        blk_tile = np.zeros(P * P + 1, np.int32)
+        _check(load().snect_plan_layout(self.h, word.ctypes.data, x.ctypes.data, tile_off.ctypes.data,
+                                        tile_k.ctypes.data, blk_tile.ctypes.data), self.ctx.h)
+        return dict(word=word[:nnz], x=x[:nnz], tile_off=tile_off, tile_k=tile_k[:nt], blk_tile=blk_tile,
+                    bits_i=int(inf["bits_i"]), bits_j=int(inf["bits_j"]))
+
     def set_exec(self, per_launch_timing: bool = False, path: int = PATH_AUTO, waves: int = 0,
                  rec_cap: int = 0):
         """snect_set_exec: per-launch timing events, the stratum driver, the
@@ -466,4 +524,4 @@ class Problem:
 
 __all__ = ["load", "Context", "Problem", "Hyper", "SnectError", "EXPORTS", "ERRORS",
            "PRECISION_FP32", "PRECISION_BF16", "LIB_PATH", "PATH_AUTO", "PATH_PERSISTENT",
-           "PATH_MULTI", "orthonormalize", "Server", "sweep_train", "sweep_autotune"]
+           "PATH_MULTI", "orthonormalize", "Server", "sweep_train", "sweep_autotune", "decompose"]

@@ -55,12 +55,20 @@ uint64_t sm64_next(uint64_t& s)
     return z ^ (z >> 31);
 }
 
-uint64_t stream_start(uint64_t seed, uint64_t stream)
+// Output number n (0-based) of SplitMix64 seeded with `seed`: the state
+// after n + 1 steps is seed + (n + 1) * gamma, then the finaliser.
+uint64_t sm64_at(uint64_t seed, uint64_t n)
 {
-    uint64_t s = seed, r = 0;
-    for (uint64_t t = 0; t <= stream; ++t) r = sm64_next(s);
-    return r;
+    uint64_t s = seed + n * 0x9e3779b97f4a7c15ULL;
+    return sm64_next(s);
 }
+
+// Stream t of a seed starts from output t of SplitMix64(seed).
+uint64_t stream_start(uint64_t seed, uint64_t stream) { return sm64_at(seed, stream); }
+
+// Stream of the default random initialisation (far from the plan's streams
+// 0, 1 and 2 + epoch).
+constexpr uint64_t kInitStream = uint64_t(1) << 40;
 
 void seeded_shuffle(std::vector<int32_t>& v, uint64_t seed, uint64_t stream)
 {
@@ -622,6 +630,8 @@ int snect_problem_info(const snect_problem* pr, snect_info* info)
     info->T = pr->T;
     info->rows1_max = pr->rows1_max;
     info->rows2_max = pr->rows2_max;
+    info->bits_i = pr->bits_i;
+    info->bits_j = pr->bits_j;
     info->n_sub = pr->n_sub;
     info->d_max = pr->dmax;
     int64_t b = 0;
@@ -1109,12 +1119,38 @@ int snect_sweep_autotune(snect_ctx* ctx, int32_t n, snect_problem* const* probs,
     return SNECT_OK;
 }
 
+// Algorithm 1's random start: A, B, C, G (in that order, row-major) i.i.d.
+// N(0, sigma^2), sigma = (mean x^2 / (J1 J2 J3))^(1/8) (1 without data), by
+// the Box-Muller transform of uniforms from the seed's initialisation
+// stream, in double, rounded once to float.
+static std::vector<float> random_start(const snect_tensor* X, const snect_params* pa)
+{
+    double ss = 0.0;
+    for (int64_t t = 0; t < X->nnz; ++t) ss += (double)X->x[t] * (double)X->x[t];
+    const double ms = X->nnz > 0 ? ss / (double)X->nnz : 0.0;
+    const double sigma = ms > 0.0 ? std::pow(ms / ((double)pa->J1 * pa->J2 * pa->J3), 0.125) : 1.0;
+    const size_t n = (size_t)X->I1 * pa->J1 + (size_t)X->I2 * pa->J2 + (size_t)X->I3 * pa->J3 +
+                     (size_t)pa->J1 * pa->J2 * pa->J3;
+    std::vector<float> v(n);
+    uint64_t s = stream_start(pa->seed, kInitStream);
+    const double two_pi = 6.283185307179586476925286766559;
+    auto uniform = [&]() { return ((double)(sm64_next(s) >> 11) + 0.5) * 0x1.0p-53; };
+    for (size_t t = 0; t < n; t += 2) {
+        const double u1 = uniform(), u2 = uniform();
+        const double r = std::sqrt(-2.0 * std::log(u1));
+        v[t] = (float)(sigma * (r * std::cos(two_pi * u2)));
+        if (t + 1 < n) v[t + 1] = (float)(sigma * (r * std::sin(two_pi * u2)));
+    }
+    return v;
+}
+
 int snect_decompose(snect_ctx* ctx, const snect_tensor* X, const snect_graph* Y, const snect_params* params,
                     const snect_factors* init, snect_factors* out, int32_t start_epoch, int32_t epochs, double* loss,
                     double* rmse)
 {
     if (!ctx) return SNECT_E_ARG;
-    int rc = check_factors(ctx, init);
+    ctx->err.clear();
+    int rc = init ? check_factors(ctx, init) : SNECT_OK;
     if (rc) return rc;
     rc = check_factors(ctx, out);
     if (rc) return rc;
@@ -1125,10 +1161,26 @@ int snect_decompose(snect_ctx* ctx, const snect_tensor* X, const snect_graph* Y,
                  szC = (size_t)X->I3 * params->J3 * 4, szG = (size_t)params->J1 * params->J2 * params->J3 * 4;
     hipStream_t st = ctx->stream;
     hipError_t e = hipSuccess;
-    if (init->A != out->A) e = e ? e : hipMemcpyAsync(out->A, init->A, szA, hipMemcpyDeviceToDevice, st);
-    if (init->B != out->B) e = e ? e : hipMemcpyAsync(out->B, init->B, szB, hipMemcpyDeviceToDevice, st);
-    if (init->C != out->C) e = e ? e : hipMemcpyAsync(out->C, init->C, szC, hipMemcpyDeviceToDevice, st);
-    if (init->G != out->G) e = e ? e : hipMemcpyAsync(out->G, init->G, szG, hipMemcpyDeviceToDevice, st);
+    if (init) {
+        if (init->A != out->A) e = e ? e : hipMemcpyAsync(out->A, init->A, szA, hipMemcpyDeviceToDevice, st);
+        if (init->B != out->B) e = e ? e : hipMemcpyAsync(out->B, init->B, szB, hipMemcpyDeviceToDevice, st);
+        if (init->C != out->C) e = e ? e : hipMemcpyAsync(out->C, init->C, szC, hipMemcpyDeviceToDevice, st);
+        if (init->G != out->G) e = e ? e : hipMemcpyAsync(out->G, init->G, szG, hipMemcpyDeviceToDevice, st);
+    } else {
+        std::vector<float> v;
+        try {
+            v = random_start(X, params);
+        } catch (const std::bad_alloc&) {
+            snect_problem_destroy(pr);
+            return set_err(ctx, SNECT_E_OOM, "host allocation for the random start");
+        }
+        const char* h = reinterpret_cast<const char*>(v.data());
+        // synchronous copies: the host vector is released on return
+        e = e ? e : hipMemcpy(out->A, h, szA, hipMemcpyHostToDevice);
+        e = e ? e : hipMemcpy(out->B, h + szA, szB, hipMemcpyHostToDevice);
+        e = e ? e : hipMemcpy(out->C, h + szA + szB, szC, hipMemcpyHostToDevice);
+        e = e ? e : hipMemcpy(out->G, h + szA + szB + szC, szG, hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         snect_problem_destroy(pr);
         return set_err(ctx, SNECT_E_HIP, std::string("copy init: ") + hipGetErrorString(e));
@@ -1149,6 +1201,30 @@ int snect_plan_export(const snect_problem* pr, int32_t epoch, int32_t* perm1, in
         const std::vector<int32_t> o = stratum_order(pr->P, pr->seed, epoch);
         std::memcpy(strata, o.data(), o.size() * 4);
     }
+    return SNECT_OK;
+}
+
+int snect_plan_layout(const snect_problem* pr, uint32_t* word, float* x, int32_t* tile_off, int32_t* tile_k,
+                      int32_t* blk_tile)
+{
+    if (!pr) return SNECT_E_ARG;
+    snect_ctx* ctx = pr->ctx;
+    ctx->err.clear();
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (word || x) {
+        std::vector<uint2> rec((size_t)pr->nnz);
+        if (pr->nnz > 0) HIP_TRY(hipMemcpy(rec.data(), pr->d_nz, (size_t)pr->nnz * sizeof(uint2), hipMemcpyDeviceToHost));
+        for (int64_t t = 0; t < pr->nnz; ++t) {
+            if (word) word[t] = rec[t].x;
+            if (x) std::memcpy(&x[t], &rec[t].y, 4);
+        }
+    }
+    if (tile_off) HIP_TRY(hipMemcpy(tile_off, pr->d_tile_off, (size_t)(pr->ntiles + 1) * 4, hipMemcpyDeviceToHost));
+    if (tile_k && pr->ntiles > 0)
+        HIP_TRY(hipMemcpy(tile_k, pr->d_tile_k, (size_t)pr->ntiles * 4, hipMemcpyDeviceToHost));
+    if (blk_tile)
+        HIP_TRY(hipMemcpy(blk_tile, pr->d_blk_tile, ((size_t)pr->P * pr->P + 1) * 4, hipMemcpyDeviceToHost));
     return SNECT_OK;
 }
 
@@ -1178,22 +1254,48 @@ int snect_set_exec(snect_problem* pr, const snect_exec* ex)
     return SNECT_OK;
 }
 
-int snect_orthonormalize(snect_ctx* ctx, int32_t I1, int32_t I2, int32_t I3, int32_t J1, int32_t J2, int32_t J3,
-                         snect_factors* f)
+static int check_qr_args(snect_ctx* ctx, int32_t I1, int32_t I2, int32_t I3, int32_t J1, int32_t J2, int32_t J3,
+                         const snect_factors* f)
 {
-    if (!ctx) return SNECT_E_ARG;
-    ctx->err.clear();
     int rc = check_factors(ctx, f);
     if (rc) return rc;
     if (I1 < 1 || I2 < 1 || I3 < 1 || J1 < 1 || J2 < 1 || J3 < 1)
         return set_err(ctx, SNECT_E_ARG, "sizes must be positive");
     if (J1 > SNECT_MAX_RANK || J2 > SNECT_MAX_RANK || J3 > SNECT_MAX_RANK || J1 > I1 || J2 > I2 || J3 > I3)
         return set_err(ctx, SNECT_E_RANK, "orthonormalisation needs J_n <= I_n and J_n <= 32");
-    HIP_TRY(hipSetDevice(ctx->device));
+    return SNECT_OK;
+}
+
+// The three modes in turn on `scratch` (qr_scratch_bytes(), FP64) with six
+// status words at `status`; waits for the stream and reports a
+// rank-deficient factor.
+static int run_qr(snect_ctx* ctx, int32_t I1, int32_t I2, int32_t I3, int32_t J1, int32_t J2, int32_t J3,
+                  snect_factors* f, void* scratch, int* status)
+{
     const int Is[3] = {I1, I2, I3}, Js[3] = {J1, J2, J3};
     float* Us[3] = {f->A, f->B, f->C};
-    size_t bytes = 0;
-    for (int n = 0; n < 3; ++n) bytes = std::max(bytes, qr_scratch_bytes(Is[n], Js[n], J1, J2, J3));
+    hipError_t e = launch_qr_clear(status, 6, ctx->stream);
+    for (int n = 0; n < 3 && e == hipSuccess; ++n)
+        e = launch_qr_mode(Us[n], Is[n], Js[n], f->G, J1, J2, J3, n, scratch, status + 2 * n, ctx->stream);
+    int hs[6] = {0, 0, 0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return set_err(ctx, SNECT_E_HIP, std::string("orthonormalize: ") + hipGetErrorString(e));
+    for (int n = 0; n < 3; ++n)
+        if (hs[2 * n] || hs[2 * n + 1])
+            return set_err(ctx, SNECT_E_ARG, "factor " + std::to_string(n + 1) + " is rank-deficient");
+    return SNECT_OK;
+}
+
+int snect_orthonormalize(snect_ctx* ctx, int32_t I1, int32_t I2, int32_t I3, int32_t J1, int32_t J2, int32_t J3,
+                         snect_factors* f)
+{
+    if (!ctx) return SNECT_E_ARG;
+    ctx->err.clear();
+    int rc = check_qr_args(ctx, I1, I2, I3, J1, J2, J3, f);
+    if (rc) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const size_t bytes = qr_scratch_bytes();
     void* scratch = nullptr;
     int* status = nullptr;
     if (hipMalloc(&scratch, bytes) != hipSuccess || hipMalloc((void**)&status, 6 * sizeof(int)) != hipSuccess) {
@@ -1201,19 +1303,11 @@ int snect_orthonormalize(snect_ctx* ctx, int32_t I1, int32_t I2, int32_t I3, int
         if (scratch) (void)hipFree(scratch);
         return set_err(ctx, SNECT_E_OOM, "QR scratch allocation failed");
     }
-    hipError_t e = hipMemsetAsync(status, 0, 6 * sizeof(int), ctx->stream);
-    for (int n = 0; n < 3 && e == hipSuccess; ++n)
-        e = launch_qr_mode(Us[n], Is[n], Js[n], f->G, J1, J2, J3, n, scratch, status + 2 * n, ctx->stream);
-    int hs[6] = {0, 0, 0, 0, 0, 0};
-    if (e == hipSuccess) e = hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    rc = run_qr(ctx, I1, I2, I3, J1, J2, J3, f, scratch, status);
+    (void)hipStreamSynchronize(ctx->stream);
     (void)hipFree(scratch);
     (void)hipFree(status);
-    if (e != hipSuccess) return set_err(ctx, SNECT_E_HIP, std::string("orthonormalize: ") + hipGetErrorString(e));
-    for (int n = 0; n < 3; ++n)
-        if (hs[2 * n] || hs[2 * n + 1])
-            return set_err(ctx, SNECT_E_ARG, "factor " + std::to_string(n + 1) + " is rank-deficient");
-    return SNECT_OK;
+    return rc;
 }
 
 int snect_exec_path(const snect_problem* pr)

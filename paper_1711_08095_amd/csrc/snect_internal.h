@@ -153,9 +153,11 @@ hipError_t prepare_kernels(int jp, size_t loss_lds, size_t core_lds, size_t loss
 // Allows the stratum kernels of one variant more than 64 KB of LDS.
 hipError_t prepare_strata(int jp, int bf, int nw, size_t strata_lds);
 // Orthonormalisation of one mode (FP64 CholeskyQR2); see snect_qr.hip.
-size_t qr_scratch_bytes(int I, int J, int J1, int J2, int J3);
+// Scratch of one mode (independent of the factor's row count).
+size_t qr_scratch_bytes();
 hipError_t launch_qr_mode(float* U, int I, int J, float* G, int J1, int J2, int J3, int mode, void* scratch,
                           int* status, hipStream_t st);
+hipError_t launch_qr_clear(int* status, int n, hipStream_t st);
 // Largest number of co-resident workgroups of the persistent kernel.
 int persistent_capacity(int jp, int bf, int nw, size_t lds);
 // Largest number of co-resident workgroups of the batched sweep kernel.

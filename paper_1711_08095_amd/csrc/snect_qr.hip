@@ -3,45 +3,89 @@
 // FP32 storage.
 //
 // Each tall factor U (I x J, J <= 32) is factored by CholeskyQR2: the Gram
-// matrix W = U^T U is summed in FP64 over row blocks (fixed order), its
-// Cholesky factor R1 (upper, positive diagonal) gives Q1 = U R1^{-1}; a
-// second pass on Q1 gives Q = Q1 R2^{-1} and R = R2 R1.  R has a positive
-// diagonal, which makes (Q, R) the unique QR factorisation of a full-rank U.
-// The core then takes G <- G x_n R.
+// matrix W1 = U^T U is summed in FP64, its Cholesky factor R1 (upper,
+// positive diagonal) gives Q1 = U R1^{-1}; a second pass on Q1 gives
+// Q = Q1 R2^{-1} and R = R2 R1.  R has a positive diagonal, which makes
+// (Q, R) the unique QR factorisation of a full-rank U.  The core then takes
+// G <- G x_n R.
+//
+// Q1 is never stored: the second Gram pass and the final pass recompute the
+// rows of U R1^{-1} in FP64 from U, block by block.  The scratch a mode
+// needs is therefore independent of I: kQrParts partial Gram matrices, the
+// triangular factors and the new core (qr_scratch_bytes).
 #include <hip/hip_runtime.h>
 
 #include "snect_internal.h"
 
 namespace snect {
 
-constexpr int kQrRows = 128;  // rows per Gram block
+constexpr int kQrParts = 256;  // partial Gram matrices (row ranges) per pass
+constexpr int kQrRows = 64;    // rows staged in LDS at a time
+constexpr int kQrPad = 33;     // LDS row pitch (doubles)
 
-// Partial Gram matrices: block b sums rows [b*kQrRows, ...) of U (or of the
-// double-precision Q1 when U1 != nullptr), U^T U in FP64.
-__global__ __launch_bounds__(256) void qr_gram_partial(const float* U, const double* U1, int I, int J,
-                                                       double* part)
+// Rows [r0, r0 + nr) of U into LDS as FP64 (row pitch kQrPad); with Ri set,
+// each row is replaced by its product with the upper-triangular Ri
+// (q_c = sum_{i <= c} u_i Ri[i][c], ascending i).  tmp: kQrRows * kQrPad
+// doubles of LDS.
+__device__ void qr_stage_rows(const float* U, const double* Ri, int r0, int nr, int J, double* rows, double* tmp,
+                              int tid)
 {
-    __shared__ double rows[kQrRows * 33];
-    const int b = blockIdx.x, tid = threadIdx.x;
-    const int r0 = b * kQrRows, nr = (I - r0) < kQrRows ? (I - r0) : kQrRows;
+    double* dst = Ri ? tmp : rows;
     for (int idx = tid; idx < nr * J; idx += 256) {
         const int r = idx / J, c = idx - r * J;
-        rows[r * 33 + c] = U1 ? U1[(size_t)(r0 + r) * J + c] : (double)U[(size_t)(r0 + r) * J + c];
+        dst[r * kQrPad + c] = (double)U[(size_t)(r0 + r) * J + c];
     }
     __syncthreads();
-    for (int e = tid; e < J * J; e += 256) {
-        const int x = e / J, y = e - x * J;
-        double s = 0.0;
-        for (int r = 0; r < nr; ++r) s += rows[r * 33 + x] * rows[r * 33 + y];
-        part[(size_t)b * J * J + e] = s;
+    if (Ri) {
+        for (int idx = tid; idx < nr * J; idx += 256) {
+            const int r = idx / J, c = idx - r * J;
+            double s = 0.0;
+            for (int i = 0; i <= c; ++i) s += tmp[r * kQrPad + i] * Ri[i * J + c];
+            rows[r * kQrPad + c] = s;
+        }
+        __syncthreads();
     }
 }
 
-// Sum of the partial Gram matrices (ascending block order), Cholesky
-// W = R^T R (R upper, positive diagonal) and the inverse of R, in one
-// workgroup.  status[0] = 1 when W is not positive definite.
-__global__ __launch_bounds__(256) void qr_chol(const double* part, int nb, int J, double* R, double* Rinv,
-                                              int* status)
+// Partial Gram matrices: workgroup b of the kQrParts sums the rows
+// [b I / kQrParts, (b+1) I / kQrParts) of U (Ri == nullptr) or of U Ri,
+// ascending, in FP64.  part[b][x][y] receives the sum.
+__global__ __launch_bounds__(256) void qr_gram_partial(const float* U, const double* Ri, int I, int J, double* part)
+{
+    __shared__ double rows[kQrRows * kQrPad];
+    __shared__ double tmp[kQrRows * kQrPad];
+    __shared__ double ri[32 * 32];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int r0 = (int)(((long long)I * b) / kQrParts), r1 = (int)(((long long)I * (b + 1)) / kQrParts);
+    if (Ri)
+        for (int e = tid; e < J * J; e += 256) ri[e] = Ri[e];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};  // entries tid, tid + 256, ... of the J x J Gram
+    for (int c0 = r0; c0 < r1; c0 += kQrRows) {
+        const int nr = (r1 - c0) < kQrRows ? (r1 - c0) : kQrRows;
+        __syncthreads();
+        qr_stage_rows(U, Ri ? ri : nullptr, c0, nr, J, rows, tmp, tid);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int e = tid + 256 * h;
+            if (e < J * J) {
+                const int x = e / J, y = e - x * J;
+                double s = acc[h];
+                for (int r = 0; r < nr; ++r) s += rows[r * kQrPad + x] * rows[r * kQrPad + y];
+                acc[h] = s;
+            }
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        const int e = tid + 256 * h;
+        if (e < J * J) part[(size_t)b * J * J + e] = acc[h];
+    }
+}
+
+// Sum of the partial Gram matrices (ascending), Cholesky W = R^T R (R upper,
+// positive diagonal) and the inverse of R, in one workgroup.  status[0] = 1
+// when W is not positive definite, 0 otherwise.
+__global__ __launch_bounds__(256) void qr_chol(const double* part, int J, double* R, double* Rinv, int* status)
 {
     __shared__ double W[32 * 32];
     __shared__ double Rs[32 * 32];
@@ -50,7 +94,7 @@ __global__ __launch_bounds__(256) void qr_chol(const double* part, int nb, int J
     const int tid = threadIdx.x;
     for (int e = tid; e < J * J; e += 256) {
         double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += part[(size_t)b * J * J + e];
+        for (int b = 0; b < kQrParts; ++b) s += part[(size_t)b * J * J + e];
         W[e] = s;
     }
     if (tid == 0) bad = 0;
@@ -92,25 +136,28 @@ __global__ __launch_bounds__(256) void qr_chol(const double* part, int nb, int J
     }
 }
 
-// Q = U Rinv row by row (FP64); the result goes to Q64 (pass 1) or to the
-// FP32 factor (pass 2).
-__global__ __launch_bounds__(256) void qr_apply(const float* U, const double* U1, const double* Rinv, int I, int J,
-                                               double* Q64, float* Q32)
+// Q = (U R1^{-1}) R2^{-1}, kQrRows rows per workgroup, in FP64, stored to U
+// as FP32 (each workgroup reads and writes only its own rows).
+__global__ __launch_bounds__(256) void qr_apply(float* U, const double* R1i, const double* R2i, int I, int J)
 {
-    __shared__ double Ri[32 * 32];
+    __shared__ double rows[kQrRows * kQrPad];
+    __shared__ double tmp[kQrRows * kQrPad];
+    __shared__ double r1[32 * 32];
+    __shared__ double r2[32 * 32];
     const int tid = threadIdx.x;
-    for (int e = tid; e < J * J; e += 256) Ri[e] = Rinv[e];
-    __syncthreads();
-    const long long idx = (long long)blockIdx.x * 256 + tid;
-    if (idx >= (long long)I * J) return;
-    const int r = (int)(idx / J), c = (int)(idx - (long long)r * J);
-    double s = 0.0;
-    for (int i = 0; i <= c; ++i) {
-        const double u = U1 ? U1[(size_t)r * J + i] : (double)U[(size_t)r * J + i];
-        s += u * Ri[i * J + c];
+    for (int e = tid; e < J * J; e += 256) {
+        r1[e] = R1i[e];
+        r2[e] = R2i[e];
     }
-    if (Q64) Q64[idx] = s;
-    if (Q32) Q32[idx] = (float)s;
+    const int r0 = blockIdx.x * kQrRows, nr = (I - r0) < kQrRows ? (I - r0) : kQrRows;
+    __syncthreads();
+    qr_stage_rows(U, r1, r0, nr, J, rows, tmp, tid);
+    for (int idx = tid; idx < nr * J; idx += 256) {
+        const int r = idx / J, c = idx - r * J;
+        double s = 0.0;
+        for (int i = 0; i <= c; ++i) s += rows[r * kQrPad + i] * r2[i * J + c];
+        U[(size_t)(r0 + r) * J + c] = (float)s;
+    }
 }
 
 // R = R2 R1 (upper triangular products), then G <- G x_n R:
@@ -144,33 +191,46 @@ __global__ __launch_bounds__(256) void qr_core(const double* R1, const double* R
     for (int e = tid; e < ng; e += 256) G[e] = (float)gtmp[e];
 }
 
-size_t qr_scratch_bytes(int I, int J, int J1, int J2, int J3)
+// Clears the status words (a kernel, not a memset, so that the whole
+// sequence can be captured in a graph).
+__global__ void qr_clear_status(int* status, int n)
 {
-    const int nb = (I + kQrRows - 1) / kQrRows;
-    return sizeof(double) * ((size_t)nb * J * J + 4 * (size_t)J * J + (size_t)I * J + (size_t)J1 * J2 * J3) + 64;
+    if ((int)threadIdx.x < n) status[threadIdx.x] = 0;
+}
+
+// Scratch of one mode's factorisation: kQrParts partial Gram matrices,
+// R1, R1^{-1}, R2, R2^{-1} (32 x 32 each) and the new core (32^3), FP64;
+// independent of I.
+size_t qr_scratch_bytes()
+{
+    return sizeof(double) * ((size_t)kQrParts * 32 * 32 + 4 * 32 * 32 + 32 * 32 * 32);
+}
+
+hipError_t launch_qr_clear(int* status, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(qr_clear_status, dim3(1), dim3(64), 0, st, status, n);
+    return hipGetLastError();
 }
 
 // One mode: U (I x J, device FP32) replaced by Q, G by G x_n R.  scratch
-// holds qr_scratch_bytes(I, J, ...); status (device int) is set to 1 on a
-// rank-deficient factor.
+// holds qr_scratch_bytes(); status[0..1] (device ints, cleared by the
+// caller) are set to 1 when a pass finds the Gram matrix not positive
+// definite (a rank-deficient factor).
 hipError_t launch_qr_mode(float* U, int I, int J, float* G, int J1, int J2, int J3, int mode, void* scratch,
                           int* status, hipStream_t st)
 {
-    const int nb = (I + kQrRows - 1) / kQrRows;
     double* part = static_cast<double*>(scratch);
-    double* R1 = part + (size_t)nb * J * J;
-    double* R1i = R1 + J * J;
-    double* R2 = R1i + J * J;
-    double* R2i = R2 + J * J;
-    double* Q1 = R2i + J * J;
-    double* gtmp = Q1 + (size_t)I * J;
-    const unsigned gapply = (unsigned)(((long long)I * J + 255) / 256);
-    hipLaunchKernelGGL(qr_gram_partial, dim3(nb), dim3(256), 0, st, U, nullptr, I, J, part);
-    hipLaunchKernelGGL(qr_chol, dim3(1), dim3(256), 0, st, part, nb, J, R1, R1i, status);
-    hipLaunchKernelGGL(qr_apply, dim3(gapply), dim3(256), 0, st, U, nullptr, R1i, I, J, Q1, nullptr);
-    hipLaunchKernelGGL(qr_gram_partial, dim3(nb), dim3(256), 0, st, nullptr, Q1, I, J, part);
-    hipLaunchKernelGGL(qr_chol, dim3(1), dim3(256), 0, st, part, nb, J, R2, R2i, status + 1);
-    hipLaunchKernelGGL(qr_apply, dim3(gapply), dim3(256), 0, st, nullptr, Q1, R2i, I, J, nullptr, U);
+    double* R1 = part + (size_t)kQrParts * 32 * 32;
+    double* R1i = R1 + 32 * 32;
+    double* R2 = R1i + 32 * 32;
+    double* R2i = R2 + 32 * 32;
+    double* gtmp = R2i + 32 * 32;
+    const unsigned gapply = (unsigned)((I + kQrRows - 1) / kQrRows);
+    hipLaunchKernelGGL(qr_gram_partial, dim3(kQrParts), dim3(256), 0, st, U, nullptr, I, J, part);
+    hipLaunchKernelGGL(qr_chol, dim3(1), dim3(256), 0, st, part, J, R1, R1i, status);
+    hipLaunchKernelGGL(qr_gram_partial, dim3(kQrParts), dim3(256), 0, st, U, R1i, I, J, part);
+    hipLaunchKernelGGL(qr_chol, dim3(1), dim3(256), 0, st, part, J, R2, R2i, status + 1);
+    hipLaunchKernelGGL(qr_apply, dim3(gapply), dim3(256), 0, st, U, R1i, R2i, I, J);
     hipLaunchKernelGGL(qr_core, dim3(1), dim3(256), 0, st, R1, R2, G, J1, J2, J3, mode, gtmp);
     return hipGetLastError();
 }

@@ -49,7 +49,10 @@ def _check(gpu, orc, init):
 
 @pytest.mark.parametrize("ranks,P,T,lr", [((5, 5, 2), 8, 64, 1e-3), ((10, 10, 5), 8, 64, 1e-3),
                                           ((20, 20, 5), 8, 64, 2e-4), ((16, 12, 3), 3, 37, 2e-4),
-                                          ((32, 17, 4), 8, 16, 2e-4), ((1, 1, 1), 2, 5, 1e-3)])
+                                          ((32, 17, 4), 8, 16, 2e-4), ((1, 1, 1), 2, 5, 1e-3),
+                                          ((4, 3, 2), 8, 64, 1e-3), ((8, 7, 2), 5, 29, 1e-3),
+                                          ((12, 11, 3), 8, 64, 5e-4), ((24, 21, 4), 4, 37, 2e-4),
+                                          ((24, 9, 3), 3, 64, 2e-4)])
 def test_bf16_one_epoch_within_rounding_bound(ctx, ranks, P, T, lr):
     case = planted_case(ranks=ranks, P=P, T=T, lr=lr, sigma=0.5)
     print(f"bf16 planted ranks={ranks} P={P} T={T}", flush=True)

@@ -86,16 +86,26 @@ def test_plan_draws_match_oracle(ctx):
     assert info["ntiles"] == len(o["tile_start"]) - 1
 
 
-@pytest.mark.parametrize("ranks", [(3, 7, 2), (10, 10, 5), (16, 12, 3), (20, 20, 5), (32, 17, 4), (1, 1, 1)])
+# every kernel instantiation (JP = the smallest of 2, 4, 5, 8, 10, 12, 16,
+# 20, 24, 32 that holds max(J1, J2)), with J1 != J2 where it matters
+CORE_SIZES = [(1, 1, 1), (4, 3, 2), (5, 4, 2), (3, 7, 2), (8, 7, 2), (10, 10, 5), (12, 11, 3), (12, 12, 3),
+              (16, 12, 3), (20, 20, 5), (24, 21, 4), (24, 9, 3), (32, 17, 4)]
+
+
+@pytest.mark.parametrize("ranks", CORE_SIZES)
 def test_core_sizes(ctx, ranks):
-    # every kernel instantiation family, ragged block and tile tails
+    # ragged block and tile tails; the one-epoch factor bound and the loss
+    # bound over two epochs
     case = planted_case(seed=77, dims=(61, 83, 6), ranks=ranks, nnz=5000, edges=300, P=5, T=29,
                         sigma=0.5, lr=2e-4)
     print(f"ranks {ranks}", flush=True)
+    orc1 = run_oracle(case, 1)
+    gpu, loss, _, prob = run_gpu(ctx, case, 1)
+    _check_factors(gpu, orc1[:4])
+    assert abs(loss[0] - orc1[4][0]) <= LOSS_TOL * abs(orc1[4][0])
     orc = run_oracle(case, 2)
-    gpu, loss, _, _ = run_gpu(ctx, case, 2)
-    _check_factors(gpu, orc[:4], tol=2e-4)
-    np.testing.assert_allclose(loss, orc[4], rtol=LOSS_TOL)
+    _, loss2, _, _ = run_gpu(ctx, case, 2, prob=prob)
+    np.testing.assert_allclose(loss2, orc[4], rtol=LOSS_TOL)
 
 
 def test_empty_rows_and_platforms(ctx):
@@ -210,22 +220,58 @@ def test_validation_errors(ctx):
         assert e.value.code == code
 
 
-def test_pancan_full_size_one_epoch(ctx):
+@pytest.fixture(scope="module")
+def pancan_data():
+    import time
+    t = time.time()
+    data = synth.pancan_like()
+    print(f"pancan inputs generated in {time.time() - t:.1f}s", flush=True)
+    return data
+
+
+def _pancan_case(data, ranks, init_offset):
+    i, j, k, x, eu, ev = data
+    sigma = synth.default_sigma(x, ranks)
+    A, B, C, G = synth.normal_init(synth.INIT_SEED + init_offset, (4500, 14000, 5), ranks, sigma)
+    return dict(dims=(4500, 14000, 5), ranks=ranks, i=i, j=j, k=k, x=x, eu=eu, ev=ev, ew=None,
+                lam=0.01, lam_g=0.1, lr=1e-3, cls=1.0, P=128, T=64, seed=synth.PLAN_SEED + init_offset,
+                init=tuple(a.astype(np.float32) for a in (A, B, C, G)))
+
+
+def test_pancan_full_size_one_epoch(ctx, pancan_data):
     # the PanCan-shaped workload at full size (4,500 x 14,000 x 5, 25M
     # nonzeros, core 10x10x5, P = 128, T = 64), one epoch against the oracle
     import time
     t = time.time()
-    i, j, k, x, eu, ev = synth.pancan_like()
-    ranks = (10, 10, 5)
-    sigma = synth.default_sigma(x, ranks)
-    A, B, C, G = synth.normal_init(synth.INIT_SEED + 1, (4500, 14000, 5), ranks, sigma)
-    case = dict(dims=(4500, 14000, 5), ranks=ranks, i=i, j=j, k=k, x=x, eu=eu, ev=ev, ew=None,
-                lam=0.01, lam_g=0.1, lr=1e-3, cls=1.0, P=128, T=64, seed=synth.PLAN_SEED + 1,
-                init=tuple(a.astype(np.float32) for a in (A, B, C, G)))
-    print(f"generated in {time.time() - t:.1f}s", flush=True)
+    case = _pancan_case(pancan_data, (10, 10, 5), 1)
     gpu, loss, rmse, prob = run_gpu(ctx, case, 1)
     print(f"gpu done {time.time() - t:.1f}s loss {loss}", flush=True)
     orc = run_oracle(case, 1)
     print(f"oracle done {time.time() - t:.1f}s loss {orc[4]}", flush=True)
     _check_factors(gpu, orc[:4])
     assert abs(loss[0] - orc[4][0]) <= LOSS_TOL * abs(orc[4][0])
+
+
+def test_pancan_full_size_core20_fp32_and_bf16(ctx, pancan_data):
+    # the same tensor with core 20x20x5 (the BF16 workload), one epoch: FP32
+    # within the FP32 bound, BF16 within the rounding bound of the BF16
+    # tests (8 u ||F_oracle - F_0|| + 1e-4 ||F_oracle||, u = 2^-8)
+    import time
+    t = time.time()
+    case = _pancan_case(pancan_data, (20, 20, 5), 2)
+    orc = run_oracle(case, 1)
+    print(f"oracle core 20 done {time.time() - t:.1f}s loss {orc[4]}", flush=True)
+    gpu, loss, _, _ = run_gpu(ctx, case, 1)
+    print(f"fp32 core 20: loss {loss}", flush=True)
+    _check_factors(gpu, orc[:4])
+    assert abs(loss[0] - orc[4][0]) <= LOSS_TOL * abs(orc[4][0])
+    gb, lb, _, _ = run_gpu(ctx, case, 1, precision=1)
+    u = 2.0 ** -8
+    for name, g, o, f0 in zip("ABCG", gb, orc[:4], case["init"]):
+        d = np.linalg.norm(g - o)
+        step = np.linalg.norm(o - np.asarray(f0, np.float64))
+        bound = 8.0 * u * step + FACTOR_TOL * np.linalg.norm(o)
+        print(f"  bf16 {name}: |F-F_orc|/|F_orc| {d / np.linalg.norm(o):.2e}  ratio to u|dF| "
+              f"{d / max(u * step, 1e-300):.2f}", flush=True)
+        assert d <= bound, name
+    assert abs(lb[0] - orc[4][0]) <= 1e-2 * abs(orc[4][0])

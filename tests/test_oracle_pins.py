@@ -52,6 +52,76 @@ def test_splitmix64_published_outputs():
     assert [oracle.splitmix64_at(0, n) for n in range(3)] == vals
 
 
+def test_splitmix64_state_advances_by_the_increment():
+    # output n from the closed form equals n + 1 steps of the recurrence,
+    # stepped here in plain Python integers
+    mask = (1 << 64) - 1
+
+    def steps(seed, n):
+        s, z = seed, 0
+        for _ in range(n + 1):
+            s = (s + 0x9E3779B97F4A7C15) & mask
+            z = s
+            z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+            z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+            z ^= z >> 31
+        return z
+
+    for seed in (0, 1, 3003, (1 << 64) - 5):
+        for n in (0, 1, 2, 17, 200):
+            assert oracle.splitmix64_at(seed, n) == steps(seed, n)
+
+
+def _start_problem(x_scale=1.0, ranks=(3, 4, 2), seed=11, dims=(300, 400, 5), nnz=3000):
+    rng = np.random.default_rng(seed)
+    I1, I2, I3 = dims
+    cells = synth.sample_cells(rng, I1 * I2 * I3, nnz)
+    x = x_scale * rng.standard_normal(nnz)
+    return oracle.Problem(dims, ranks, cells // (I2 * I3), (cells // I3) % I2, cells % I3, x, seed=seed)
+
+
+def test_random_start_is_normal_with_the_stated_sigma():
+    from scipy import stats
+    prob = _start_problem()
+    A, B, C, G = oracle.random_start(prob)
+    z = np.concatenate([a.ravel() for a in (A, B, C, G)])
+    J = np.prod(prob.ranks)
+    sigma = (np.mean(prob.x ** 2) / J) ** 0.125
+    # Kolmogorov-Smirnov against N(0, sigma^2) on 2,530 draws
+    assert stats.kstest(z, "norm", args=(0.0, sigma)).pvalue > 1e-3
+    assert abs(z.std() / sigma - 1.0) < 0.06
+    assert abs(z.mean()) < 4 * sigma / np.sqrt(z.size)
+    # cos and sin halves of a pair are uncorrelated
+    n2 = z.size // 2 * 2
+    assert abs(np.corrcoef(z[0:n2:2], z[1:n2:2])[0, 1]) < 0.1
+    # same seed, same draw; another seed, another draw
+    again = oracle.random_start(prob)
+    for u, v in zip((A, B, C, G), again):
+        np.testing.assert_array_equal(u, v)
+    other = _start_problem(seed=12)
+    assert not np.allclose(oracle.random_start(other)[0][:5], A[:5])
+
+
+def test_random_start_sigma_scales_with_the_data_and_the_core():
+    # the standard normals do not depend on the data: scaling x by s scales
+    # sigma, and so every entry, by s^(1/4); a core with 16 times as many
+    # entries divides sigma by 16^(1/8)
+    base = oracle.random_start(_start_problem())
+    scaled = oracle.random_start(_start_problem(x_scale=16.0))
+    for u, v in zip(base, scaled):
+        np.testing.assert_allclose(v, 2.0 * u, rtol=1e-13)
+    big = _start_problem(ranks=(12, 8, 4))
+    small = _start_problem(ranks=(3, 4, 2))
+    a_big = oracle.random_start(big)[0]
+    a_small = oracle.random_start(small)[0]
+    # A is drawn first, so its first 3 columns' worth of draws coincide
+    np.testing.assert_allclose(a_big.ravel()[:12] * 16.0 ** 0.125, a_small.ravel()[:12], rtol=1e-13)
+    # no data: sigma = 1
+    empty = oracle.Problem((4, 5, 2), (2, 2, 2), np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0), seed=11)
+    e = oracle.random_start(empty)
+    assert 0.3 < np.concatenate([a.ravel() for a in e]).std() < 2.0
+
+
 def test_shuffle_is_a_uniform_permutation():
     for n in (1, 2, 5, 97):
         s = oracle.shuffle(n, 123, 4)
