@@ -192,6 +192,23 @@ int snect_decompose(snect_ctx *ctx, const snect_tensor *X, const snect_graph *Y,
 int snect_orthonormalize(snect_ctx *ctx, int32_t I1, int32_t I2, int32_t I3, int32_t J1, int32_t J2, int32_t J3,
                          snect_factors *f);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * orthonormalisation as snect_orthonormalize, with the same kernels and
+ * bit-identical results, but no allocation of any kind.  Its FP64 scratch
+ * (256 partial 32 x 32 Gram matrices, the triangular factors, a 32^3 core
+ * and the status words: 2,392,320 bytes) is a fixed array in device memory
+ * that every device the library runs on holds until the process ends; its
+ * address is looked up once per device by the first snect_create on it.
+ * Limit: J1, J2, J3 <= 32 (the capacity of that array; larger ranks give
+ * E_RANK), J_n <= I_n.  All calls on one device share the array, so calls
+ * that overlap on a device (two streams or two contexts at once) race and
+ * must be serialised by the caller; each call leaves its last mode's data in
+ * the array and clears its status words before use.  Synchronises the
+ * stream.  Errors: E_ARG (also a rank-deficient factor), E_RANK, E_HIP. */
+int snect_orthonormalize_noalloc(snect_ctx *ctx, int32_t I1, int32_t I2, int32_t I3, int32_t J1, int32_t J2,
+                                 int32_t J3, snect_factors *f);
+
 /* The plan's seeded draws, for cross-checks: perm1[I1] and perm2[I2] (the
  * row at each position of the patient / gene permutation; block of position
  * r is floor(r P / I)), strata[P] (stratum order of `epoch`).  Any pointer

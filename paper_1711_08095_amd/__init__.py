@@ -37,7 +37,7 @@ EXPORTS = (
     "snect_decompose", "snect_plan_export", "snect_last_timing", "snect_set_exec",
     "snect_exec_path", "snect_orthonormalize", "snect_server_create", "snect_server_destroy",
     "snect_server_submit", "snect_server_poll", "snect_server_replay", "snect_sweep_train",
-    "snect_autotune", "snect_sweep_autotune", "snect_plan_layout",
+    "snect_autotune", "snect_sweep_autotune", "snect_plan_layout", "snect_orthonormalize_noalloc",
 )
 PATH_AUTO, PATH_PERSISTENT, PATH_MULTI = 0, 1, 2
 
@@ -126,6 +126,8 @@ def load(path: str = LIB_PATH):
         "snect_set_exec": (ctypes.c_int, [vp, ctypes.POINTER(Exec)]),
         "snect_exec_path": (ctypes.c_int, [vp]),
         "snect_orthonormalize": (ctypes.c_int, [vp, i32, i32, i32, i32, i32, i32, ctypes.POINTER(Factors)]),
+        "snect_orthonormalize_noalloc": (ctypes.c_int, [vp, i32, i32, i32, i32, i32, i32,
+                                                        ctypes.POINTER(Factors)]),
         "snect_server_create": (ctypes.c_int, [vp, i32, i32, i32, i32, i32, i32, ctypes.POINTER(Factors),
                                                ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]),
         "snect_server_destroy": (ctypes.c_int, [vp]),
@@ -272,6 +274,20 @@ def decompose(ctx: "Context", dims, i, j, k, x, eu, ev, ew, hyper: "Hyper", out,
                                None if fi is None else ctypes.byref(fi), ctypes.byref(fo), int(start_epoch),
                                int(epochs), loss.ctypes.data, rmse.ctypes.data), ctx.h)
     return loss[:epochs], rmse[:epochs]
+
+
+def orthonormalize_noalloc(ctx: "Context", A, B, C, G):
+    """snect_orthonormalize_noalloc: the same, on the library's fixed
+    per-device scratch (no allocation; overlapping calls on one device race)."""
+    I1, J1 = A.shape
+    I2, J2 = B.shape
+    I3, J3 = C.shape
+    f = Factors()
+    f.A = _dev_ptr(A, (I1, J1), "A")
+    f.B = _dev_ptr(B, (I2, J2), "B")
+    f.C = _dev_ptr(C, (I3, J3), "C")
+    f.G = _dev_ptr(G, (J1, J2, J3), "G")
+    _check(load().snect_orthonormalize_noalloc(ctx.h, I1, I2, I3, J1, J2, J3, ctypes.byref(f)), ctx.h)
 
 
 def _sweep_args(problems, factors):
@@ -524,4 +540,4 @@ class Problem:
 
 __all__ = ["load", "Context", "Problem", "Hyper", "SnectError", "EXPORTS", "ERRORS",
            "PRECISION_FP32", "PRECISION_BF16", "LIB_PATH", "PATH_AUTO", "PATH_PERSISTENT",
-           "PATH_MULTI", "orthonormalize", "Server", "sweep_train", "sweep_autotune", "decompose"]
+           "PATH_MULTI", "orthonormalize", "orthonormalize_noalloc", "Server", "sweep_train", "sweep_autotune", "decompose"]

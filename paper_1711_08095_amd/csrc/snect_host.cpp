@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -233,6 +234,26 @@ static hipError_t configure_exec(snect_problem* pr, int nw, int rec_cap)
             return set_err(ctx, SNECT_E_HIP, std::string(#call ": ") + hipGetErrorString(_e)); \
     } while (0)
 
+// Device address of the fixed QR scratch on each device, looked up once per
+// device (with that device current) by the first snect_create on it.
+static std::mutex g_qr_mu;
+static void* g_qr_static[256] = {};
+
+static hipError_t qr_static_for(int device, void** ptr)
+{
+    std::lock_guard<std::mutex> lk(g_qr_mu);
+    if (device < 0 || device >= 256) return hipErrorInvalidDevice;
+    if (!g_qr_static[device]) {
+        void* p = nullptr;
+        const hipError_t e = qr_static_scratch_address(&p);
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_qr_static[device] = p;
+    }
+    *ptr = g_qr_static[device];
+    return hipSuccess;
+}
+
 extern "C" {
 
 int snect_create(snect_ctx** out, int device, void* stream)
@@ -257,6 +278,11 @@ int snect_create(snect_ctx** out, int device, void* stream)
         c->max_lds = (size_t)v;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess) c->num_cu = v;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, device) == hipSuccess) c->coop = v;
+    if (qr_static_for(device, &c->qr_static) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return SNECT_E_HIP;
+    }
     *out = c;
     return SNECT_OK;
 }
@@ -1308,6 +1334,22 @@ int snect_orthonormalize(snect_ctx* ctx, int32_t I1, int32_t I2, int32_t I3, int
     (void)hipFree(scratch);
     (void)hipFree(status);
     return rc;
+}
+
+int snect_orthonormalize_noalloc(snect_ctx* ctx, int32_t I1, int32_t I2, int32_t I3, int32_t J1, int32_t J2,
+                                 int32_t J3, snect_factors* f)
+{
+    if (!ctx) return SNECT_E_ARG;
+    ctx->err.clear();
+    int rc = check_qr_args(ctx, I1, I2, I3, J1, J2, J3, f);
+    if (rc) return rc;
+    if (qr_scratch_bytes() + 6 * sizeof(int) > qr_static_scratch_bytes())
+        return set_err(ctx, SNECT_E_UNSUPPORTED, "the fixed QR scratch is smaller than one mode needs");
+    if (!ctx->qr_static) return set_err(ctx, SNECT_E_HIP, "the fixed QR scratch has no device address");
+    HIP_TRY(hipSetDevice(ctx->device));
+    char* base = static_cast<char*>(ctx->qr_static);
+    int* status = reinterpret_cast<int*>(base + qr_scratch_bytes());
+    return run_qr(ctx, I1, I2, I3, J1, J2, J3, f, base, status);
 }
 
 int snect_exec_path(const snect_problem* pr)

@@ -16,6 +16,7 @@ struct snect_ctx {
     int num_cu = 0;
     int coop = 0;
     int live_problems = 0;  // problems and servers still referring to this context
+    void* qr_static = nullptr;  // this device's fixed QR scratch (device address)
 };
 
 namespace snect {
@@ -158,6 +159,11 @@ size_t qr_scratch_bytes();
 hipError_t launch_qr_mode(float* U, int I, int J, float* G, int J1, int J2, int J3, int mode, void* scratch,
                           int* status, hipStream_t st);
 hipError_t launch_qr_clear(int* status, int n, hipStream_t st);
+// The fixed per-device scratch of the allocation-free variant: its size
+// (one mode's scratch plus 256 bytes of status words) and its address on the
+// current device.
+size_t qr_static_scratch_bytes();
+hipError_t qr_static_scratch_address(void** ptr);
 // Largest number of co-resident workgroups of the persistent kernel.
 int persistent_capacity(int jp, int bf, int nw, size_t lds);
 // Largest number of co-resident workgroups of the batched sweep kernel.

@@ -235,4 +235,20 @@ hipError_t launch_qr_mode(float* U, int I, int J, float* G, int J1, int J2, int 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free orthonormalisation: one copy
+// per device, kept until the process ends.  Host code never passes the
+// symbol itself to a kernel; it takes the address hipGetSymbolAddress gives
+// for the current device.
+// ---------------------------------------------------------------------------
+constexpr size_t kQrStaticBytes = sizeof(double) * ((size_t)kQrParts * 32 * 32 + 4 * 32 * 32 + 32 * 32 * 32) + 256;
+static __device__ __align__(256) unsigned char scratch[kQrStaticBytes];
+
+size_t qr_static_scratch_bytes() { return kQrStaticBytes; }
+
+hipError_t qr_static_scratch_address(void** ptr)
+{
+    return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
+
 }  // namespace snect
