@@ -157,7 +157,8 @@ struct snect_problem {
     float *d_adj_w = nullptr, *d_deg = nullptr;
     float *d_Ap = nullptr, *d_Bp = nullptr, *d_Btmp = nullptr;
     float *d_Spart = nullptr, *d_Ssum = nullptr;
-    int32_t* d_scount = nullptr;
+    int32_t* d_blk_rec = nullptr;  // [P*P+1] first record of each block
+    float* d_ccst = nullptr;       // [P][kCstHead+I3] core-step constants per stratum
     int32_t* d_order = nullptr;  // [P]
     GridBar* d_bar = nullptr;
     double *d_sse = nullptr, *d_regp = nullptr, *d_net = nullptr, *d_lossout = nullptr;
@@ -208,8 +209,8 @@ struct snect_problem {
 // allows it for the chosen variant and counts the co-resident workgroups.
 static hipError_t configure_exec(snect_problem* pr, int nw, int rec_cap)
 {
-    const size_t slds = strata_lds_bytes(pr->jp, pr->rows1_max, pr->rows2_max, pr->I3, pr->J1, pr->J2, pr->J3,
-                                         rec_cap, pr->bf, nw);
+    const size_t slds = strata_lds_bytes(pr->jp, pr->P, pr->rows1_max, pr->rows2_max, pr->I3, pr->J1, pr->J2,
+                                         pr->J3, rec_cap, pr->bf, nw);
     if (slds > pr->ctx->max_lds) return hipErrorInvalidValue;
     const hipError_t e = prepare_strata(pr->jp, pr->bf, nw, slds);
     if (e != hipSuccess) return e;
@@ -352,9 +353,9 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
     // the largest record chunk that still fits in LDS
     int rec_cap = kMaxRecCap;
     while (rec_cap > kTileMax &&
-           strata_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf, 8) > ctx->max_lds)
+           strata_lds_bytes(jp, P, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf, 8) > ctx->max_lds)
         rec_cap /= 2;
-    const size_t slds = strata_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf, 8);
+    const size_t slds = strata_lds_bytes(jp, P, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf, 8);
     const size_t blds = slds;
     const size_t llds = loss_lds_bytes(jp, rows1_max, rows2_max, I3, J1, J2, J3);
     const size_t clds = core_lds_bytes(I3, J1, J2, J3, kCoreThreads);
@@ -488,6 +489,28 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
                 for (int64_t tl = blk_tile[blk]; tl < blk_tile[blk + 1]; ++tl)
                     scount[(size_t)s * I3 + tile_k[tl]] += tile_off[tl + 1] - tile_off[tl];
             }
+        // core-step constants of each stratum (see kCstHead), in the precision
+        // the step uses them
+        const int ncst = kCstHead + I3;
+        std::vector<float> ccst((size_t)P * ncst, 0.f);
+        const float lamf = (float)pa->lambda;
+        for (int s = 0; s < P; ++s) {
+            double m = 0.0;
+            for (int k = 0; k < I3; ++k) m += (double)scount[(size_t)s * I3 + k];
+            float* c = &ccst[(size_t)s * ncst];
+            if (m > 0.0) {
+                c[0] = 1.f;
+                c[1] = (float)(1.0 / m);
+                c[2] = lamf * (float)(m / (double)nnz);
+                for (int k = 0; k < I3; ++k) {
+                    const int32_t mk = scount[(size_t)s * I3 + k];
+                    c[kCstHead + k] = mk > 0 ? lamf * (float)((double)mk / (double)cnt3[k]) : 0.f;
+                }
+            }
+        }
+        // first record of each block
+        std::vector<int32_t> blk_rec((size_t)P * P + 1);
+        for (int64_t blk = 0; blk <= (int64_t)P * P; ++blk) blk_rec[blk] = tile_off[blk_tile[blk]];
         // ---------------- pack records with the tile's gene-slot order ----------------
         std::vector<uint2> nz(nnz);
         const int sh_f = bits_i + bits_j;
@@ -574,7 +597,8 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         pr->d_Btmp = pr->alloc<float>((size_t)I2 * J2, rc);
         pr->d_Spart = pr->alloc<float>((size_t)P * ni, rc);
         pr->d_Ssum = pr->alloc<float>(std::max(ni, ng), rc);
-        pr->d_scount = pr->alloc<int32_t>((size_t)P * I3, rc);
+        pr->d_blk_rec = pr->alloc<int32_t>((size_t)P * P + 1, rc);
+        pr->d_ccst = pr->alloc<float>((size_t)P * (kCstHead + I3), rc);
         pr->d_order = pr->alloc<int32_t>(P, rc);
         pr->d_bar = pr->alloc<GridBar>(1, rc);
         pr->d_sse = pr->alloc<double>((size_t)P * P, rc);
@@ -604,7 +628,8 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         he = he ? he : up(pr->d_tile_off, tile_off.data(), tile_off.size() * 4);
         he = he ? he : up(pr->d_tile_k, tile_k.data(), tile_k.size() * 4);
         he = he ? he : up(pr->d_blk_tile, blk_tile.data(), blk_tile.size() * 4);
-        he = he ? he : up(pr->d_scount, scount.data(), scount.size() * 4);
+        he = he ? he : up(pr->d_blk_rec, blk_rec.data(), blk_rec.size() * 4);
+        he = he ? he : up(pr->d_ccst, ccst.data(), ccst.size() * 4);
         he = he ? he : up(pr->d_perm1, pr->perm1.data(), (size_t)I1 * 4);
         he = he ? he : up(pr->d_perm2, pr->perm2.data(), (size_t)I2 * 4);
         he = he ? he : up(pr->d_start1, start1.data(), (size_t)(P + 1) * 4);
@@ -752,7 +777,7 @@ static StratArgs strat_args(const snect_problem* pr, const snect_factors* f)
     sa.start1 = pr->d_start1; sa.start2 = pr->d_start2;
     sa.reg1 = pr->d_reg1; sa.reg2 = pr->d_reg2; sa.cnt3 = pr->d_cnt3;
     sa.Ap = pr->d_Ap; sa.Bp = pr->d_Bp; sa.C = f->C; sa.G = f->G;
-    sa.Spart = pr->d_Spart; sa.scount = pr->d_scount; sa.Ssum = pr->d_Ssum;
+    sa.Spart = pr->d_Spart; sa.blk_rec = pr->d_blk_rec; sa.ccst = pr->d_ccst; sa.Ssum = pr->d_Ssum;
     sa.order = pr->d_order; sa.bar = pr->d_bar; sa.jp = pr->jp;
     sa.P = pr->P; sa.s = 0; sa.I3 = pr->I3; sa.J1 = pr->J1; sa.J2 = pr->J2; sa.J3 = pr->J3;
     sa.rows1_max = pr->rows1_max; sa.rows2_max = pr->rows2_max; sa.bits_i = pr->bits_i; sa.bits_j = pr->bits_j;
@@ -944,8 +969,8 @@ int snect_sweep_train(snect_ctx* ctx, int32_t n, snect_problem* const* probs, sn
     for (int i = 0; i < n; ++i) {
         const snect_problem* pr = probs[i];
         rcap[i] = pr->sweep_rec_cap ? pr->sweep_rec_cap : pr->rec_cap_max;
-        lds = std::max(lds, strata_lds_bytes(pr->jp, pr->rows1_max, pr->rows2_max, pr->I3, pr->J1, pr->J2, pr->J3,
-                                             rcap[i], bf, kDefaultWaves));
+        lds = std::max(lds, strata_lds_bytes(pr->jp, pr->P, pr->rows1_max, pr->rows2_max, pr->I3, pr->J1, pr->J2,
+                                             pr->J3, rcap[i], bf, kDefaultWaves));
     }
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(prepare_sweep(bf, lds));

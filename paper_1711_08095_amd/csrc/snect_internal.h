@@ -33,7 +33,6 @@ constexpr int kTileMax = 64;    // one tile = one wavefront
 constexpr int kTileCache = 256; // tile metadata entries cached in LDS
 constexpr int kMaxRecCap = 2048; // largest record chunk staged in LDS
 constexpr int kRedChunk = 16;   // blocks summed per chunk in the stratum reduce
-constexpr int kCoreChunk = 16;  // core entries summed per chunk in the C step
 
 // Core-size instantiations of the kernels: the smallest JP >= max(J1, J2).
 constexpr int kJpSet[] = {2, 4, 5, 8, 10, 12, 16, 20, 24, 32};
@@ -73,7 +72,8 @@ struct StratArgs {
     float* C;                  // [I3][J3]
     float* G;                  // [J1][J2][J3]
     float* Spart;              // [P][I3*J1*J2] per-block sums of e a (x) b
-    const int32_t* scount;     // [P][I3] nonzeros of stratum s on platform k (fixed by the plan)
+    const int32_t* blk_rec;    // [P*P+1] first record of each block (and nnz at the end)
+    const float* ccst;         // [P][I3+3] core-step constants of each stratum (fixed by the plan)
     float* Ssum;               // [I3*J1*J2] stratum sums (persistent kernel)
     const int32_t* order;      // [P] stratum order of this epoch
     GridBar* bar;
@@ -126,8 +126,13 @@ struct GraphArgs {
     float alpha;
 };
 
-size_t strata_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3, int rec_cap,
+size_t strata_lds_bytes(int jp, int P, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3, int rec_cap,
                         int bf, int nw);
+// Per-stratum constants of the core step, from the counts m_k of the
+// stratum's nonzeros on each platform k and m = sum_k m_k: [0] 1 if m > 0
+// else 0, [1] (float)(1 / m), [2] lambda (float)(m / nnz),
+// [3 + k] lambda (float)(m_k / n3[k]) (0 when m_k = 0).
+constexpr int kCstHead = 3;
 size_t loss_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3);
 size_t loss_cols_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3);
 size_t core_lds_bytes(int I3, int J1, int J2, int J3, int threads);

@@ -63,18 +63,17 @@ __device__ inline void lds_order_fence() { asm volatile("" ::: "memory"); }
 // LDS carve-up of the stratum kernels (in 4-byte words).
 // ---------------------------------------------------------------------------
 struct StratLds {
-    int a, b, ra, rb, c, g, h, ht, as, es, xtp, stg, sk, tco, tck, red, msum, cgt, flag, rec;
+    int a, b, ra, rb, c, g, h, ht, as, es, xtp, stg, sk, tco, tck, red, cst, cgt, flag, sch, rec;
     int hb, sw1, sw2, xts, esl, a16, e16;  // BF16 path only (zero-sized otherwise)
     int total;
 };
 
 __host__ __device__ inline int up4(int o) { return (o + 3) & ~3; }
 
-__host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2,
-                                                     int J3, int rec_cap, int bf, int nw)
+__host__ __device__ inline StratLds strat_lds_layout(int jp, int P, int rows1_max, int rows2_max, int I3, int J1,
+                                                     int J2, int J3, int rec_cap, int bf, int nw)
 {
     const int rs = strat_row_stride(jp, bf), mp = mfma_dim(jp), j12 = J1 * J2;
-    const int nch = (j12 + kCoreChunk - 1) / kCoreChunk;
     StratLds L;
     int o = 0;
     L.a = o;     o = up4(o + rows1_max * rs);
@@ -101,19 +100,20 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int rows1_max, int 
     L.sk = o;    o = up4(o + I3 * j12);
     L.tco = o;   o = up4(o + kTileCache + 1);
     L.tck = o;   o = up4(o + kTileCache);
-    L.red = o;   o = up4(o + (64 * nw > I3 * J3 * nch ? 64 * nw : I3 * J3 * nch));
-    L.msum = o;  o = up4(o + 2 * I3);          // doubles
+    L.red = o;   o = up4(o + 64 * nw);
+    L.cst = o;   o = up4(o + kCstHead + I3);        // core-step constants of the stratum
     L.cgt = o;   o = up4(o + I3 * J3 + j12 * J3);
     L.flag = o;  o = up4(o + 1);
+    L.sch = o;   o = up4(o + 7 * P);                // the epoch's schedule of this workgroup
     L.rec = o;   o = up4(o + 2 * rec_cap);
     L.total = o;
     return L;
 }
 
-size_t strata_lds_bytes(int jp, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3, int rec_cap, int bf,
-                        int nw)
+size_t strata_lds_bytes(int jp, int P, int rows1_max, int rows2_max, int I3, int J1, int J2, int J3, int rec_cap,
+                        int bf, int nw)
 {
-    return align16(4 * (size_t)strat_lds_layout(jp, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf, nw).total);
+    return align16(4 * (size_t)strat_lds_layout(jp, P, rows1_max, rows2_max, I3, J1, J2, J3, rec_cap, bf, nw).total);
 }
 
 int jp_for(int J1, int J2)
@@ -161,14 +161,31 @@ __device__ void build_hb(__bf16* Hb, const float* Hs, int I3, int J1, int J2, in
     }
 }
 
+// Device-coherent accesses, for data that other workgroups of the same
+// launch write or read: agent-scope relaxed atomics, which bypass the
+// non-coherent L2 of the accessing XCD (global_load / global_store with sc1).
+// With them the grid barrier needs no L2 writeback or invalidation.
+__device__ inline float ld_coh(const float* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline void st_coh(float* p, float v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// Waits until this wavefront's stores have been performed (s_waitcnt
+// vmcnt(0), the other counters left alone; gfx9 encoding); memory accesses
+// are not moved across it.
+__device__ inline void coh_stores_done()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Stratum sum of one item of S over the blocks: chunks of kRedChunk
 // consecutive blocks are summed in ascending order, then the chunk sums in
-// ascending order.
+// ascending order.  The partial sums are read device-coherently.
 __device__ inline float chunk_sum(const float* Spart, int ni, int item, int p0, int p1)
 {
     float v[kRedChunk];
 #pragma unroll
-    for (int u = 0; u < kRedChunk; ++u) v[u] = p0 + u < p1 ? Spart[(size_t)(p0 + u) * ni + item] : 0.f;
+    for (int u = 0; u < kRedChunk; ++u) v[u] = p0 + u < p1 ? ld_coh(Spart + (size_t)(p0 + u) * ni + item) : 0.f;
     float s = 0.f;
 #pragma unroll
     for (int u = 0; u < kRedChunk; ++u) s += v[u];
@@ -176,9 +193,10 @@ __device__ inline float chunk_sum(const float* Spart, int ni, int item, int p0, 
 }
 
 // Sums items [i0, i1) of the stratum into dst[item - i0] using the whole
-// workgroup (red: nthr floats of LDS).
-__device__ void reduce_items(const float* Spart, int P, int ni, int i0, int i1, float* dst, float* red, int tid,
-                             int nthr)
+// workgroup (red: nthr floats of LDS); dst_coh: dst is read by other
+// workgroups of the launch (device-coherent stores).
+__device__ void reduce_items(const float* Spart, int P, int ni, int i0, int i1, float* dst, bool dst_coh, float* red,
+                             int tid, int nthr)
 {
     const int nch = (P + kRedChunk - 1) / kRedChunk;
     const int per_pass = nthr / nch > 0 ? nthr / nch : 1;
@@ -194,59 +212,59 @@ __device__ void reduce_items(const float* Spart, int P, int ni, int i0, int i1, 
         if (tid < items) {
             float s = 0.f;
             for (int ch = 0; ch < nch; ++ch) s += red[tid * nch + ch];
-            dst[base + tid - i0] = s;
+            if (dst_coh)
+                st_coh(dst + base + tid - i0, s);
+            else
+                dst[base + tid - i0] = s;
         }
     }
     __syncthreads();
 }
 
-// Core / platform-factor step from the stratum sums S (I3 x J1J2) and the
-// counts m_k: one mean-gradient step of size etac,
+// Sum over the 16 lanes of each row, returned in every lane of the row.
+__device__ inline float row_sum16(float v);
+
+// Core / platform-factor step from the stratum sums S (I3 x J1J2) with the
+// stratum's constants cst (kCstHead + I3 values, see kCstHead): one
+// mean-gradient step of size etac,
 //   C[k][c] -= etac/m (-sum_ab G0[ab][c] S_k[ab] + lam m_k/n3[k] C0[k][c])
 //   G[ab][c] -= etac/m (-sum_k S_k[ab] C0[k][c] + lam m/nnz G0[ab][c]).
-// The C sums over ab run in chunks of kCoreChunk (red: I3*J3*nch floats),
-// then the chunks in ascending order.  New C goes to newC, new G to newG
-// (neither may alias C0 / G0); the caller synchronises afterwards.
-__device__ void core_update(const float* C0, const float* G0, const float* S, const double* mk,
-                            const int32_t* cnt3, int I3, int J12, int J3, float lam, float etac, double nnz,
-                            float* red, float* newC, float* newG, int tid, int nthr)
+// The C sum of item (k, c) runs on one 16-lane row of a wavefront: lane g
+// adds ab = g, g + 16, ... in ascending order, then the 16 lanes are added by
+// a fixed rotation tree.  The G sums run over ascending k.  New C goes to
+// newC, new G to newG (neither may alias C0 / G0); the caller synchronises
+// afterwards.  Every thread of the workgroup calls it (nthr a multiple of 64).
+__device__ void core_update(const float* C0, const float* G0, const float* S, const float* cst, int I3, int J12,
+                            int J3, float etac, float* newC, float* newG, int tid, int nthr)
 {
-    double m = 0.0;
-    for (int k = 0; k < I3; ++k) m += mk[k];
-    if (m <= 0.0) {
-        for (int idx = tid; idx < I3 * J3; idx += nthr) newC[idx] = C0[idx];
+    const int nc = I3 * J3;
+    if (cst[0] == 0.f) {  // no nonzero in this stratum
+        for (int idx = tid; idx < nc; idx += nthr) newC[idx] = C0[idx];
         for (int idx = tid; idx < J12 * J3; idx += nthr) newG[idx] = G0[idx];
         return;
     }
-    const float inv_m = (float)(1.0 / m);
-    const int nch = (J12 + kCoreChunk - 1) / kCoreChunk;
-    const int nc = I3 * J3;
-    // lanes take consecutive items of one chunk (neighbouring G columns and
-    // platforms: few LDS bank conflicts); every chunk is summed in ascending
-    // ab order whatever the lane
-    for (int u = tid; u < nc * nch; u += nthr) {
-        const int ch = u / nc, item = u - ch * nc;
-        const int k = item / J3, c = item - k * J3;
-        const int ab1 = (ch + 1) * kCoreChunk < J12 ? (ch + 1) * kCoreChunk : J12;
-        float g = 0.f;
-        for (int ab = ch * kCoreChunk; ab < ab1; ++ab) g = fmaf(-G0[ab * J3 + c], S[k * J12 + ab], g);
-        red[item * nch + ch] = g;
+    const float inv_m = cst[1], greg = cst[2];
+    const int g16 = tid & 15, rows = nthr >> 4;
+    for (int base = 0; base < nc; base += rows) {
+        const int item = base + (tid >> 4);
+        float v = 0.f;
+        if (item < nc) {
+            const int k = item / J3, c = item - k * J3;
+            for (int ab = g16; ab < J12; ab += 16) v = fmaf(-G0[ab * J3 + c], S[k * J12 + ab], v);
+        }
+        v = row_sum16(v);
+        if (item < nc && g16 == 0) {
+            const float cr = cst[kCstHead + item / J3];
+            const float g = cr != 0.f ? fmaf(cr, C0[item], v) : v;
+            newC[item] = fmaf(-etac, g * inv_m, C0[item]);
+        }
     }
-    const float greg = lam * (float)(m / nnz);
     for (int idx = tid; idx < J12 * J3; idx += nthr) {
         const int ab = idx / J3, c = idx - ab * J3;
         float g = 0.f;
         for (int k = 0; k < I3; ++k) g = fmaf(-S[k * J12 + ab], C0[k * J3 + c], g);
         g = fmaf(greg, G0[idx], g);
         newG[idx] = fmaf(-etac, g * inv_m, G0[idx]);
-    }
-    __syncthreads();
-    for (int item = tid; item < nc; item += nthr) {
-        const int k = item / J3;
-        float g = 0.f;
-        for (int ch = 0; ch < nch; ++ch) g += red[item * nch + ch];
-        if (mk[k] > 0.0) g = fmaf(lam * (float)(mk[k] / (double)cnt3[k]), C0[item], g);
-        newC[item] = fmaf(-etac, g * inv_m, C0[item]);
     }
 }
 
@@ -600,7 +618,7 @@ template <int JP, int NW> struct TileSplit {
     }
 };
 
-// The tiles of block (p, q), run by the whole workgroup (NW wavefronts).
+// The tiles [t0, t1) of one block, run by the whole workgroup (NW wavefronts).
 // L.Ab/L.Bb hold the block's rows; L.Sk (zeroed by the caller) receives
 // the block's per-platform sums through the staged partials of the four
 // matrix-core wavefronts.  Every sum is
@@ -623,7 +641,7 @@ template <int JP, int NW> struct TileSplit {
 // reads.  Products are not contracted into fused multiply-adds beyond the
 // explicit fmaf.
 template <int JP, int NW>
-__device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, int tid, int pre_cend)
+__device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L, int tid, int pre_cend)
 {
 #pragma clang fp contract(off)
     using SP = TileSplit<JP, NW>;
@@ -637,8 +655,6 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
     const int J1 = a.J1, J2 = a.J2, J12 = J1 * J2;
     const uint32_t mask_i = (1u << a.bits_i) - 1u, mask_j = (1u << a.bits_j) - 1u;
     const int sh_j = a.bits_i, sh_r = a.bits_i + a.bits_j;
-    const int blk = p * a.P + q;
-    const int t0 = a.blk_tile[blk], t1 = a.blk_tile[blk + 1];
     if (t0 >= t1) return;
 
     // operand columns beyond the factor columns stay zero
@@ -842,7 +858,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
     __syncthreads();
 }
 
-// The tiles of block (p, q) with BF16 matrix-core contractions (FP32
+// The tiles [t0, t1) of one block with BF16 matrix-core contractions (FP32
 // accumulation; factor rows, residuals and updates stay FP32).  Per tile:
 //   1. row block b = 0..3 (nonzeros 16b..16b+15) forms W1 = B_tile H_k^T
 //      and W2 = A_tile H_k on the matrix cores (BF16 operands, one K step
@@ -858,7 +874,7 @@ __device__ void block_tiles(const StratArgs& a, int p, int q, const TileLds& L, 
 //      (with eight wavefronts gene tasks on 0..3, patient tasks on 4..7);
 //   -- barrier --
 template <int JP, int NW>
-__device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& L, int tid, int pre_cend)
+__device__ void block_tiles_bf(const StratArgs& a, int t0, int t1, const TileLds& L, int tid, int pre_cend)
 {
 #pragma clang fp contract(off)
     constexpr int RS = strat_row_stride(JP, 1);
@@ -875,8 +891,6 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
     const int J1 = a.J1, J2 = a.J2, J12 = J1 * J2;
     const uint32_t mask_i = (1u << a.bits_i) - 1u, mask_j = (1u << a.bits_j) - 1u;
     const int sh_j = a.bits_i, sh_r = a.bits_i + a.bits_j;
-    const int blk = p * a.P + q;
-    const int t0 = a.blk_tile[blk], t1 = a.blk_tile[blk + 1];
     if (t0 >= t1) return;
     const bool hj = w < NJ, hi = w >= OI;
     const int rj = w, ri = w - OI;
@@ -1062,11 +1076,17 @@ __device__ void block_tiles_bf(const StratArgs& a, int p, int q, const TileLds& 
 // ---------------------------------------------------------------------------
 // Grid barrier for the persistent kernel: a monotone arrival counter (zeroed
 // before the launch).  Barrier number b of the launch is passed when the
-// counter reaches nblocks * b; arrivals do not wait for their atomic to
-// return, and nobody resets anything, so the last arrival releases the
-// others by itself.  Returns false (for every thread of the workgroup) if
-// the barrier gave up: another workgroup timed out, or this one waited far
-// longer than any stratum can take.
+// counter reaches nblocks * b; nobody resets anything, so the last arrival
+// releases the others by itself.  Everything workgroups exchange across it
+// (patient rows, block sums, stratum sums) is written and read with the
+// device-coherent accesses above, and every wavefront waits for its stores
+// (coh_stores_done) before the workgroup barrier that precedes the arrival;
+// so the arrival and the polls are relaxed atomics and no L2 writeback or
+// invalidation is needed (those cost about 4 us per barrier on this chip).
+// Global loads issued before the barrier stay in flight across it.  Returns
+// false (for every thread of the workgroup) if the barrier gave up: another
+// workgroup timed out, or this one waited far longer than any stratum can
+// take.
 // ---------------------------------------------------------------------------
 constexpr unsigned kSpinLimit = 1u << 25;
 
@@ -1076,16 +1096,11 @@ __device__ bool grid_sync(GridBar* bar, unsigned nblocks, unsigned& nbar, int* f
     if (threadIdx.x == 0) {
         int ok = 1;
         const unsigned target = nblocks * ++nbar;
-        // the release publishes every write the workgroup made before the
-        // barrier above
-        __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        // poll with relaxed loads (no cache invalidation per poll: a waiting
-        // workgroup must not keep invalidating the L2 that workgroups still
-        // running tiles share), then acquire once; one load per poll, the
-        // error flag (another workgroup gave up) every 128 polls
+        __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // one coherent load per poll; the error flag (another workgroup gave
+        // up) every 128 polls
         unsigned spins = 0;
         while (__hip_atomic_load(&bar->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
             if ((++spins & 127u) == 0u) {
                 if (spins > kSpinLimit) {
                     atomicOr(&bar->err, 1u);
@@ -1098,7 +1113,6 @@ __device__ bool grid_sync(GridBar* bar, unsigned nblocks, unsigned& nbar, int* f
                 }
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *flag = ok;
     }
     __syncthreads();
@@ -1143,11 +1157,61 @@ __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
     return L;
 }
 
+// Contiguous rows [row0, row0+nrows) of a position-ordered factor written
+// by other workgroups of this launch, into LDS rows of stride RS
+// (device-coherent loads, eight in flight per thread).
+__device__ inline void load_rows_coh(float* dst, const float* src, int row0, int nrows, int J, int RS, int tid,
+                                     int nthr)
+{
+    constexpr int U = 8;
+    const float* s = src + (size_t)row0 * J;
+    const int total = nrows * J;
+    for (int base = tid; base < total; base += U * nthr) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * nthr;
+            v[u] = idx < total ? ld_coh(s + idx) : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * nthr;
+            if (idx < total) {
+                const int l = idx / J, c = idx - l * J;
+                dst[l * RS + c] = v[u];
+            }
+        }
+    }
+}
+
+__device__ inline void store_rows_coh(float* dst, const float* src, int row0, int nrows, int J, int RS, int tid,
+                                      int nthr)
+{
+    float* d = dst + (size_t)row0 * J;
+    for (int idx = tid; idx < nrows * J; idx += nthr) {
+        const int l = idx / J, c = idx - l * J;
+        st_coh(d + idx, src[l * RS + c]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Persistent driver: every stratum of one epoch in one launch.
 // ---------------------------------------------------------------------------
 // Every stratum of one epoch of one problem, run by its workgroup q (gene
-// block q) of the problem's P co-resident workgroups.
+// block q) of the problem's P co-resident workgroups.  The epoch's schedule
+// (stratum order, and for each stratum the block's tile range, record range
+// and patient rows) is read into LDS once.  Per stratum:
+//   H_k from the current C, G; the block's tiles (its first record chunk and
+//   tile metadata already in LDS); its patient rows and sums of e a (x) b out
+//   (coherent stores); the next block's tile metadata and first record chunk
+//   requested (read-only data, in flight across the barrier);
+//   -- grid barrier --
+//   this workgroup's share of the stratum sums (coherent loads of the
+//   partials, fixed order) and the next block's patient rows in one round of
+//   loads; the prefetched chunk into LDS; the share out (coherent stores);
+//   -- grid barrier --
+//   the stratum sums in (coherent loads) and the same C/G step in every
+//   workgroup, on its LDS copy.
 template <int JP, bool BF, int NW>
 __device__ void strata_body(const StratArgs& a, int q, float* lds)
 {
@@ -1156,33 +1220,52 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
     const int tid = threadIdx.x;
     const int P = a.P, I3 = a.I3, J1 = a.J1, J2 = a.J2, J3 = a.J3, J12 = J1 * J2;
     const int ni = I3 * J12;
-    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3, a.rec_cap, BF ? 1 : 0, NW);
+    const StratLds S = strat_lds_layout(JP, P, a.rows1_max, a.rows2_max, I3, J1, J2, J3, a.rec_cap, BF ? 1 : 0, NW);
     const TileLds L = tile_lds<JP>(lds, S);
     float* Cs = lds + S.c;
     float* Gs = lds + S.g;
     float* Hs = lds + S.h;
     float* Sk = lds + S.sk;
     float* red = lds + S.red;
-    double* msum = reinterpret_cast<double*>(lds + S.msum);
+    float* cst = lds + S.cst;
     float* cgt = lds + S.cgt;
     float* Cn = cgt;            // C and G after the stratum's core step
     float* Gn = cgt + I3 * J3;
     int* flag = reinterpret_cast<int*>(lds + S.flag);
+    // schedule of stratum index si: [0] first tile, [1] tile end, [2] first
+    // record, [3] record end, [4] first patient row, [5] patient row end,
+    // [6] the stratum s (at sch[x * P + si])
+    int* sch = reinterpret_cast<int*>(lds + S.sch);
 
     for (int idx = tid; idx < a.rows1_max * RS; idx += NT) lds[S.a + idx] = 0.f;
     for (int idx = tid; idx < a.rows2_max * RS; idx += NT) lds[S.b + idx] = 0.f;
+    for (int si = tid; si < P; si += NT) {
+        const int s = a.order[si], p = (q - s + P) % P, b = p * P + q;
+        sch[si] = a.blk_tile[b];
+        sch[P + si] = a.blk_tile[b + 1];
+        sch[2 * P + si] = a.blk_rec[b];
+        sch[3 * P + si] = a.blk_rec[b + 1];
+        sch[4 * P + si] = a.start1[p];
+        sch[5 * P + si] = a.start1[p + 1];
+        sch[6 * P + si] = s;
+    }
     __syncthreads();
     const int s2 = a.start2[q], r2 = a.start2[q + 1] - s2;
     load_rows(L.Bb, a.Bp, s2, r2, J2, RS, tid, NT);
     for (int l = tid; l < r2; l += NT) lds[S.rb + l] = a.reg2[s2 + l];
     for (int idx = tid; idx < I3 * J3; idx += NT) Cs[idx] = a.C[idx];
     for (int idx = tid; idx < J12 * J3; idx += NT) Gs[idx] = a.G[idx];
+    {
+        const int s1 = sch[4 * P], r1 = sch[5 * P] - s1;
+        load_rows_coh(L.Ab, a.Ap, s1, r1, J1, RS, tid, NT);
+        for (int l = tid; l < r1; l += NT) lds[S.ra + l] = a.reg1[s1 + l];
+    }
     unsigned nbar = 0;  // grid barriers passed so far (thread 0)
     __syncthreads();
 
     // this workgroup's share of the stratum reduction: consecutive shares go
-    // to workgroups on the same XCD, so each XCD's L2 fetches its own
-    // contiguous slice of the per-block sums
+    // to workgroups on the same XCD, so each XCD fetches its own contiguous
+    // slice of the per-block sums
     const int r = xcd_slot(q, P);
     const int i0 = (int)(((long long)ni * r) / P), i1 = (int)(((long long)ni * (r + 1)) / P);
     const int nchr = (P + kRedChunk - 1) / kRedChunk;
@@ -1190,20 +1273,18 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
     // consecutive items of one chunk (coalesced loads)
     const int nitems = i1 - i0 > 0 ? i1 - i0 : 1;
     const int rch = tid / nitems, rit = tid - rch * nitems;
-    constexpr int kPreRec = (kMaxRecCap + NT - 65) / (NT - 64);  // records per thread of a prefetched chunk
-    // the next stratum's first chunk is prefetched across the second grid
-    // barrier except on the FP32 small-core path (no gain measured there)
-    constexpr bool kPrefetch = BF || JP > 12;
+    const bool one = (i1 - i0) * nchr <= NT;
+    // the next stratum's first chunk is requested by wavefronts 1.. (wavefront
+    // 0 arrives at the grid barrier and polls it)
+    constexpr int kPreRec = (kMaxRecCap + NT - 65) / (NT - 64);  // records per thread
+    constexpr int kPreTc = (kTileCache + NT - 64) / (NT - 64);    // tile entries per thread (of kTileCache + 1)
+    const int pt = tid - 64;
     int pre_cend = 0;  // tiles of this stratum's first chunk already in LDS
 
     for (int si = 0; si < P; ++si) {
-        const int s = a.order[si];
+        const int s = sch[6 * P + si];
         const int p = (q - s + P) % P;
-        const int s1 = a.start1[p], r1 = a.start1[p + 1] - s1;
-        if (si == 0) {  // later strata load their patient rows during the previous reduction
-            load_rows(L.Ab, a.Ap, s1, r1, J1, RS, tid, NT);
-            for (int l = tid; l < r1; l += NT) lds[S.ra + l] = a.reg1[s1 + l];
-        }
+        const int s1 = sch[4 * P + si], r1 = sch[5 * P + si] - s1;
         build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT, (!BF && JP > 12) ? lds + S.ht : nullptr);
         if constexpr (BF) {
             __syncthreads();
@@ -1212,61 +1293,66 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
         for (int idx = tid; idx < ni; idx += NT) Sk[idx] = 0.f;
         __syncthreads();
         if constexpr (BF)
-            block_tiles_bf<JP, NW>(a, p, q, L, tid, pre_cend);
+            block_tiles_bf<JP, NW>(a, sch[si], sch[P + si], L, tid, pre_cend);
         else
-            block_tiles<JP, NW>(a, p, q, L, tid, pre_cend);
+            block_tiles<JP, NW>(a, sch[si], sch[P + si], L, tid, pre_cend);
         pre_cend = 0;
-        store_rows(a.Ap, L.Ab, s1, r1, J1, RS, tid, NT);
-        __syncthreads();
+        store_rows_coh(a.Ap, L.Ab, s1, r1, J1, RS, tid, NT);
         float* Sp = a.Spart + (size_t)p * ni;
-        for (int idx = tid; idx < ni; idx += NT) Sp[idx] = Sk[idx];
+        for (int idx = tid; idx < ni; idx += NT) st_coh(Sp + idx, Sk[idx]);
+        coh_stores_done();
+        // the next stratum's tile metadata (as load_tile_cache lays it out) and
+        // first record chunk: read-only, requested now, used after the barrier
+        const bool more = si + 1 < P;
+        const int tn0 = more ? sch[si + 1] : 0, tn1 = more ? sch[P + si + 1] : 0;
+        const int zn0 = more ? sch[2 * P + si + 1] : 0, zn1 = more ? sch[3 * P + si + 1] : 0;
+        const int ntc = (tn1 - tn0) < kTileCache ? (tn1 - tn0) : kTileCache;
+        const int nrec = (zn1 - zn0) < a.rec_cap ? (zn1 - zn0) : a.rec_cap;
+        int tov[kPreTc], tkv[kPreTc];
+        uint2 rr[kPreRec];
+#pragma unroll
+        for (int h = 0; h < kPreTc; ++h) {
+            const int u = pt + h * (NT - 64);
+            tov[h] = pt >= 0 && u <= ntc ? a.tile_off[tn0 + u] : 0;
+            tkv[h] = pt >= 0 && u < ntc ? a.tile_k[tn0 + u] : 0;
+        }
+#pragma unroll
+        for (int h = 0; h < kPreRec; ++h) {
+            const int i = pt + h * (NT - 64);
+            rr[h] = pt >= 0 && i < nrec ? a.nz[zn0 + i] : make_uint2(0u, 0u);
+        }
         if (!grid_sync(a.bar, P, nbar, flag)) return;
 
         // every block of this stratum has stored its rows and sums: this
         // workgroup's share of the sums (one chunk of kRedChunk blocks per
-        // thread when the share allows), the stratum's counts and the next
-        // stratum's patient rows are read in one round of loads
-        const bool one = (i1 - i0) * nchr <= NT;
+        // thread when the share allows) and the next stratum's patient rows,
+        // in one round of loads
         float rv[kRedChunk];
         {
             const bool rt = one && tid < (i1 - i0) * nchr;
             const int p0 = rch * kRedChunk;
 #pragma unroll
             for (int u = 0; u < kRedChunk; ++u)
-                rv[u] = rt && p0 + u < P ? a.Spart[(size_t)(p0 + u) * ni + i0 + rit] : 0.f;
+                rv[u] = rt && p0 + u < P ? ld_coh(a.Spart + (size_t)(p0 + u) * ni + i0 + rit) : 0.f;
         }
-        const int cnt0 = tid < I3 ? a.scount[s * I3 + tid] : 0;
-        int tn0 = 0, tn1 = 0;  // tiles of the next stratum's block
-        if (si + 1 < P) {
-            const int pn = (q - a.order[si + 1] + P) % P;
-            if constexpr (kPrefetch) {
-                tn0 = a.blk_tile[pn * P + q];
-                tn1 = a.blk_tile[pn * P + q + 1];
-            }
-            // its tile metadata (as load_tile_cache lays it out), loaded
-            // together with its patient rows
-            constexpr int kTC = (kTileCache + NT) / NT;
-            int tov[kTC], tkv[kTC];
-#pragma unroll
-            for (int h = 0; h < kTC; ++h) {
-                const int u = tid + h * NT, t = tn0 + u;
-                tov[h] = tn0 < tn1 && u <= kTileCache && t <= tn1 ? a.tile_off[t] : 0;
-                tkv[h] = tn0 < tn1 && u < kTileCache && t < tn1 ? a.tile_k[t] : 0;
-            }
-            const int s1n = a.start1[pn], r1n = a.start1[pn + 1] - s1n;
-            load_rows(L.Ab, a.Ap, s1n, r1n, J1, RS, tid, NT);
+        if (more) {
+            const int s1n = sch[4 * P + si + 1], r1n = sch[5 * P + si + 1] - s1n;
+            load_rows_coh(L.Ab, a.Ap, s1n, r1n, J1, RS, tid, NT);
             for (int l = tid; l < r1n; l += NT) lds[S.ra + l] = a.reg1[s1n + l];
-            if (tn0 < tn1) {
+        }
+        if (pt >= 0) {
 #pragma unroll
-                for (int h = 0; h < kTC; ++h) {
-                    const int u = tid + h * NT;
-                    if (u <= kTileCache) L.tco[u] = tov[h];
-                    if (u < kTileCache) L.tck[u] = tkv[h];
-                }
+            for (int h = 0; h < kPreTc; ++h) {
+                const int u = pt + h * (NT - 64);
+                if (u <= kTileCache) L.tco[u] = tov[h];
+                if (u < kTileCache) L.tck[u] = tkv[h];
+            }
+#pragma unroll
+            for (int h = 0; h < kPreRec; ++h) {
+                const int i = pt + h * (NT - 64);
+                if (i < nrec) L.rec[i] = rr[h];
             }
         }
-        if (tid < I3) msum[tid] = (double)cnt0;
-        for (int k = tid + NT; k < I3; k += NT) msum[k] = (double)a.scount[s * I3 + k];
         if (one) {
             // the order of reduce_items: each chunk's blocks ascending, then
             // the chunks ascending
@@ -1280,40 +1366,20 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
             if (tid < i1 - i0) {
                 float t = 0.f;
                 for (int ch = 0; ch < nchr; ++ch) t += red[tid * nchr + ch];
-                a.Ssum[i0 + tid] = t;
+                st_coh(a.Ssum + i0 + tid, t);
             }
         } else {
-            reduce_items(a.Spart, P, ni, i0, i1, a.Ssum + i0, red, tid, NT);
+            reduce_items(a.Spart, P, ni, i0, i1, a.Ssum + i0, true, red, tid, NT);
         }
-        // the next stratum's first chunk: its tile count now (the metadata
-        // arrived with the loads above), its records in flight across the
-        // second barrier, into LDS after it.  Wavefront 0 takes no part: its
-        // barrier arrival waits for all of its outstanding memory operations.
-        const int pt = tid - 64;
-        uint2 rr[kPreRec];
-        if (tn0 < tn1) {
-            const int ntc = (tn1 - tn0) < kTileCache ? (tn1 - tn0) : kTileCache;
-            pre_cend = __syncthreads_count(tid < ntc && L.tco[tid + 1] - L.tco[0] <= a.rec_cap);
-            const int z0 = L.tco[0], nrec = L.tco[pre_cend] - z0;
-#pragma unroll
-            for (int u = 0; u < kPreRec; ++u) {
-                const int i = pt + u * (NT - 64);
-                rr[u] = pt >= 0 && i < nrec ? a.nz[z0 + i] : make_uint2(0u, 0u);
-            }
-        }
+        // the tiles of the prefetched chunk whose records fit in it
+        pre_cend = __syncthreads_count(tid < ntc && L.tco[tid + 1] - L.tco[0] <= a.rec_cap);
+        coh_stores_done();
         if (!grid_sync(a.bar, P, nbar, flag)) return;
-        if (pre_cend > 0) {
-            const int nrec = L.tco[pre_cend] - L.tco[0];
-#pragma unroll
-            for (int u = 0; u < kPreRec; ++u) {
-                const int i = pt + u * (NT - 64);
-                if (pt >= 0 && i < nrec) L.rec[i] = rr[u];
-            }
-        }
 
-        for (int idx = tid; idx < ni; idx += NT) Sk[idx] = a.Ssum[idx];
+        for (int idx = tid; idx < ni; idx += NT) Sk[idx] = ld_coh(a.Ssum + idx);
+        for (int idx = tid; idx < kCstHead + I3; idx += NT) cst[idx] = a.ccst[(size_t)s * (kCstHead + I3) + idx];
         __syncthreads();
-        core_update(Cs, Gs, Sk, msum, a.cnt3, I3, J12, J3, a.lam, a.etac, a.nnz, red, Cn, Gn, tid, NT);
+        core_update(Cs, Gs, Sk, cst, I3, J12, J3, a.etac, Cn, Gn, tid, NT);
         __syncthreads();
         // the new C and G become current; the old buffers take the next step
         float* t = Cs;
@@ -1380,7 +1446,7 @@ __global__ __launch_bounds__(64 * NW) void block_step(StratArgs a)
     const int p = blockIdx.x, P = a.P;
     const int q = (p + a.s) % P;
     const int I3 = a.I3, J1 = a.J1, J2 = a.J2, J3 = a.J3, J12 = J1 * J2, ni = I3 * J12;
-    const StratLds S = strat_lds_layout(JP, a.rows1_max, a.rows2_max, I3, J1, J2, J3, a.rec_cap, BF ? 1 : 0, NW);
+    const StratLds S = strat_lds_layout(JP, P, a.rows1_max, a.rows2_max, I3, J1, J2, J3, a.rec_cap, BF ? 1 : 0, NW);
     const TileLds L = tile_lds<JP>(lds, S);
     float* Cs = lds + S.c;
     float* Gs = lds + S.g;
@@ -1405,10 +1471,11 @@ __global__ __launch_bounds__(64 * NW) void block_step(StratArgs a)
         build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Hs, I3, J1, J2, tid, NT);
     }
     __syncthreads();
+    const int t0 = a.blk_tile[p * P + q], t1 = a.blk_tile[p * P + q + 1];
     if constexpr (BF)
-        block_tiles_bf<JP, NW>(a, p, q, L, tid, 0);
+        block_tiles_bf<JP, NW>(a, t0, t1, L, tid, 0);
     else
-        block_tiles<JP, NW>(a, p, q, L, tid, 0);
+        block_tiles<JP, NW>(a, t0, t1, L, tid, 0);
     store_rows(a.Ap, L.Ab, s1, r1, J1, RS, tid, NT);
     store_rows(a.Bp, L.Bb, s2, r2, J2, RS, tid, NT);
     __syncthreads();
@@ -1417,19 +1484,18 @@ __global__ __launch_bounds__(64 * NW) void block_step(StratArgs a)
 }
 
 struct CoreLds {
-    int s, c, cgt, red, msum, total;
+    int s, c, cgt, red, cst, total;
 };
 
 __host__ __device__ inline CoreLds core_lds_layout(int I3, int J1, int J2, int J3, int threads)
 {
-    const int nch = (J1 * J2 + kCoreChunk - 1) / kCoreChunk;
     CoreLds L;
     int o = 0;
     L.s = o;    o = up4(o + I3 * J1 * J2);
     L.c = o;    o = up4(o + I3 * J3);
     L.cgt = o;  o = up4(o + I3 * J3);
-    L.red = o;  o = up4(o + (threads > I3 * J3 * nch ? threads : I3 * J3 * nch));
-    L.msum = o; o = up4(o + 2 * I3);
+    L.red = o;  o = up4(o + threads);
+    L.cst = o;  o = up4(o + kCstHead + I3);
     L.total = o;
     return L;
 }
@@ -1452,11 +1518,11 @@ __global__ __launch_bounds__(kCoreThreads) void core_step(StratArgs a, float* Gt
     float* C0 = lds + L.c;
     float* cgt = lds + L.cgt;
     float* red = lds + L.red;
-    double* msum = reinterpret_cast<double*>(lds + L.msum);
-    for (int k = tid; k < I3; k += NT) msum[k] = (double)a.scount[a.s * I3 + k];
+    float* cst = lds + L.cst;
+    for (int idx = tid; idx < kCstHead + I3; idx += NT) cst[idx] = a.ccst[(size_t)a.s * (kCstHead + I3) + idx];
     for (int idx = tid; idx < I3 * J3; idx += NT) C0[idx] = a.C[idx];
-    reduce_items(a.Spart, P, ni, 0, ni, S, red, tid, NT);
-    core_update(C0, a.G, S, msum, a.cnt3, I3, J12, J3, a.lam, a.etac, a.nnz, red, cgt, Gtmp, tid, NT);
+    reduce_items(a.Spart, P, ni, 0, ni, S, false, red, tid, NT);
+    core_update(C0, a.G, S, cst, I3, J12, J3, a.etac, cgt, Gtmp, tid, NT);
     __syncthreads();
     for (int idx = tid; idx < I3 * J3; idx += NT) a.C[idx] = cgt[idx];
     for (int idx = tid; idx < J12 * J3; idx += NT) a.G[idx] = Gtmp[idx];
