@@ -248,9 +248,8 @@ int snect_last_timing(const snect_problem *prob, double *ms5);
 #define SNECT_PATH_MULTI 2      /* one launch per stratum + a core-step launch */
 
 /* Execution choices; they never change results: every sum of the stratum
- * kernels is taken in an order fixed by the problem alone, so both drivers,
- * both wavefront counts and every record-chunk size give bit-identical
- * factors and losses.  per_launch_timing records a pair of HIP events around
+ * kernels is taken in an order fixed by the problem alone, so both drivers
+ * and every record-chunk size give bit-identical factors and losses.  per_launch_timing records a pair of HIP events around
  * every stratum-kernel launch (no extra host synchronisation); path selects
  * the stratum driver; waves and rec_cap shape the stratum workgroups.
  * SNECT_PATH_PERSISTENT fails with E_UNSUPPORTED at snect_train if the P
@@ -258,7 +257,7 @@ int snect_last_timing(const snect_problem *prob, double *ms5);
 typedef struct {
     int32_t per_launch_timing;
     int32_t path;
-    int32_t waves;   /* wavefronts per stratum workgroup: 0 (default, 8), 4 or 8 */
+    int32_t waves;   /* wavefronts per stratum workgroup: 0 or 8 (the only size) */
     int32_t rec_cap; /* nonzero records staged in LDS per chunk: 0 (the largest
                         that fits) or a power of two from 64 up to that */
 } snect_exec;
@@ -289,7 +288,7 @@ int snect_sweep_train(snect_ctx *ctx, int32_t n, snect_problem *const *probs, sn
 
 /* Execution autotuner.  Times `trials` epochs (the best one counts) of
  * every execution choice -- both stratum drivers (the persistent one where
- * its workgroups can be resident), 8 or 4 wavefronts, record chunks from
+ * its workgroups can be resident), record chunks from
  * the largest that fits down to 256 in powers of two -- on scratch copies
  * of the factors f (device; f itself is not changed), keeps the fastest on
  * the problem (as snect_set_exec would) and reports it in *best (may be

@@ -1085,7 +1085,7 @@ int snect_autotune(snect_problem* pr, const snect_factors* f, int32_t trials, sn
     snect_exec b{0, keep_path, keep_nw, keep_rc};
     double bt = -1.0;
     for (int path : {SNECT_PATH_PERSISTENT, SNECT_PATH_MULTI})
-        for (int nw : {8, 4})
+        for (int nw : {kDefaultWaves})
             for (int rcap = pr->rec_cap_max; rcap >= std::min(256, pr->rec_cap_max); rcap /= 2) {
                 if (configure_exec(pr, nw, rcap) != hipSuccess) continue;
                 pr->path = path;
@@ -1292,7 +1292,7 @@ int snect_set_exec(snect_problem* pr, const snect_exec* ex)
     if (ex->path < SNECT_PATH_AUTO || ex->path > SNECT_PATH_MULTI)
         return set_err(pr->ctx, SNECT_E_ARG, "unknown path");
     const int nw = ex->waves == 0 ? kDefaultWaves : ex->waves;
-    if (nw != 4 && nw != 8) return set_err(pr->ctx, SNECT_E_ARG, "waves must be 0, 4 or 8");
+    if (nw != kDefaultWaves) return set_err(pr->ctx, SNECT_E_ARG, "waves must be 0 or 8");
     const int rc = ex->rec_cap == 0 ? pr->rec_cap_max : ex->rec_cap;
     if (rc < kTileMax || rc > pr->rec_cap_max || (rc & (rc - 1)) != 0)
         return set_err(pr->ctx, SNECT_E_ARG,

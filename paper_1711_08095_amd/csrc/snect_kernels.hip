@@ -3,8 +3,8 @@
 // Eq. 3).
 //
 // Factor rows are kept in plan (position) order, so the rows of a block are
-// one contiguous range.  A block (p, q) is processed by one workgroup of NW
-// wavefronts (8 by default, 4 as an execution choice): its patient rows and
+// one contiguous range.  A block (p, q) is processed by one workgroup of NW = 8
+// wavefronts (two per SIMD): its patient rows and
 // gene rows sit in LDS, H_k = G x3 c_k for every platform k is built in LDS
 // from the stratum's frozen C and G, and each tile (<= 64 nonzeros of one
 // platform) is one step in which lane t of every wavefront stands for
@@ -12,9 +12,10 @@
 // update of column c of a_i) and a gene task (w2_c = (H_k^T a_i)_c and the
 // update of column c of b_j), spread over the wavefronts:
 //   1. patient tasks read the tile's b rows, gene tasks its a rows, as they
-//      were before the tile; patient tasks stage a_c w1_c per column;
-//   2. after a barrier every lane sums x~ = a_i . w1 over ascending columns
-//      and forms e = x - x~; a segmented wavefront scan then sums the terms
+//      were before the tile; each patient-task wavefront stages its share of
+//      x~ = a_i . w1 (its columns, ascending);
+//   2. after a barrier every lane adds the shares in wavefront order and
+//      forms e = x - x~; a segmented wavefront scan then sums the terms
 //      of every patient run (contiguous: tiles are sorted by i) and every
 //      gene run (contiguous in the tile's gene-sorted slot order) in a fixed
 //      tree order, and the last lane of a run writes the row's column;
@@ -22,8 +23,8 @@
 //      of e a (x) b, which four wavefronts accumulate at the start of the
 //      next tile, each over a fixed quarter of the nonzeros;
 //   3. a barrier ends the tile.
-// Every sum runs in an order fixed by the problem alone, so NW and the other
-// execution choices never change a bit of the result.  Staging arrays are
+// Every sum runs in an order fixed by the problem alone (and the core size),
+// so the execution choices never change a bit of the result.  Staging arrays are
 // column-major with a pitch of 66 words, which keeps the column writes and
 // the matrix-core operand reads free of bank conflicts; factor rows use an
 // odd stride so that the rows gathered by one tile spread over the banks.
@@ -88,7 +89,7 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int P, int rows1_ma
     L.ht = o;    o = up4(o + tr * I3 * jp * jp);         // H_k^T (FP32 path, JP > 12)
     L.as = o;    o = up4(o + f32 * mp * kTS);
     L.es = o;    o = up4(o + f32 * mp * kTS);
-    L.xtp = o;   o = up4(o + f32 * jp * kTileMax);          // a_c w1_c per column
+    L.xtp = o;   o = up4(o + f32 * nw * kTileMax);          // each patient-task wavefront's share of x~
     L.hb = o;    o = up4(o + bf * I3 * mp * kKB);        // 2 x I3 x mp x 32 bf16
     L.sw1 = o;   o = up4(o + bf * mp * kTW);
     L.sw2 = o;   o = up4(o + bf * mp * kTW);
@@ -499,9 +500,11 @@ __device__ inline float seg_scan(float v, int lane, int head)
     if (r >= 4 && lane - 4 >= head) v += t;
     t = dpp_move<kDppRowShr + 8, 0xf>(v);
     if (r >= 8 && lane - 8 >= head) v += t;
-    t = dpp_move<kDppRowBcast15, 0xa>(v);
+    // the row broadcasts write every row (lanes without a source read 0); the
+    // conditions keep the add to rows 1 and 3, and to rows 2 and 3
+    t = dpp_move<kDppRowBcast15, 0xf>(v);
     if ((row & 1) && head <= 16 * row - 1) v += t;
-    t = dpp_move<kDppRowBcast31, 0xc>(v);
+    t = dpp_move<kDppRowBcast31, 0xf>(v);
     if (row >= 2 && head <= 31) v += t;
     return v;
 }
@@ -621,16 +624,15 @@ template <int JP, int NW> struct TileSplit {
 // The tiles [t0, t1) of one block, run by the whole workgroup (NW wavefronts).
 // L.Ab/L.Bb hold the block's rows; L.Sk (zeroed by the caller) receives
 // the block's per-platform sums through the staged partials of the four
-// matrix-core wavefronts.  Every sum is
-// taken in an order that does not depend on NW (x~ over ascending columns,
-// S over four fixed nonzero ranges), so NW is an execution choice only.
+// matrix-core wavefronts.  Every sum is taken in a fixed order (x~ over the
+// patient-task wavefronts' shares, S over four fixed nonzero ranges).
 //
 // Two workgroup barriers per tile:
-//   1. patient tasks read the tile's b rows and form w1_c, a_c w1_c going
-//      to LDS; gene tasks read the a rows and form w2_c (all values from
-//      before the tile);
+//   1. patient tasks read the tile's b rows and form w1_c and their share of
+//      x~ (to LDS); gene tasks read the a rows and form w2_c (all values
+//      from before the tile);
 //   -- barrier --
-//   2. every wavefront sums x~ over ascending columns and forms e; patient
+//   2. every wavefront adds the shares of x~ and forms e; patient
 //      tasks stage the S operands and sum their runs of e w1_c in
 //      registers; gene tasks push e w2_c to slot order within the
 //      wavefront (ds_permute) and sum their runs there; the last lane of a
@@ -713,7 +715,10 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
         const bool act = lane < n;
         const uint32_t wd = wv.x;
         const float x = __uint_as_float(wv.y);
+        // lanes past the tile's end: patient -1 for the run logic, row 0 for
+        // reads (their values are never used: e = 0 there)
         const int il = act ? (int)(wd & mask_i) : -1;
+        const int ilc = act ? (int)(wd & mask_i) : 0;
         const int jl = act ? (int)((wd >> sh_j) & mask_j) : 0;
         const int jrank = (int)(wd >> sh_r);
 
@@ -722,9 +727,10 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
         const float* H = L.Hs + k * JP * JP;
         float w1q[QI], aq[QI], bq[QI], w2q[QJ];
         if (hi) {
+            float xp = 0.f;  // this wavefront's share of x~: its columns, ascending
             float bv[JP];
 #pragma unroll
-            for (int c = 0; c < JP; ++c) bv[c] = act ? L.Bb[jl * RS + c] : 0.f;
+            for (int c = 0; c < JP; ++c) bv[c] = L.Bb[jl * RS + c];
 #pragma unroll
             for (int qq = 0; qq < QI; ++qq) {
                 const int c = ri + NI * qq;
@@ -743,15 +749,16 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
                             for (int r = 0; r < 4; ++r) t = fmaf(h4[r], bv[4 * y4 + r], t);
                         }
                     }
-                    ac = act ? L.Ab[il * RS + c] : 0.f;
-                    bc = act ? L.Bb[jl * RS + c] : 0.f;
-                    L.xtp[c * kTileMax + lane] = ac * t;
+                    ac = act ? L.Ab[ilc * RS + c] : 0.f;
+                    bc = act ? bv[c] : 0.f;
+                    xp = qq == 0 ? ac * t : fmaf(ac, t, xp);
                 }
                 w1q[qq] = t;
                 aq[qq] = ac;
                 bq[qq] = bc;
                 if constexpr (JP > 16) lds_order_fence();
             }
+            L.xtp[ri * kTileMax + lane] = xp;
         }
         // gene runs, in the tile's gene-sorted slot order: slot s learns its
         // gene row from the lane that holds it (inactive lanes push to their
@@ -778,7 +785,7 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
         if (hj) {
             float av[JP];
 #pragma unroll
-            for (int c = 0; c < JP; ++c) av[c] = act ? L.Ab[il * RS + c] : 0.f;
+            for (int c = 0; c < JP; ++c) av[c] = L.Ab[ilc * RS + c];
 #pragma unroll
             for (int qq = 0; qq < QJ; ++qq) {
                 const int c = rj + NJ * qq;
@@ -802,12 +809,17 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
             }
         }
         // patient runs (the tile is sorted by patient): heads and the
-        // regularisation weight of each run
-        const int il_up = dpp_move_i<kDppWaveShr1>(il), il_dn = dpp_move_i<kDppWaveShl1>(il);
-        const bool ifirst = act && (lane == 0 || il_up != il);
-        const bool ilast = act && (lane == 63 || il_dn != il);
-        const int ihead = run_head(__ballot(ifirst), lane);
-        const float icr = (act && hi) ? (float)(lane - ihead + 1) * L.rA[il] : 0.f;
+        // regularisation weight of each run (patient tasks only)
+        bool ilast = false;
+        int ihead = 0;
+        float icr = 0.f;
+        if (hi) {
+            const int il_up = dpp_move_i<kDppWaveShr1>(il), il_dn = dpp_move_i<kDppWaveShl1>(il);
+            const bool ifirst = act && (lane == 0 || il_up != il);
+            ilast = act && (lane == 63 || il_dn != il);
+            ihead = run_head(__ballot(ifirst), lane);
+            icr = act ? (float)(lane - ihead + 1) * L.rA[ilc] : 0.f;
+        }
         __syncthreads();
         if (pend >= 0) {
             stage_sum<false, MP>(L.St, L.Sk + pend * J12, J1, J2, tid, NT);
@@ -818,10 +830,11 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
             wv_next = lane < n2 ? L.rec[o2 - z0 + lane] : make_uint2(0u, 0u);
         }
 
-        // 2. residual (x~ summed over ascending columns); the tasks' run sums
+        // 2. residual (x~: the patient-task wavefronts' shares in wavefront
+        // order); the tasks' run sums
         float xt = L.xtp[lane];
 #pragma unroll
-        for (int c = 1; c < JP; ++c) xt += L.xtp[c * kTileMax + lane];
+        for (int ww = 1; ww < NI; ++ww) xt += L.xtp[ww * kTileMax + lane];
         const float e = act ? x - xt : 0.f;
         if (hi) {
 #pragma unroll
@@ -1956,9 +1969,7 @@ __global__ __launch_bounds__(256) void permute_rows(const float* src, float* dst
     }
 
 // Instantiation of a (JP, BF16?, wavefronts) variant of a stratum-kernel helper.
-#define SNECT_VARIANT(F, J, ...)                                                              \
-    (bf ? (nw == 4 ? F<J, true, 4>(__VA_ARGS__) : F<J, true, 8>(__VA_ARGS__))                 \
-        : (nw == 4 ? F<J, false, 4>(__VA_ARGS__) : F<J, false, 8>(__VA_ARGS__)))
+#define SNECT_VARIANT(F, J, ...) (bf ? F<J, true, kDefaultWaves>(__VA_ARGS__) : F<J, false, kDefaultWaves>(__VA_ARGS__))
 
 template <int JP, bool BF, int NW>
 static hipError_t launch_persistent_t(const StratArgs& a, size_t lds, hipStream_t st)

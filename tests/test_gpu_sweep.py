@@ -1,4 +1,4 @@
-"""Execution choices (wavefronts, record chunk, driver), the autotuners and
+"""Execution choices (record chunk, driver), the autotuners and
 the batched sweep: every one of them must leave the results bit-identical
 to a plain snect_train of the same problem."""
 import numpy as np
@@ -35,8 +35,8 @@ def test_execution_choices_are_bit_identical(ctx, precision, ranks, P, T):
     print(f"exec choices ranks={ranks} P={P} T={T} precision={precision}", flush=True)
     prob = gpu_problem(ctx, case, precision=precision)
     ref = run_gpu(ctx, case, 2, prob=prob)
-    for path, waves, rec_cap in [(sn.PATH_PERSISTENT, 4, 0), (sn.PATH_MULTI, 8, 64), (sn.PATH_PERSISTENT, 8, 128),
-                                 (sn.PATH_MULTI, 4, 256)]:
+    for path, waves, rec_cap in [(sn.PATH_PERSISTENT, 8, 0), (sn.PATH_MULTI, 8, 64), (sn.PATH_PERSISTENT, 0, 128),
+                                 (sn.PATH_MULTI, 0, 256)]:
         prob.set_exec(path=path, waves=waves, rec_cap=rec_cap)
         _same(ref, run_gpu(ctx, case, 2, prob=prob))
 
@@ -45,7 +45,7 @@ def test_exec_validation(ctx):
     import paper_1711_08095_amd as sn
     case = planted_case(seed=32, dims=(40, 60, 3), ranks=(4, 4, 2), nnz=1500, edges=50, P=4, T=16)
     prob = gpu_problem(ctx, case)
-    for kw in (dict(waves=6), dict(rec_cap=100), dict(rec_cap=32), dict(rec_cap=1 << 20)):
+    for kw in (dict(waves=6), dict(waves=4), dict(rec_cap=100), dict(rec_cap=32), dict(rec_cap=1 << 20)):
         print("set_exec", kw, flush=True)
         with pytest.raises(sn.SnectError) as e:
             prob.set_exec(**kw)
@@ -60,7 +60,7 @@ def test_autotune_keeps_results_and_factors(ctx):
     before = [t.clone() for t in f]
     choice, ms = prob.autotune(*f, trials=1)
     print("autotune choice", choice, f"{ms:.3f} ms", flush=True)
-    assert choice["waves"] in (4, 8) and choice["rec_cap"] >= 64 and ms > 0
+    assert choice["waves"] == 8 and choice["rec_cap"] >= 64 and ms > 0
     for a, b in zip(f, before):
         assert bool((a == b).all())
     _same(ref, run_gpu(ctx, case, 2, prob=prob))
