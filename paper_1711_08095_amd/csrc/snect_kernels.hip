@@ -509,10 +509,14 @@ __device__ inline float seg_scan(float v, int lane, int head)
     return v;
 }
 
-// Position of the highest set bit of `heads` at or below `lane`.
-__device__ inline int run_head(unsigned long long heads, int lane)
+// Lanes 0..lane as a bit mask (computed once per thread).
+__device__ inline unsigned long long lanes_upto(int lane) { return lane == 63 ? ~0ull : (2ull << lane) - 1ull; }
+
+// Position of the highest set bit of `heads` among the bits of `upto`
+// (lanes_upto of the calling lane).
+__device__ inline int run_head(unsigned long long heads, unsigned long long upto)
 {
-    const unsigned long long m = lane == 63 ? heads : (heads & ((2ull << lane) - 1ull));
+    const unsigned long long m = heads & upto;
     return m ? 63 - __clzll(m) : 0;
 }
 
@@ -652,6 +656,7 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
     constexpr int MP = mfma_dim(JP);
     constexpr int NT = 64 * NW;
     const int lane = tid & 63, w = tid >> 6;
+    const unsigned long long upto = lanes_upto(lane);
     const bool hj = w < NJ, hi = w >= OI;  // has gene tasks / patient tasks
     const int rj = w, ri = w - OI;         // columns rj + NJ q, ri + NI q
     const int J1 = a.J1, J2 = a.J2, J12 = J1 * J2;
@@ -750,7 +755,7 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
                         }
                     }
                     ac = act ? L.Ab[ilc * RS + c] : 0.f;
-                    bc = act ? bv[c] : 0.f;
+                    bc = act ? L.Bb[jl * RS + c] : 0.f;
                     xp = qq == 0 ? ac * t : fmaf(ac, t, xp);
                 }
                 w1q[qq] = t;
@@ -774,7 +779,7 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
             const int sj_up = dpp_move_i<kDppWaveShr1>(sj), sj_dn = dpp_move_i<kDppWaveShl1>(sj);
             const bool jfirst = sact && (lane == 0 || sj_up != sj);
             jlast = sact && (lane == 63 || sj_dn != sj);
-            jhead = run_head(__ballot(jfirst), lane);
+            jhead = run_head(__ballot(jfirst), upto);
             jcr = sact ? (float)(lane - jhead + 1) * L.rB[sj] : 0.f;
 #pragma unroll
             for (int qq = 0; qq < QJ; ++qq) {
@@ -817,7 +822,7 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
             const int il_up = dpp_move_i<kDppWaveShr1>(il), il_dn = dpp_move_i<kDppWaveShl1>(il);
             const bool ifirst = act && (lane == 0 || il_up != il);
             ilast = act && (lane == 63 || il_dn != il);
-            ihead = run_head(__ballot(ifirst), lane);
+            ihead = run_head(__ballot(ifirst), upto);
             icr = act ? (float)(lane - ihead + 1) * L.rA[ilc] : 0.f;
         }
         __syncthreads();
@@ -901,6 +906,7 @@ __device__ void block_tiles_bf(const StratArgs& a, int t0, int t1, const TileLds
     constexpr int NJ = kTwo ? NW / 2 : NW, OI = kTwo ? NW / 2 : 0, NI = NW - OI;
     constexpr int QI = (JP + NI - 1) / NI, QJ = (JP + NJ - 1) / NJ;
     const int lane = tid & 63, w = tid >> 6, g = lane >> 4, m = lane & 15;
+    const unsigned long long upto = lanes_upto(lane);
     const int J1 = a.J1, J2 = a.J2, J12 = J1 * J2;
     const uint32_t mask_i = (1u << a.bits_i) - 1u, mask_j = (1u << a.bits_j) - 1u;
     const int sh_j = a.bits_i, sh_r = a.bits_i + a.bits_j;
@@ -1020,7 +1026,7 @@ __device__ void block_tiles_bf(const StratArgs& a, int t0, int t1, const TileLds
         const int il_up = dpp_move_i<kDppWaveShr1>(il), il_dn = dpp_move_i<kDppWaveShl1>(il);
         const bool ifirst = act && (lane == 0 || il_up != il);
         const bool ilast = act && (lane == 63 || il_dn != il);
-        const int ihead = run_head(__ballot(ifirst), lane);
+        const int ihead = run_head(__ballot(ifirst), upto);
         const float icr = act ? (float)(lane - ihead + 1) * L.rA[il] : 0.f;
         float aq[QI], bq[QI];
 #pragma unroll
@@ -1036,7 +1042,7 @@ __device__ void block_tiles_bf(const StratArgs& a, int t0, int t1, const TileLds
         const int sj_up = dpp_move_i<kDppWaveShr1>(sj), sj_dn = dpp_move_i<kDppWaveShl1>(sj);
         const bool jfirst = act && (lane == 0 || sj_up != sj);
         const bool jlast = act && (lane == 63 || sj_dn != sj);
-        const int jhead = run_head(__ballot(jfirst), lane);
+        const int jhead = run_head(__ballot(jfirst), upto);
         const float jcr = act ? (float)(lane - jhead + 1) * L.rB[sj] : 0.f;
         float bp[QJ];
 #pragma unroll
