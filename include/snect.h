@@ -314,12 +314,14 @@ int snect_exec_path(const snect_problem *prob);
  * continuous batching.  With B, C, G fixed, a new patient's observed cells
  * (j_t, k_t, x_t) give rows w_t = G x2 b_{j_t} x3 c_{k_t}; the server finds
  *     u = argmin 1/2 |x - W u|^2 + lambda/2 |u|^2
- * (Eq. 6 with a ridge term) in FP64: pg_iters projected-gradient steps from
- * u = 0 with step 1/|Q|_F, Q = W^T W + lambda I, then one refinement
- * u <- u + Q^{-1}(r - Q u) through a Cholesky factorisation of Q (the exact
- * minimiser).  It then returns the topk rows of A with the largest cosine
- * similarity to u (rows of zero norm excluded, ties to the lower row index;
- * missing entries are -1 with score -inf).
+ * (Eq. 6 with a ridge term): the rows w, Q = W^T W + lambda I and r = W^T x
+ * in FP32 (fixed-order sums), pg_iters projected-gradient steps from u = 0
+ * with step 1/|Q|_F in FP32, then one refinement u <- u + Q^{-1}(r - Q u) in
+ * FP64 (residual, Cholesky factorisation of Q and the two triangular solves),
+ * which gives the minimiser of the FP32-formed system.  It then returns the
+ * topk rows of A with the largest cosine similarity to u (FP32; rows of zero
+ * norm excluded, ties to the lower row index; missing entries are -1 with
+ * score -inf).
  *
  * Requests are admitted while a slot (one HIP stream each) and room in the
  * device request pool (12 bytes per cell, 256-byte aligned) are free; each
@@ -369,10 +371,14 @@ int snect_server_poll(snect_server *srv, int64_t ticket, double *u, int32_t *idx
  * arrive and as slots and pool room free up, completions are polled, and
  * latency_s[r] = completion - arrival.  u [nreq*J1], idx and score
  * [nreq*topk] and status [nreq] (SNECT_OK or the request's error) may be
- * NULL.  *wall_s receives the total time. */
+ * NULL.  *wall_s receives the total time.  If gpu_busy_s is not NULL, each
+ * request's kernels are bracketed with timing events and *gpu_busy_s
+ * receives the time during which at least one request's kernels ran (the
+ * union of those windows; uploads and downloads not included).  Errors:
+ * E_ARG, E_HIP (timing events); a request's own error goes to status. */
 int snect_server_replay(snect_server *srv, int64_t nreq, const double *arrival_s, const int64_t *offsets,
                         const int32_t *j, const int32_t *k, const float *x, double *latency_s, double *u,
-                        int32_t *idx, double *score, int32_t *status, double *wall_s);
+                        int32_t *idx, double *score, int32_t *status, double *wall_s, double *gpu_busy_s);
 
 #ifdef __cplusplus
 }

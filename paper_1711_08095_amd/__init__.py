@@ -12,7 +12,6 @@ import os
 import sys
 import weakref
 
-_finalizing = sys.is_finalizing
 from dataclasses import dataclass
 from typing import Optional
 
@@ -133,7 +132,7 @@ def load(path: str = LIB_PATH):
         "snect_server_destroy": (ctypes.c_int, [vp]),
         "snect_server_submit": (ctypes.c_int, [vp, i64, vp, vp, vp, ctypes.POINTER(i64)]),
         "snect_server_poll": (ctypes.c_int, [vp, i64, vp, vp, vp]),
-        "snect_server_replay": (ctypes.c_int, [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "snect_server_replay": (ctypes.c_int, [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "snect_sweep_train": (ctypes.c_int, [vp, i32, vp, vp, i32, i32, vp, vp]),
         "snect_autotune": (ctypes.c_int, [vp, ctypes.POINTER(Factors), i32, ctypes.POINTER(Exec), vp]),
         "snect_sweep_autotune": (ctypes.c_int, [vp, i32, vp, vp, i32, vp]),
@@ -212,10 +211,11 @@ class Context:
             _check(load().snect_destroy(self.h), self.h)
             self.h = None
 
-    def __del__(self):
-        # at interpreter shutdown the HIP runtime may already be gone; the
+    def __del__(self, _fin=sys.is_finalizing):
+        # at interpreter shutdown the HIP runtime may already be gone (and
+        # module globals already cleared, hence the bound default); the
         # process exit releases the memory
-        if _finalizing():
+        if _fin():
             return
         try:
             self.close()
@@ -369,8 +369,9 @@ class Server:
             _check(rc, self.ctx.h)
         return u, idx, sc
 
-    def replay(self, arrival_s, offsets, j, k, x):
-        """Native open-loop replay; returns latencies, results and status."""
+    def replay(self, arrival_s, offsets, j, k, x, gpu_busy=False):
+        """Native open-loop replay; returns latencies, results and status
+        (and, with gpu_busy, the seconds during which request kernels ran)."""
         arrival_s = np.ascontiguousarray(arrival_s, dtype=np.float64)
         offsets = np.ascontiguousarray(offsets, dtype=np.int64)
         j = np.ascontiguousarray(j, dtype=np.int32)
@@ -383,19 +384,24 @@ class Server:
         sc = np.zeros((n, self.topk))
         st = np.zeros(n, np.int32)
         wall = ctypes.c_double()
+        busy = ctypes.c_double(-1.0)
         _check(load().snect_server_replay(self.h, n, arrival_s.ctypes.data, offsets.ctypes.data, j.ctypes.data,
                                           k.ctypes.data, x.ctypes.data, lat.ctypes.data, u.ctypes.data,
                                           idx.ctypes.data, sc.ctypes.data, st.ctypes.data,
-                                          ctypes.addressof(wall)), self.ctx.h)
-        return dict(latency_s=lat, u=u, idx=idx, score=sc, status=st, wall_s=wall.value)
+                                          ctypes.addressof(wall), ctypes.addressof(busy) if gpu_busy else None),
+               self.ctx.h)
+        out = dict(latency_s=lat, u=u, idx=idx, score=sc, status=st, wall_s=wall.value)
+        if gpu_busy:
+            out["gpu_busy_s"] = busy.value
+        return out
 
     def close(self):
         if getattr(self, "h", None):
             load().snect_server_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if _finalizing():
+    def __del__(self, _fin=sys.is_finalizing):
+        if _fin():
             return
         try:
             self.close()
@@ -529,8 +535,8 @@ class Problem:
             load().snect_problem_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if _finalizing():
+    def __del__(self, _fin=sys.is_finalizing):
+        if _fin():
             return
         try:
             self.close()

@@ -5,15 +5,18 @@
 // rows w_t = G x2 b_{j_t} x3 c_{k_t} = H_{k_t} b_{j_t} (J1 values).  Eq. (6)
 // asks for the u minimising |x - W u|; as in the library's reading a ridge
 // term lambda/2 |u|^2 is added, so u solves (W^T W + lambda I) u = W^T x.
-// The server computes, per request and in FP64:
-//   Q = W^T W + lambda I and r = W^T x (partial sums per workgroup over
-//       contiguous nonzero ranges, then added in ascending order);
-//   pg_iters projected-gradient steps from u = 0 with step 1/|Q|_F (the
-//       projection is the identity: u is unconstrained);
-//   one refinement u <- u + Q^{-1}(r - Q u) through a Cholesky factorisation
-//       of Q, which lands on the exact minimiser;
-//   cosine similarity of u with every row of A (rows of zero norm excluded)
-//       and the top k rows, ties to the lower row index.
+// The server computes, per request:
+//   Q = W^T W + lambda I and r = W^T x in FP32 (the rows w from an FP32
+//       table; partial sums per workgroup over contiguous nonzero ranges,
+//       then added in ascending order);
+//   pg_iters projected-gradient steps from u = 0 with step 1/|Q|_F, in FP32
+//       (the projection is the identity: u is unconstrained);
+//   one refinement u <- u + Q^{-1}(r - Q u) in FP64: the residual and a
+//       Cholesky factorisation of Q with its two triangular solves, which
+//       lands on the minimiser of the FP32-formed system;
+//   cosine similarity of u with every row of A in FP32 (rows of zero norm
+//       excluded) and the top k rows, ties to the lower row index.
+// FP64 is used for the J1 x J1 refinement only.
 // Nothing is shared between requests, so a request's result does not depend
 // on what else runs beside it.
 #include <hip/hip_runtime.h>
@@ -23,40 +26,41 @@
 namespace snect {
 
 // W[(k*I2 + j)*J1 + a] = sum_b H_k[a][b] B[j][b], H_k[a][b] = sum_c G[a,b,c] C[k][c]
+// (FP32, ascending b and c).
 __global__ __launch_bounds__(256) void serve_build_w(const float* B, const float* C, const float* G, int I2, int I3,
-                                                     int J1, int J2, int J3, double* W)
+                                                     int J1, int J2, int J3, float* W)
 {
     const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
     if (idx >= (long long)I3 * I2 * J1) return;
     const int a = (int)(idx % J1);
     const long long kj = idx / J1;
     const int j = (int)(kj % I2), k = (int)(kj / I2);
-    double s = 0.0;
+    float s = 0.f;
     for (int b = 0; b < J2; ++b) {
-        double h = 0.0;
-        for (int c = 0; c < J3; ++c) h += (double)G[(a * J2 + b) * J3 + c] * (double)C[k * J3 + c];
-        s += h * (double)B[(size_t)j * J2 + b];
+        float h = 0.f;
+        for (int c = 0; c < J3; ++c) h = fmaf(G[(a * J2 + b) * J3 + c], C[k * J3 + c], h);
+        s = fmaf(h, B[(size_t)j * J2 + b], s);
     }
     W[idx] = s;
 }
 
-// Row norms of A and its transpose At[c * I1 + r] = A[r][c] (FP32), so
-// that the cosine pass reads columns with consecutive threads on
-// consecutive rows.
-__global__ __launch_bounds__(256) void serve_rows(const float* A, int I1, int J1, double* nrm, float* At)
+// Row norms of A (FP32, ascending columns) and its transpose
+// At[c * I1 + r] = A[r][c], so that the cosine pass reads columns with
+// consecutive threads on consecutive rows.
+__global__ __launch_bounds__(256) void serve_rows(const float* A, int I1, int J1, float* nrm, float* At)
 {
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= I1) return;
-    double s = 0.0;
+    float s = 0.f;
     for (int c = 0; c < J1; ++c) {
         const float v = A[(size_t)r * J1 + c];
-        s += (double)v * (double)v;
+        s = fmaf(v, v, s);
         At[(size_t)c * I1 + r] = v;
     }
-    nrm[r] = sqrt(s);
+    nrm[r] = sqrtf(s);
 }
 
-constexpr int kFoldBatch = 128;  // nonzeros staged per pass (34 KB of LDS)
+constexpr int kFoldBatch = 128;  // nonzeros staged per pass (17 KB of LDS)
 
 // Partial Gram sums: workgroup g takes nonzeros [g*chunk, (g+1)*chunk)
 // (at most kServeMaxParts workgroups per request).
@@ -66,12 +70,12 @@ constexpr int kFoldBatch = 128;  // nonzeros staged per pass (34 KB of LDS)
 // s of a batch's nb nonzeros is [s*nb/G, (s+1)*nb/G), and the G sums of an
 // entry are added in slice order at the end.
 __global__ __launch_bounds__(256) void serve_gram(const int32_t* jj, const int32_t* kk, const float* xx, int n,
-                                                  int chunk, const double* W, int I2, int J1, double* part)
+                                                  int chunk, const float* W, int I2, int J1, float* part)
 {
-    __shared__ double wb[kFoldBatch * 33];
-    __shared__ double xb[kFoldBatch];
+    __shared__ float wb[kFoldBatch * 33];
+    __shared__ float xb[kFoldBatch];
     __shared__ long long rbase[kFoldBatch];
-    __shared__ double psum[576];
+    __shared__ float psum[576];
     const int tid = threadIdx.x, g = blockIdx.x;
     const int nq = J1 * (J1 + 1) / 2, ne = nq + J1;
     const int G = ne < 256 ? 256 / ne : 1;
@@ -97,14 +101,14 @@ __global__ __launch_bounds__(256) void serve_gram(const int32_t* jj, const int32
             tb[u] = -1;  // r[a]: the value times w_a
         }
     }
-    double acc[3] = {0.0, 0.0, 0.0};
+    float acc[3] = {0.f, 0.f, 0.f};
     for (int b0 = z0; b0 < z1; b0 += kFoldBatch) {
         const int nb = (z1 - b0) < kFoldBatch ? (z1 - b0) : kFoldBatch;
         __syncthreads();
         if (tid < nb) {
             const int z = b0 + tid;
             rbase[tid] = ((long long)kk[z] * I2 + jj[z]) * J1;
-            xb[tid] = (double)xx[z];
+            xb[tid] = xx[z];
         }
         __syncthreads();
         // the batch's rows of W, every thread gathering (independent loads)
@@ -119,13 +123,13 @@ __global__ __launch_bounds__(256) void serve_gram(const int32_t* jj, const int32
             if (tsl[u] < 0) continue;
             const int t0 = (int)(((long long)nb * tsl[u]) / G), t1 = (int)(((long long)nb * (tsl[u] + 1)) / G);
             const int aa = ta[u], bb = tb[u];
-            double s = acc[u];
+            float s = acc[u];
             if (bb >= 0) {
 #pragma unroll 4
-                for (int t = t0; t < t1; ++t) s += wb[t * 33 + aa] * wb[t * 33 + bb];
+                for (int t = t0; t < t1; ++t) s = fmaf(wb[t * 33 + aa], wb[t * 33 + bb], s);
             } else {
 #pragma unroll 4
-                for (int t = t0; t < t1; ++t) s += xb[t] * wb[t * 33 + aa];
+                for (int t = t0; t < t1; ++t) s = fmaf(xb[t], wb[t * 33 + aa], s);
             }
             acc[u] = s;
         }
@@ -135,7 +139,7 @@ __global__ __launch_bounds__(256) void serve_gram(const int32_t* jj, const int32
         if (tsl[u] >= 0) psum[tid + 256 * u] = acc[u];
     __syncthreads();
     for (int e = tid; e < ne; e += 256) {
-        double s = psum[e];
+        float s = psum[e];
         for (int sl = 1; sl < G; ++sl) s += psum[sl * ne + e];
         part[(size_t)g * ne + e] = s;
     }
@@ -152,6 +156,10 @@ __device__ inline void wave_sync()
 }
 
 // Value of v in lane l of the wavefront (l uniform).
+__device__ inline float lane_f(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
 __device__ inline double lane_d(double v, int l)
 {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
@@ -160,19 +168,20 @@ __device__ inline double lane_d(double v, int l)
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-// Cosine scores of the eight rows i0 + 256 q (q < 8): the loads of up to
-// twelve columns of all eight rows are issued before any product.  Rows
-// past I1 are computed on row I1 - 1 and must not be used.
-__device__ inline void cosine8(const float* At, const double* anrm, const double* u, double un, int I1, int J1,
-                               int i0, double sc[8])
+// Cosine scores (FP32) of the eight rows i0 + 256 q (q < 8): the loads of up
+// to twelve columns of all eight rows are issued before any product, and
+// each dot product adds its columns in ascending order.  Rows past I1 are
+// computed on row I1 - 1 and must not be used.
+__device__ inline void cosine8(const float* At, const float* anrm, const float* u, float un, int I1, int J1, int i0,
+                               float sc[8])
 {
     constexpr int kCols = 12;
     int row[8];
-    double nr[8], dot[8];
+    float nr[8], dot[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         row[q] = i0 + 256 * q < I1 ? i0 + 256 * q : I1 - 1;
-        dot[q] = 0.0;
+        dot[q] = 0.f;
     }
     for (int c0 = 0; c0 < J1; c0 += kCols) {
         float v[8][kCols];
@@ -188,29 +197,29 @@ __device__ inline void cosine8(const float* At, const double* anrm, const double
 #pragma unroll
         for (int c = 0; c < kCols; ++c) {
             if (c0 + c >= J1) break;
-            const double uc = u[c0 + c];
+            const float uc = u[c0 + c];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) dot[q] += (double)v[q][c] * uc;
+            for (int q = 0; q < 8; ++q) dot[q] = fmaf(v[q][c], uc, dot[q]);
         }
     }
     // rows of zero norm are excluded (NaN); a zero u scores every other row -inf
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        double x = nr[q] > 0.0 ? -INFINITY : NAN;
-        if (nr[q] > 0.0 && un > 0.0) x = dot[q] / (nr[q] * un);
+        float x = nr[q] > 0.f ? -INFINITY : NAN;
+        if (nr[q] > 0.f && un > 0.f) x = dot[q] / (nr[q] * un);
         sc[q] = x;
     }
 }
 
 // Larger score first, lower row index on ties; an index < 0 is no candidate.
-__device__ inline bool better(double s2, int i2, double s1, int i1)
+__device__ inline bool better(float s2, int i2, float s1, int i1)
 {
     return i2 >= 0 && (i1 < 0 || s2 > s1 || (s2 == s1 && i2 < i1));
 }
 
 // A thread's best (bs, bi) and runner-up (cs, ci) among the rows offered.
 struct Best2 {
-    double bs, cs;
+    float bs, cs;
     int bi, ci;
 };
 
@@ -225,11 +234,9 @@ __device__ inline int dpp_i(int v)
 }
 
 template <int CTRL>
-__device__ inline void best_step_dpp(double& s, int& i)
+__device__ inline void best_step_dpp(float& s, int& i)
 {
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, s);
-    const unsigned lo = (unsigned)dpp_i<CTRL>((int)(unsigned)b), hi = (unsigned)dpp_i<CTRL>((int)(unsigned)(b >> 32));
-    const double s2 = __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+    const float s2 = __int_as_float(dpp_i<CTRL>(__float_as_int(s)));
     const int i2 = dpp_i<CTRL>(i);
     if (better(s2, i2, s, i)) {
         s = s2;
@@ -237,7 +244,7 @@ __device__ inline void best_step_dpp(double& s, int& i)
     }
 }
 
-__device__ inline void wave_best(double& s, int& i)
+__device__ inline void wave_best(float& s, int& i)
 {
     best_step_dpp<0xB1>(s, i);   // quad_perm [1,0,3,2]
     best_step_dpp<0x4E>(s, i);   // quad_perm [2,3,0,1]
@@ -245,7 +252,7 @@ __device__ inline void wave_best(double& s, int& i)
     best_step_dpp<0x128>(s, i);  // row_ror 8
 #pragma unroll
     for (int o = 16; o <= 32; o <<= 1) {
-        const double s2 = __shfl_xor(s, o);
+        const float s2 = __shfl_xor(s, o);
         const int i2 = __shfl_xor(i, o);
         if (better(s2, i2, s, i)) {
             s = s2;
@@ -254,7 +261,7 @@ __device__ inline void wave_best(double& s, int& i)
     }
 }
 
-__device__ __attribute__((always_inline)) inline void offer(Best2& c, double x, int i)
+__device__ __attribute__((always_inline)) inline void offer(Best2& c, float x, int i)
 {
     if (x != x) return;
     if (better(x, i, c.bs, c.bi)) {
@@ -269,29 +276,31 @@ __device__ __attribute__((always_inline)) inline void offer(Best2& c, double x, 
 }
 
 // Solve and search, one workgroup per request.  out: u[J1], then for the
-// top k: scores (double), then indices (int, stored as double); status[0]:
-// 1 if Q is not positive definite.  Both are stored once, at the end (a
-// store to host memory would hold up every later barrier), so out and
-// status may be device mappings of pinned host memory.  RS: a thread's
-// scores (rows tid + 256 q) stay in registers (I1 <= 256 * kRegRows), else
-// they go to `gscores` (global, I1 entries).
+// top k: scores, then indices (as doubles); status[0]: 1 if Q is not
+// positive definite.  Both are stored once, at the end (a store to host
+// memory would hold up every later barrier), so out and status may be
+// device mappings of pinned host memory.  RS: a thread's scores (rows
+// tid + 256 q) stay in registers (I1 <= 256 * kRegRows), else they go to
+// `gscores` (global, I1 entries).
 template <bool RS>
-__global__ __launch_bounds__(256) void serve_solve(const double* part, int nparts, int J1, double lam, int pg_iters,
-                                                   const float* At, const double* anrm, int I1, int topk,
-                                                   double* gscores, double* out, int* status)
+__global__ __launch_bounds__(256) void serve_solve(const float* part, int nparts, int J1, float lam, int pg_iters,
+                                                   const float* At, const float* anrm, int I1, int topk,
+                                                   float* gscores, double* out, int* status)
 {
-    __shared__ double Q[32 * 32];  // Q, then the rows of L
-    __shared__ double r[32], u[32];
-    __shared__ double psub[576];
-    __shared__ double red_s[8];  // per wavefront, two rounds
+    __shared__ float Q[32 * 32];
+    __shared__ double Lt[32 * 32];  // rows of L, read back as columns
+    __shared__ float r[32], uf[32];
+    __shared__ double ud[32];
+    __shared__ float psub[576];
+    __shared__ float red_s[8];  // per wavefront, two rounds
     __shared__ int red_i[8];
-    __shared__ double unorm;
+    __shared__ float unorm;
     __shared__ int bad;
-    __shared__ double top_s[64];  // topk <= 64
+    __shared__ float top_s[64];  // topk <= 64
     __shared__ int top_i[64];
     const int tid = threadIdx.x;
     const int nq = J1 * (J1 + 1) / 2, ne = nq + J1;
-    // Q and r from the partial sums: G threads per entry each add a
+    // Q and r from the partial sums (FP32): G threads per entry each add a
     // contiguous range of workgroups in ascending order (32 loads in
     // flight), then the G range sums are added in ascending order.
     // Consecutive threads take consecutive entries of one range, so a
@@ -300,11 +309,11 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
     for (int task = tid; task < ne * G; task += 256) {
         const int gsub = task / ne, e = task - gsub * ne;
         const int p0 = (int)(((long long)nparts * gsub) / G), p1 = (int)(((long long)nparts * (gsub + 1)) / G);
-        double acc = 0.0;
+        float acc = 0.f;
         for (int pb = p0; pb < p1; pb += 32) {
-            double v[32];
+            float v[32];
 #pragma unroll
-            for (int q = 0; q < 32; ++q) v[q] = pb + q < p1 ? part[(size_t)(pb + q) * ne + e] : 0.0;
+            for (int q = 0; q < 32; ++q) v[q] = pb + q < p1 ? part[(size_t)(pb + q) * ne + e] : 0.f;
 #pragma unroll
             for (int q = 0; q < 32; ++q) acc += v[q];
         }
@@ -312,7 +321,7 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
     }
     __syncthreads();
     for (int e = tid; e < ne; e += 256) {
-        double s = psub[e];
+        float s = psub[e];
         for (int gsub = 1; gsub < G; ++gsub) s += psub[gsub * ne + e];
         if (e < nq) {
             int a = 0, rem = e;
@@ -321,65 +330,65 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
                 ++a;
             }
             const int b = a + rem;
-            Q[a * J1 + b] = s + (a == b ? lam : 0.0);
-            Q[b * J1 + a] = s + (a == b ? lam : 0.0);
+            Q[a * J1 + b] = s + (a == b ? lam : 0.f);
+            Q[b * J1 + a] = s + (a == b ? lam : 0.f);
         } else {
             r[e - nq] = s;
         }
     }
     __syncthreads();
     // The J1 x J1 algebra runs in wavefront 0 alone: lane a holds row a of
-    // Q and of L in registers and reads other lanes' values by readlane.
+    // Q (and of L) in registers and reads other lanes' values by readlane.
     if (tid < 64) {
         const int a = tid;
         const bool own = a < J1;
-        double qa[32], la[32];
+        float qa[32];
 #pragma unroll
-        for (int b = 0; b < 32; ++b) {
-            qa[b] = (own && b < J1) ? Q[a * J1 + b] : 0.0;
-            la[b] = 0.0;
-        }
+        for (int b = 0; b < 32; ++b) qa[b] = (own && b < J1) ? Q[a * J1 + b] : 0.f;
         // PG step 1/|Q|_F: row sums of squares, added in row order
-        double fa = 0.0;
+        float fa = 0.f;
 #pragma unroll
-        for (int b = 0; b < 32; ++b) fa += qa[b] * qa[b];
-        double f = 0.0;
-        for (int b = 0; b < J1; ++b) f += lane_d(fa, b);
-        const double stp = f > 0.0 ? 1.0 / sqrt(f) : 0.0;
-        const double ra = own ? r[a] : 0.0;
-        // projected-gradient steps from u = 0 (identity projection); the
-        // row-times-u sum runs on four accumulators (columns b mod 4), as
-        // the FP64 multiply-add chain bounds these steps.  Columns J1..
-        // and lanes J1.. hold zeros, so blocks of four need no inner guard.
-        double ua = 0.0;
+        for (int b = 0; b < 32; ++b) fa = fmaf(qa[b], qa[b], fa);
+        float f = 0.f;
+        for (int b = 0; b < J1; ++b) f += lane_f(fa, b);
+        const float stp = f > 0.f ? 1.f / sqrtf(f) : 0.f;
+        const float ra = own ? r[a] : 0.f;
+        // projected-gradient steps from u = 0 (identity projection), FP32; the
+        // row-times-u sum runs on four accumulators (columns b mod 4).
+        // Columns J1.. and lanes J1.. hold zeros, so blocks of four need no
+        // inner guard.
+        float ua = 0.f;
         for (int it = 0; it < pg_iters; ++it) {
-            double s0 = -ra, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            float s0 = -ra, s1 = 0.f, s2 = 0.f, s3 = 0.f;
 #pragma unroll
             for (int b = 0; b < 32; b += 4) {
                 if (b < J1) {
-                    s0 += qa[b] * lane_d(ua, b);
-                    s1 += qa[b + 1] * lane_d(ua, b + 1);
-                    s2 += qa[b + 2] * lane_d(ua, b + 2);
-                    s3 += qa[b + 3] * lane_d(ua, b + 3);
+                    s0 = fmaf(qa[b], lane_f(ua, b), s0);
+                    s1 = fmaf(qa[b + 1], lane_f(ua, b + 1), s1);
+                    s2 = fmaf(qa[b + 2], lane_f(ua, b + 2), s2);
+                    s3 = fmaf(qa[b + 3], lane_f(ua, b + 3), s3);
                 }
             }
             if (own) ua -= stp * ((s0 + s1) + (s2 + s3));
         }
-        // refinement through Q = L L^T: residual g = r - Q u
-        double ga = ra;
+        // refinement in FP64: residual g = r - Q u, then Q = L L^T
+        double ga = (double)ra;
 #pragma unroll
         for (int b = 0; b < 32; ++b)
-            if (b < J1) ga -= qa[b] * lane_d(ua, b);
+            if (b < J1) ga -= (double)qa[b] * (double)lane_f(ua, b);
         // Cholesky column by column; every entry in the order of the
         // textbook row loop (lane c forms the pivot, lanes below it L[a][c]).
         // After a pivot <= 0 the factor is not used: the loop carries on
         // with a unit pivot, so that every loop here has a fixed trip count
         // and the register arrays keep static indices.
+        double la[32];
+#pragma unroll
+        for (int b = 0; b < 32; ++b) la[b] = 0.0;
         bool failed = false;
 #pragma unroll
         for (int c = 0; c < 32; ++c) {
             if (c < J1) {
-                double v = qa[c];
+                double v = (double)qa[c];
 #pragma unroll
                 for (int t = 0; t < c; ++t) v -= la[t] * lane_d(la[t], c);
                 const double dd = lane_d(v, c);
@@ -403,17 +412,15 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
                     if (a > t) va -= la[t] * yt;
                 }
             }
-            // L^T z = y needs column a of L in lane a: through LDS (Q is no
-            // longer needed)
-            wave_sync();
+            // L^T z = y needs column a of L in lane a: through LDS
             if (own) {
 #pragma unroll
-                for (int t = 0; t < 32; ++t) Q[a * 32 + t] = la[t];
+                for (int t = 0; t < 32; ++t) Lt[a * 32 + t] = la[t];
             }
             wave_sync();
             double lc[32];
 #pragma unroll
-            for (int t = 0; t < 32; ++t) lc[t] = (own && t < J1) ? Q[t * 32 + a] : 0.0;
+            for (int t = 0; t < 32; ++t) lc[t] = (own && t < J1) ? Lt[t * 32 + a] : 0.0;
             // z_t final at step t (descending), lanes a < t subtract
             double wa = ya;
 #pragma unroll
@@ -425,20 +432,22 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
                 }
             }
         }
-        ua += za;
-        double s = 0.0;
-        for (int e = 0; e < J1; ++e) {
-            const double ue = lane_d(ua, e);
-            s += ue * ue;
+        const double uad = (double)ua + za;
+        // the search works on u rounded to FP32
+        const float uaf = (float)uad;
+        float s = 0.f;
+        for (int e = 0; e < J1; ++e) s = fmaf(lane_f(uaf, e), lane_f(uaf, e), s);
+        if (own) {
+            ud[a] = uad;
+            uf[a] = uaf;
         }
-        if (own) u[a] = ua;
         if (a == 0) {
-            unorm = sqrt(s);
+            unorm = sqrtf(s);
             bad = failed ? 1 : 0;
         }
     }
     __syncthreads();
-    const double un = unorm;
+    const float un = unorm;
     // cosine scores, then top k by repeated arg-max.  Every thread keeps the
     // best and the runner-up of its own rows (tid, tid + 256, ...); a round
     // reduces the bests within each wavefront by lane exchanges, then every
@@ -446,24 +455,24 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
     // winner promotes its runner-up, and rescans its rows only when it has
     // none (it won before).  A thread's rows go in decreasing order, so the
     // rows it has left are those worse than the last one taken.
-    double sc[RS ? kRegRows : 1];
+    float sc[RS ? kRegRows : 1];
     Best2 cb{-INFINITY, -INFINITY, -1, -1};
     bool have2 = true;  // cb.cs, cb.ci is the runner-up of the remaining rows
-    double lt_s = 0.0;  // the last row this thread gave up (none while lt_i < 0)
+    float lt_s = 0.f;   // the last row this thread gave up (none while lt_i < 0)
     int lt_i = -1;
     if constexpr (RS) {
 #pragma unroll
         for (int p = 0; p < kRegRows / 8; ++p) {
             if (p * 2048 >= I1) break;
-            cosine8(At, anrm, u, un, I1, J1, tid + p * 2048, sc + 8 * p);
+            cosine8(At, anrm, uf, un, I1, J1, tid + p * 2048, sc + 8 * p);
         }
 #pragma unroll
         for (int q = 0; q < kRegRows; ++q)
             if (tid + 256 * q < I1) offer(cb, sc[q], tid + 256 * q);
     } else {
         for (int i0 = tid; i0 < I1; i0 += 2048) {
-            double x[8];
-            cosine8(At, anrm, u, un, I1, J1, i0, x);
+            float x[8];
+            cosine8(At, anrm, uf, un, I1, J1, i0, x);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int i = i0 + 256 * q;
@@ -475,7 +484,7 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
     }
     const int lane = tid & 63, wv = tid >> 6;
     for (int t = 0; t < topk; ++t) {
-        double ws = cb.bs;
+        float ws = cb.bs;
         int wi = cb.bi;
         wave_best(ws, wi);
         const int rb = (t & 1) * 4;  // a buffer is rewritten two rounds later, past one more barrier
@@ -484,7 +493,7 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
             red_i[rb + wv] = wi;
         }
         __syncthreads();
-        double s1 = red_s[rb];
+        float s1 = red_s[rb];
         int i1 = red_i[rb];
         for (int w = 1; w < 4; ++w) {
             if (better(red_s[rb + w], red_i[rb + w], s1, i1)) {
@@ -519,16 +528,16 @@ __global__ __launch_bounds__(256) void serve_solve(const double* part, int npart
         }
     }
     __syncthreads();
-    if (tid < J1) out[tid] = u[tid];
+    if (tid < J1) out[tid] = ud[tid];
     if (tid < topk) {
-        out[J1 + tid] = top_s[tid];
+        out[J1 + tid] = (double)top_s[tid];
         out[J1 + topk + tid] = (double)top_i[tid];
     }
     if (tid == 0) status[0] = bad;
 }
 
 hipError_t launch_serve_setup(const float* A, const float* B, const float* C, const float* G, int I1, int I2, int I3,
-                              int J1, int J2, int J3, double* W, double* anrm, float* At, hipStream_t st)
+                              int J1, int J2, int J3, float* W, float* anrm, float* At, hipStream_t st)
 {
     const long long nw = (long long)I3 * I2 * J1;
     hipLaunchKernelGGL(serve_build_w, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, B, C, G, I2, I3, J1, J2,
@@ -545,19 +554,19 @@ int serve_parts(int n)
     return p < 1 ? 1 : (p < kServeMaxParts ? p : kServeMaxParts);
 }
 
-hipError_t launch_serve_request(const int32_t* jj, const int32_t* kk, const float* xx, int n, const double* W, int I2,
-                                int J1, double lam, int pg_iters, const float* At, const double* anrm, int I1,
-                                int topk, double* part, double* scores, double* out, int* status, hipStream_t st)
+hipError_t launch_serve_request(const int32_t* jj, const int32_t* kk, const float* xx, int n, const float* W, int I2,
+                                int J1, double lam, int pg_iters, const float* At, const float* anrm, int I1,
+                                int topk, float* part, float* scores, double* out, int* status, hipStream_t st)
 {
     const int np = serve_parts(n);
     const int chunk = n > 0 ? (n + np - 1) / np : 1;
     hipLaunchKernelGGL(serve_gram, dim3(np), dim3(256), 0, st, jj, kk, xx, n, chunk, W, I2, J1, part);
     if (I1 <= 256 * kRegRows)
-        hipLaunchKernelGGL(serve_solve<true>, dim3(1), dim3(256), 0, st, part, np, J1, lam, pg_iters, At, anrm, I1,
-                           topk, scores, out, status);
+        hipLaunchKernelGGL(serve_solve<true>, dim3(1), dim3(256), 0, st, part, np, J1, (float)lam, pg_iters, At, anrm,
+                           I1, topk, scores, out, status);
     else
-        hipLaunchKernelGGL(serve_solve<false>, dim3(1), dim3(256), 0, st, part, np, J1, lam, pg_iters, At, anrm, I1,
-                           topk, scores, out, status);
+        hipLaunchKernelGGL(serve_solve<false>, dim3(1), dim3(256), 0, st, part, np, J1, (float)lam, pg_iters, At, anrm,
+                           I1, topk, scores, out, status);
     return hipGetLastError();
 }
 

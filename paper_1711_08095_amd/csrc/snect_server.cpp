@@ -25,10 +25,10 @@
 
 namespace snect {
 hipError_t launch_serve_setup(const float* A, const float* B, const float* C, const float* G, int I1, int I2, int I3,
-                              int J1, int J2, int J3, double* W, double* anrm, float* At, hipStream_t st);
-hipError_t launch_serve_request(const int32_t* jj, const int32_t* kk, const float* xx, int n, const double* W, int I2,
-                                int J1, double lam, int pg_iters, const float* At, const double* anrm, int I1,
-                                int topk, double* part, double* scores, double* out, int* status, hipStream_t st);
+                              int J1, int J2, int J3, float* W, float* anrm, float* At, hipStream_t st);
+hipError_t launch_serve_request(const int32_t* jj, const int32_t* kk, const float* xx, int n, const float* W, int I2,
+                                int J1, double lam, int pg_iters, const float* At, const float* anrm, int I1,
+                                int topk, float* part, float* scores, double* out, int* status, hipStream_t st);
 int serve_parts(int n);
 }  // namespace snect
 
@@ -84,6 +84,9 @@ struct PoolAlloc {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
+    // timing events around the request's kernels (recorded only by a replay
+    // that measures device-busy time)
+    hipEvent_t k0 = nullptr, k1 = nullptr;
     bool busy = false;
     int64_t ticket = -1;
     size_t off = 0, bytes = 0;
@@ -94,8 +97,8 @@ struct Slot {
     // on the device and in pinned host memory (one download per request)
     double* h_out = nullptr;
     // per-slot device scratch
-    double* d_part = nullptr;
-    double* d_scores = nullptr;
+    float* d_part = nullptr;
+    float* d_scores = nullptr;
     double* d_out = nullptr;
 };
 
@@ -112,8 +115,8 @@ struct snect_server {
     std::string* err = nullptr;  // the owning context's message
     int32_t I1 = 0, I2 = 0, I3 = 0, J1 = 0;
     snect_server_config cfg{};
-    double* d_W = nullptr;      // [I3][I2][J1]
-    double* d_anrm = nullptr;   // [I1]
+    float* d_W = nullptr;       // [I3][I2][J1]
+    float* d_anrm = nullptr;    // [I1]
     float* d_At = nullptr;      // [J1][I1], A transposed
     char* d_pool = nullptr;
     PoolAlloc pool;
@@ -168,8 +171,8 @@ int snect_server_create(snect_ctx* ctx, int32_t I1, int32_t I2, int32_t I3, int3
         *err = m;
         return code;
     };
-    if (hipMalloc((void**)&s->d_W, sizeof(double) * (size_t)I3 * I2 * J1) != hipSuccess ||
-        hipMalloc((void**)&s->d_anrm, sizeof(double) * (size_t)I1) != hipSuccess ||
+    if (hipMalloc((void**)&s->d_W, sizeof(float) * (size_t)I3 * I2 * J1) != hipSuccess ||
+        hipMalloc((void**)&s->d_anrm, sizeof(float) * (size_t)I1) != hipSuccess ||
         hipMalloc((void**)&s->d_At, sizeof(float) * (size_t)J1 * I1) != hipSuccess ||
         hipMalloc((void**)&s->d_pool, (size_t)cfg->pool_bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -185,8 +188,9 @@ int snect_server_create(snect_ctx* ctx, int32_t I1, int32_t I2, int32_t I3, int3
     for (auto& sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-            hipMalloc((void**)&sl.d_part, sizeof(double) * kServeMaxParts * ne) != hipSuccess ||
-            hipMalloc((void**)&sl.d_scores, sizeof(double) * (size_t)I1) != hipSuccess ||
+            hipEventCreate(&sl.k0) != hipSuccess || hipEventCreate(&sl.k1) != hipSuccess ||
+            hipMalloc((void**)&sl.d_part, sizeof(float) * kServeMaxParts * ne) != hipSuccess ||
+            hipMalloc((void**)&sl.d_scores, sizeof(float) * (size_t)I1) != hipSuccess ||
             hipMalloc((void**)&sl.d_out, sizeof(double) * (s->out_len() + 1)) != hipSuccess ||
             hipHostMalloc((void**)&sl.h_out, sizeof(double) * (s->out_len() + 1), hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
@@ -207,6 +211,8 @@ int snect_server_destroy(snect_server* s)
     for (auto& sl : s->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.k0) (void)hipEventDestroy(sl.k0);
+        if (sl.k1) (void)hipEventDestroy(sl.k1);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.d_part) (void)hipFree(sl.d_part);
         if (sl.d_scores) (void)hipFree(sl.d_scores);
@@ -222,8 +228,12 @@ int snect_server_destroy(snect_server* s)
     return SNECT_OK;
 }
 
-int snect_server_submit(snect_server* s, int64_t nnz, const int32_t* j, const int32_t* k, const float* x,
-                        int64_t* ticket)
+}  // extern "C"
+
+// Admission of one request; `timed` brackets its kernels with the slot's
+// timing events.
+static int submit_request(snect_server* s, int64_t nnz, const int32_t* j, const int32_t* k, const float* x,
+                          int64_t* ticket, bool timed)
 {
     if (!s || !ticket || nnz < 0 || nnz >= (int64_t(1) << 31) || (nnz > 0 && (!j || !k || !x)))
         return srv_err(s, SNECT_E_ARG, "bad request arguments");
@@ -295,11 +305,13 @@ int snect_server_submit(snect_server* s, int64_t nnz, const int32_t* j, const in
     char* dbase = s->d_pool + off;
     hipError_t e = hipSuccess;
     if (nnz > 0) e = hipMemcpyAsync(dbase, sl.h_in, 3 * bj, hipMemcpyHostToDevice, sl.stream);
+    if (e == hipSuccess && timed) e = hipEventRecord(sl.k0, sl.stream);
     if (e == hipSuccess)
         e = launch_serve_request(reinterpret_cast<const int32_t*>(dbase), reinterpret_cast<const int32_t*>(dbase + bj),
                                  reinterpret_cast<const float*>(dbase + 2 * bj), (int)nnz, s->d_W, s->I2, s->J1,
                                  s->cfg.lambda, s->cfg.pg_iters, s->d_At, s->d_anrm, s->I1, s->cfg.topk, sl.d_part,
                                  sl.d_scores, sl.d_out, reinterpret_cast<int*>(sl.d_out + s->out_len()), sl.stream);
+    if (e == hipSuccess && timed) e = hipEventRecord(sl.k1, sl.stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(sl.h_out, sl.d_out, sizeof(double) * (s->out_len() + 1), hipMemcpyDeviceToHost, sl.stream);
     if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
@@ -315,6 +327,14 @@ int snect_server_submit(snect_server* s, int64_t nnz, const int32_t* j, const in
     s->where[sl.ticket] = free_slot;
     *ticket = sl.ticket;
     return SNECT_OK;
+}
+
+extern "C" {
+
+int snect_server_submit(snect_server* s, int64_t nnz, const int32_t* j, const int32_t* k, const float* x,
+                        int64_t* ticket)
+{
+    return submit_request(s, nnz, j, k, x, ticket, false);
 }
 
 int snect_server_poll(snect_server* s, int64_t ticket, double* u, int32_t* idx, double* score)
@@ -341,19 +361,35 @@ int snect_server_poll(snect_server* s, int64_t ticket, double* u, int32_t* idx, 
 
 int snect_server_replay(snect_server* s, int64_t nreq, const double* arrival_s, const int64_t* offsets,
                         const int32_t* j, const int32_t* k, const float* x, double* latency_s, double* u,
-                        int32_t* idx, double* score, int32_t* status, double* wall_s)
+                        int32_t* idx, double* score, int32_t* status, double* wall_s, double* gpu_busy_s)
 {
     if (!s || nreq < 0 || !arrival_s || !offsets || !latency_s) return SNECT_E_ARG;
     const int J1 = s->J1, K = s->cfg.topk;
     std::vector<int64_t> tick(nreq, -1);
     std::vector<int64_t> inflight;
     int64_t next = 0, done = 0;
+    // device-busy time: the union of the requests' kernel windows, each read
+    // from its slot's timing events relative to a reference event recorded
+    // (and completed) before the first admission
+    const bool timed = gpu_busy_s != nullptr;
+    hipEvent_t ref = nullptr;
+    std::vector<std::pair<float, float>> win;
+    if (timed) {
+        (void)hipSetDevice(s->device);
+        if (hipEventCreate(&ref) != hipSuccess || hipEventRecord(ref, s->slots[0].stream) != hipSuccess ||
+            hipEventSynchronize(ref) != hipSuccess) {
+            if (ref) (void)hipEventDestroy(ref);
+            return srv_err(s, SNECT_E_HIP, "replay timing event");
+        }
+        win.reserve((size_t)nreq);
+    }
     const double t0 = now_s();
     while (done < nreq) {
         // completions first, so that a finished request is timed before the
         // host prepares the next ones
         for (size_t t = 0; t < inflight.size();) {
             const int64_t r = inflight[t];
+            const int si = s->where.count(tick[r]) ? s->where[tick[r]] : -1;
             const int rc = snect_server_poll(s, tick[r], u ? u + r * J1 : nullptr, idx ? idx + r * K : nullptr,
                                              score ? score + r * K : nullptr);
             if (rc == 0) {
@@ -362,6 +398,10 @@ int snect_server_replay(snect_server* s, int64_t nreq, const double* arrival_s, 
             }
             latency_s[r] = (now_s() - t0) - arrival_s[r];
             if (status) status[r] = rc == 1 ? SNECT_OK : rc;
+            float a = 0.f, b = 0.f;
+            if (timed && si >= 0 && hipEventElapsedTime(&a, ref, s->slots[si].k0) == hipSuccess &&
+                hipEventElapsedTime(&b, ref, s->slots[si].k1) == hipSuccess)
+                win.emplace_back(a, b);
             ++done;
             inflight[t] = inflight.back();
             inflight.pop_back();
@@ -371,7 +411,7 @@ int snect_server_replay(snect_server* s, int64_t nreq, const double* arrival_s, 
         while (next < nreq && arrival_s[next] <= now) {
             const int64_t a = offsets[next], n = offsets[next + 1] - a;
             int64_t tk = -1;
-            const int rc = snect_server_submit(s, n, j + a, k + a, x + a, &tk);
+            const int rc = submit_request(s, n, j + a, k + a, x + a, &tk, timed);
             if (rc == SNECT_E_BUSY) break;  // retry after completions
             if (rc != SNECT_OK) {           // a malformed request fails alone
                 latency_s[next] = (now_s() - t0) - arrival_s[next];
@@ -386,6 +426,23 @@ int snect_server_replay(snect_server* s, int64_t nreq, const double* arrival_s, 
         }
     }
     if (wall_s) *wall_s = now_s() - t0;
+    if (timed) {
+        (void)hipGetLastError();
+        (void)hipEventDestroy(ref);
+        std::sort(win.begin(), win.end());
+        double busy_ms = 0.0, lo = 0.0, hi = -1.0;
+        for (const auto& w : win) {
+            if (w.first > hi) {
+                if (hi > lo) busy_ms += hi - lo;
+                lo = w.first;
+                hi = w.second;
+            } else {
+                hi = std::max<double>(hi, w.second);
+            }
+        }
+        if (hi > lo) busy_ms += hi - lo;
+        *gpu_busy_s = 1e-3 * busy_ms;
+    }
     return SNECT_OK;
 }
 
