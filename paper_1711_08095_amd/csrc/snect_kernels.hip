@@ -509,6 +509,45 @@ __device__ inline float seg_scan(float v, int lane, int head)
     return v;
 }
 
+// seg_scan of N columns at once, step by step (the same additions in the
+// same order for each column as seg_scan; independent steps interleave).
+template <int N>
+__device__ inline void seg_scan_n(float (&v)[N], int lane, int head)
+{
+    const int r = lane & 15, row = lane >> 4;
+    float t[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) t[q] = dpp_move<kDppRowShr + 1, 0xf>(v[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+        if (r >= 1 && lane - 1 >= head) v[q] += t[q];
+#pragma unroll
+    for (int q = 0; q < N; ++q) t[q] = dpp_move<kDppRowShr + 2, 0xf>(v[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+        if (r >= 2 && lane - 2 >= head) v[q] += t[q];
+#pragma unroll
+    for (int q = 0; q < N; ++q) t[q] = dpp_move<kDppRowShr + 4, 0xf>(v[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+        if (r >= 4 && lane - 4 >= head) v[q] += t[q];
+#pragma unroll
+    for (int q = 0; q < N; ++q) t[q] = dpp_move<kDppRowShr + 8, 0xf>(v[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+        if (r >= 8 && lane - 8 >= head) v[q] += t[q];
+#pragma unroll
+    for (int q = 0; q < N; ++q) t[q] = dpp_move<kDppRowBcast15, 0xf>(v[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+        if ((row & 1) && head <= 16 * row - 1) v[q] += t[q];
+#pragma unroll
+    for (int q = 0; q < N; ++q) t[q] = dpp_move<kDppRowBcast31, 0xf>(v[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+        if (row >= 2 && head <= 31) v[q] += t[q];
+}
+
 // Lanes 0..lane as a bit mask (computed once per thread).
 __device__ inline unsigned long long lanes_upto(int lane) { return lane == 63 ? ~0ull : (2ull << lane) - 1ull; }
 
@@ -681,6 +720,9 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
     // rows (patient tasks) or columns (gene tasks) of H_k stay in registers
     // while consecutive tiles share k; larger ones read H_k and H_k^T from LDS
     constexpr bool kHreg = SP::kSplit && JP <= 12;
+    // small cores request every LDS value of a task before its first
+    // product; larger ones keep fewer values in flight
+    constexpr bool kHoist = kHreg;
     float hh[kHreg ? QH : 1][kHreg ? JP : 1];
     int tl = t0;
     while (tl < t1) {
@@ -731,11 +773,24 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
         //    (w1 = H_k b), a_i for gene tasks (w2 = H_k^T a)
         const float* H = L.Hs + k * JP * JP;
         float w1q[QI], aq[QI], bq[QI], w2q[QJ];
+        float rai = 0.f;  // regularisation weight of the nonzero's patient row
         if (hi) {
             float xp = 0.f;  // this wavefront's share of x~: its columns, ascending
-            float bv[JP];
+            // every LDS value of the task is requested before the first
+            // product (columns past the core read column JP - 1, unused;
+            // lanes past the tile's end read row 0, unused)
+            float bv[JP], ar[QI], br[QI];
 #pragma unroll
             for (int c = 0; c < JP; ++c) bv[c] = L.Bb[jl * RS + c];
+            if constexpr (kHoist) {
+#pragma unroll
+                for (int qq = 0; qq < QI; ++qq) {
+                    const int c = ri + NI * qq, cc = c < JP ? c : JP - 1;
+                    ar[qq] = L.Ab[ilc * RS + cc];
+                    br[qq] = L.Bb[jl * RS + cc];
+                }
+                rai = L.rA[ilc];
+            }
 #pragma unroll
             for (int qq = 0; qq < QI; ++qq) {
                 const int c = ri + NI * qq;
@@ -754,8 +809,13 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
                             for (int r = 0; r < 4; ++r) t = fmaf(h4[r], bv[4 * y4 + r], t);
                         }
                     }
-                    ac = act ? L.Ab[ilc * RS + c] : 0.f;
-                    bc = act ? L.Bb[jl * RS + c] : 0.f;
+                    if constexpr (kHoist) {
+                        ac = act ? ar[qq] : 0.f;
+                        bc = act ? br[qq] : 0.f;
+                    } else {
+                        ac = act ? L.Ab[ilc * RS + c] : 0.f;
+                        bc = act ? L.Bb[jl * RS + c] : 0.f;
+                    }
                     xp = qq == 0 ? ac * t : fmaf(ac, t, xp);
                 }
                 w1q[qq] = t;
@@ -774,23 +834,30 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
         bool jlast = false;
         float jcr = 0.f, bp[QJ];
         if (hj) {
+            float av[JP];
+            if constexpr (kHoist) {
+#pragma unroll
+                for (int c = 0; c < JP; ++c) av[c] = L.Ab[ilc * RS + c];
+            }
             sj = __builtin_amdgcn_ds_permute(jr << 2, act ? jl : -1);
             const bool sact = lane < n;
-            const int sj_up = dpp_move_i<kDppWaveShr1>(sj), sj_dn = dpp_move_i<kDppWaveShl1>(sj);
-            const bool jfirst = sact && (lane == 0 || sj_up != sj);
-            jlast = sact && (lane == 63 || sj_dn != sj);
-            jhead = run_head(__ballot(jfirst), upto);
-            jcr = sact ? (float)(lane - jhead + 1) * L.rB[sj] : 0.f;
+            const int sjc = sact ? sj : 0;
+            const float rbj = L.rB[sjc];
 #pragma unroll
             for (int qq = 0; qq < QJ; ++qq) {
-                const int c = rj + NJ * qq;
-                bp[qq] = (sact && c < JP) ? L.Bb[sj * RS + c] : 0.f;
+                const int c = rj + NJ * qq, cc = c < JP ? c : JP - 1;
+                bp[qq] = L.Bb[sjc * RS + cc];
             }
-        }
-        if (hj) {
-            float av[JP];
+            if constexpr (!kHoist) {
+                // the slot work first (fewer values live across the products)
+                const int sj_up = dpp_move_i<kDppWaveShr1>(sj), sj_dn = dpp_move_i<kDppWaveShl1>(sj);
+                const bool jfirst = sact && (lane == 0 || sj_up != sj);
+                jlast = sact && (lane == 63 || sj_dn != sj);
+                jhead = run_head(__ballot(jfirst), upto);
+                jcr = sact ? (float)(lane - jhead + 1) * rbj : 0.f;
 #pragma unroll
-            for (int c = 0; c < JP; ++c) av[c] = L.Ab[ilc * RS + c];
+                for (int c = 0; c < JP; ++c) av[c] = L.Ab[ilc * RS + c];
+            }
 #pragma unroll
             for (int qq = 0; qq < QJ; ++qq) {
                 const int c = rj + NJ * qq;
@@ -812,6 +879,18 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
                 }
                 w2q[qq] = t;
             }
+            if constexpr (kHoist) {
+                const int sj_up = dpp_move_i<kDppWaveShr1>(sj), sj_dn = dpp_move_i<kDppWaveShl1>(sj);
+                const bool jfirst = sact && (lane == 0 || sj_up != sj);
+                jlast = sact && (lane == 63 || sj_dn != sj);
+                jhead = run_head(__ballot(jfirst), upto);
+                jcr = sact ? (float)(lane - jhead + 1) * rbj : 0.f;
+            }
+#pragma unroll
+            for (int qq = 0; qq < QJ; ++qq) {
+                const int c = rj + NJ * qq;
+                bp[qq] = (sact && c < JP) ? bp[qq] : 0.f;
+            }
         }
         // patient runs (the tile is sorted by patient): heads and the
         // regularisation weight of each run (patient tasks only)
@@ -823,7 +902,8 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
             const bool ifirst = act && (lane == 0 || il_up != il);
             ilast = act && (lane == 63 || il_dn != il);
             ihead = run_head(__ballot(ifirst), upto);
-            icr = act ? (float)(lane - ihead + 1) * L.rA[ilc] : 0.f;
+            if constexpr (!kHoist) rai = L.rA[ilc];
+            icr = act ? (float)(lane - ihead + 1) * rai : 0.f;
         }
         __syncthreads();
         if (pend >= 0) {
@@ -837,31 +917,75 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
 
         // 2. residual (x~: the patient-task wavefronts' shares in wavefront
         // order); the tasks' run sums
-        float xt = L.xtp[lane];
+        float xt;
+        if constexpr (kHoist) {
+            float xs[NI];
 #pragma unroll
-        for (int ww = 1; ww < NI; ++ww) xt += L.xtp[ww * kTileMax + lane];
+            for (int ww = 0; ww < NI; ++ww) xs[ww] = L.xtp[ww * kTileMax + lane];
+            xt = xs[0];
+#pragma unroll
+            for (int ww = 1; ww < NI; ++ww) xt += xs[ww];
+        } else {
+            xt = L.xtp[lane];
+#pragma unroll
+            for (int ww = 1; ww < NI; ++ww) xt += L.xtp[ww * kTileMax + lane];
+        }
         const float e = act ? x - xt : 0.f;
         if (hi) {
+            if constexpr (kHoist) {
+                // the columns' scans interleaved
+                float v[QI];
 #pragma unroll
-            for (int qq = 0; qq < QI; ++qq) {
-                const int c = ri + NI * qq;
-                if (c < JP) {
-                    L.As[c * kTS + lane] = aq[qq];
-                    L.Es[c * kTS + lane] = e * bq[qq];
-                    const float v = seg_scan(e * w1q[qq], lane, ihead);
-                    if (ilast) L.Ab[il * RS + c] = fmaf(a.lr, v - icr * aq[qq], aq[qq]);
+                for (int qq = 0; qq < QI; ++qq) {
+                    const int c = ri + NI * qq;
+                    if (c < JP) {
+                        L.As[c * kTS + lane] = aq[qq];
+                        L.Es[c * kTS + lane] = e * bq[qq];
+                    }
+                    v[qq] = e * w1q[qq];
+                }
+                seg_scan_n<QI>(v, lane, ihead);
+#pragma unroll
+                for (int qq = 0; qq < QI; ++qq) {
+                    const int c = ri + NI * qq;
+                    if (c < JP && ilast) L.Ab[il * RS + c] = fmaf(a.lr, v[qq] - icr * aq[qq], aq[qq]);
+                }
+            } else {
+#pragma unroll
+                for (int qq = 0; qq < QI; ++qq) {
+                    const int c = ri + NI * qq;
+                    if (c < JP) {
+                        L.As[c * kTS + lane] = aq[qq];
+                        L.Es[c * kTS + lane] = e * bq[qq];
+                        const float v = seg_scan(e * w1q[qq], lane, ihead);
+                        if (ilast) L.Ab[il * RS + c] = fmaf(a.lr, v - icr * aq[qq], aq[qq]);
+                    }
                 }
             }
         }
         if (hj) {
             // e w2 of the wavefront's columns pushed to slot order
+            if constexpr (kHoist) {
+                float v[QJ];
 #pragma unroll
-            for (int qq = 0; qq < QJ; ++qq) {
-                const int c = rj + NJ * qq;
-                if (c < JP) {
-                    const float ws = __int_as_float(__builtin_amdgcn_ds_permute(jr << 2, __float_as_int(e * w2q[qq])));
-                    const float v = seg_scan(ws, lane, jhead);
-                    if (jlast) L.Bb[sj * RS + c] = fmaf(a.lr, v - jcr * bp[qq], bp[qq]);
+                for (int qq = 0; qq < QJ; ++qq)
+                    v[qq] = __int_as_float(__builtin_amdgcn_ds_permute(jr << 2, __float_as_int(e * w2q[qq])));
+                seg_scan_n<QJ>(v, lane, jhead);
+#pragma unroll
+                for (int qq = 0; qq < QJ; ++qq) {
+                    const int c = rj + NJ * qq;
+                    if (c < JP && jlast) L.Bb[sj * RS + c] = fmaf(a.lr, v[qq] - jcr * bp[qq], bp[qq]);
+                }
+            } else {
+#pragma unroll
+                for (int qq = 0; qq < QJ; ++qq) {
+                    const int c = rj + NJ * qq;
+                    if (c < JP) {
+                        const float ws =
+                            __int_as_float(__builtin_amdgcn_ds_permute(jr << 2, __float_as_int(e * w2q[qq])));
+                        const float v = seg_scan(ws, lane, jhead);
+                        if (jlast) L.Bb[sj * RS + c] = fmaf(a.lr, v - jcr * bp[qq], bp[qq]);
+                    }
                 }
             }
         }
