@@ -731,12 +731,13 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
         // (the first chunk may already be there: pre_cend tiles)
         const int cend = (pre_cend > 0 && tl == t0) ? pre_cend : load_chunk(a, L, tl, t1, tid, NT);
         const int z0 = L.tco[0];
-        // each tile's records are read from LDS during the previous tile
-        uint2 wv_next = lane < L.tco[1] - z0 ? L.rec[lane] : make_uint2(0u, 0u);
+        // each tile's records, size and platform are read from LDS during
+        // the previous tile
+        int n_next = L.tco[1] - z0, k_next = L.tck[0];
+        uint2 wv_next = lane < n_next ? L.rec[lane] : make_uint2(0u, 0u);
         for (int u = 0; u < cend; ++u, ++tl) {
-        const int off = L.tco[u];
-        const int n = L.tco[u + 1] - off;
-        const int k = L.tck[u];
+        const int n = n_next;
+        const int k = k_next;
         const uint2 wv = wv_next;
         // S of the previous tile (its platform is curk); staged operands of
         // nonzeros past the tile's end are zero
@@ -911,8 +912,10 @@ __device__ void block_tiles(const StratArgs& a, int t0, int t1, const TileLds& L
             pend = -1;
         }
         if (u + 1 < cend) {
-            const int o2 = L.tco[u + 1], n2 = L.tco[u + 2] - o2;
-            wv_next = lane < n2 ? L.rec[o2 - z0 + lane] : make_uint2(0u, 0u);
+            const int o2 = L.tco[u + 1];
+            n_next = L.tco[u + 2] - o2;
+            k_next = L.tck[u + 1];
+            wv_next = lane < n_next ? L.rec[o2 - z0 + lane] : make_uint2(0u, 0u);
         }
 
         // 2. residual (x~: the patient-task wavefronts' shares in wavefront
@@ -1081,8 +1084,44 @@ __device__ void block_tiles_bf(const StratArgs& a, int t0, int t1, const TileLds
         const uint2 wv = act ? rec[lane] : make_uint2(0u, 0u);
         const uint32_t wd = wv.x;
         const int il = act ? (int)(wd & mask_i) : -1;
+        const int ilc = act ? il : 0;
         const int jl = act ? (int)((wd >> sh_j) & mask_j) : 0;
         const int jrank = (int)(wd >> sh_r);
+
+        // the values of the wavefront's own run task, requested first: the
+        // patient rows' regularisation weights and the a, b values of its
+        // columns (patient tasks); the slot order, the gene rows' weights
+        // and b values (gene tasks).  Columns past the core read column
+        // JP - 1 and lanes past the tile's end row 0: neither value is used.
+        float aq[QI], bq[QI], bp[QJ], rai = 0.f, rbj = 0.f;
+        int sj = -1;
+        if (hi) {
+            rai = L.rA[ilc];
+#pragma unroll
+            for (int qq = 0; qq < QI; ++qq) {
+                const int c = ri + NI * qq, cc = c < JP ? c : JP - 1;
+                aq[qq] = L.Ab[ilc * RS + cc];
+                bq[qq] = L.Bb[jl * RS + cc];
+            }
+        } else {
+#pragma unroll
+            for (int qq = 0; qq < QI; ++qq) aq[qq] = bq[qq] = 0.f;
+        }
+        if (hj) {
+            // slot s learns its gene row from the lane that holds it
+            // (inactive lanes push to their own slot)
+            sj = __builtin_amdgcn_ds_permute((act ? jrank : lane) << 2, act ? jl : -1);
+            const int sjc = act ? sj : 0;
+            rbj = L.rB[sjc];
+#pragma unroll
+            for (int qq = 0; qq < QJ; ++qq) {
+                const int c = rj + NJ * qq, cc = c < JP ? c : JP - 1;
+                bp[qq] = L.Bb[sjc * RS + cc];
+            }
+        } else {
+#pragma unroll
+            for (int qq = 0; qq < QJ; ++qq) bp[qq] = 0.f;
+        }
 
         // 1. W1 with x~ and e, W2, for nonzeros 16 rb .. 16 rb + 15
         if (do1 || do2) {
@@ -1101,6 +1140,14 @@ __device__ void block_tiles_bf(const StratArgs& a, int t0, int t1, const TileLds
                     const int tr = 16 * rb + 4 * g + r;
                     ilr[r] = tr < n ? (int)(rec[tr].x & mask_i) : 0;
                 }
+                // the a values of x~ requested before the products
+                float ax[NB][4];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const int c = nb * 16 + m, cc = c < JP ? c : JP - 1;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) ax[nb][r] = L.Ab[ilr[r] * RS + cc];
+                }
                 float xp[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
@@ -1109,7 +1156,7 @@ __device__ void block_tiles_bf(const StratArgs& a, int t0, int t1, const TileLds
                     *reinterpret_cast<floatx4*>(L.sW1 + c * kTW + 16 * rb + 4 * g) = o1;
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        if (c < JP) xp[r] = fmaf(L.Ab[ilr[r] * RS + c], o1[r], xp[r]);
+                        if (c < JP) xp[r] = fmaf(ax[nb][r], o1[r], xp[r]);
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) xp[r] = row_sum16(xp[r]);
@@ -1146,33 +1193,39 @@ __device__ void block_tiles_bf(const StratArgs& a, int t0, int t1, const TileLds
                 }
             }
         }
-        // patient runs: heads and regularisation weights (records only)
-        const int il_up = dpp_move_i<kDppWaveShr1>(il), il_dn = dpp_move_i<kDppWaveShl1>(il);
-        const bool ifirst = act && (lane == 0 || il_up != il);
-        const bool ilast = act && (lane == 63 || il_dn != il);
-        const int ihead = run_head(__ballot(ifirst), upto);
-        const float icr = act ? (float)(lane - ihead + 1) * L.rA[il] : 0.f;
-        float aq[QI], bq[QI];
+        // patient runs (patient tasks): heads and regularisation weights
+        bool ilast = false;
+        int ihead = 0;
+        float icr = 0.f;
+        if (hi) {
+            const int il_up = dpp_move_i<kDppWaveShr1>(il), il_dn = dpp_move_i<kDppWaveShl1>(il);
+            const bool ifirst = act && (lane == 0 || il_up != il);
+            ilast = act && (lane == 63 || il_dn != il);
+            ihead = run_head(__ballot(ifirst), upto);
+            icr = act ? (float)(lane - ihead + 1) * rai : 0.f;
 #pragma unroll
-        for (int qq = 0; qq < QI; ++qq) {
-            const int c = ri + NI * qq;
-            aq[qq] = (hi && c < JP && act) ? L.Ab[il * RS + c] : 0.f;
-            bq[qq] = (hi && c < JP && act) ? L.Bb[jl * RS + c] : 0.f;
+            for (int qq = 0; qq < QI; ++qq) {
+                const int c = ri + NI * qq;
+                aq[qq] = (c < JP && act) ? aq[qq] : 0.f;
+                bq[qq] = (c < JP && act) ? bq[qq] : 0.f;
+            }
         }
-        // gene runs in slot order: slot s learns its gene row from the lane
-        // that holds it (inactive lanes push to their own slot), then the run
-        // heads, the regularisation weights and the rows' values before the tile
-        const int sj = __builtin_amdgcn_ds_permute((act ? jrank : lane) << 2, act ? jl : -1);
-        const int sj_up = dpp_move_i<kDppWaveShr1>(sj), sj_dn = dpp_move_i<kDppWaveShl1>(sj);
-        const bool jfirst = act && (lane == 0 || sj_up != sj);
-        const bool jlast = act && (lane == 63 || sj_dn != sj);
-        const int jhead = run_head(__ballot(jfirst), upto);
-        const float jcr = act ? (float)(lane - jhead + 1) * L.rB[sj] : 0.f;
-        float bp[QJ];
+        // gene runs in slot order (gene tasks): heads, regularisation
+        // weights and the rows' values before the tile
+        bool jlast = false;
+        int jhead = 0;
+        float jcr = 0.f;
+        if (hj) {
+            const int sj_up = dpp_move_i<kDppWaveShr1>(sj), sj_dn = dpp_move_i<kDppWaveShl1>(sj);
+            const bool jfirst = act && (lane == 0 || sj_up != sj);
+            jlast = act && (lane == 63 || sj_dn != sj);
+            jhead = run_head(__ballot(jfirst), upto);
+            jcr = act ? (float)(lane - jhead + 1) * rbj : 0.f;
 #pragma unroll
-        for (int qq = 0; qq < QJ; ++qq) {
-            const int c = rj + NJ * qq;
-            bp[qq] = (hj && c < JP && act) ? L.Bb[sj * RS + c] : 0.f;
+            for (int qq = 0; qq < QJ; ++qq) {
+                const int c = rj + NJ * qq;
+                bp[qq] = (c < JP && act) ? bp[qq] : 0.f;
+            }
         }
         __syncthreads();
         if (pend >= 0) {
@@ -1180,29 +1233,45 @@ __device__ void block_tiles_bf(const StratArgs& a, int t0, int t1, const TileLds
             pend = -1;
         }
 
+
         // 2. BF16 S operands; fixed-order run sums; owned columns
         const float e = act ? eT[lane] : 0.f;
         const float es = act ? eS[lane] : 0.f;
         if (hi) {
+            // the columns' e w1 read at once, their scans interleaved
+            float v[QI];
+#pragma unroll
+            for (int qq = 0; qq < QI; ++qq) {
+                const int c = ri + NI * qq, cc = c < JP ? c : JP - 1;
+                v[qq] = e * L.sW1[cc * kTW + lane];
+            }
 #pragma unroll
             for (int qq = 0; qq < QI; ++qq) {
                 const int c = ri + NI * qq;
                 if (c < JP) {
                     L.A16[c * kTB + lane] = (__bf16)aq[qq];
                     L.E16[c * kTB + lane] = (__bf16)(e * bq[qq]);
-                    const float v = seg_scan(e * L.sW1[c * kTW + lane], lane, ihead);
-                    if (ilast) L.Ab[il * RS + c] = fmaf(a.lr, v - icr * aq[qq], aq[qq]);
                 }
+            }
+            seg_scan_n<QI>(v, lane, ihead);
+#pragma unroll
+            for (int qq = 0; qq < QI; ++qq) {
+                const int c = ri + NI * qq;
+                if (c < JP && ilast) L.Ab[il * RS + c] = fmaf(a.lr, v[qq] - icr * aq[qq], aq[qq]);
             }
         }
         if (hj) {
+            float v[QJ];
+#pragma unroll
+            for (int qq = 0; qq < QJ; ++qq) {
+                const int c = rj + NJ * qq, cc = c < JP ? c : JP - 1;
+                v[qq] = es * L.sW2[cc * kTW + lane];
+            }
+            seg_scan_n<QJ>(v, lane, jhead);
 #pragma unroll
             for (int qq = 0; qq < QJ; ++qq) {
                 const int c = rj + NJ * qq;
-                if (c < JP) {
-                    const float v = seg_scan(es * L.sW2[c * kTW + lane], lane, jhead);
-                    if (jlast) L.Bb[sj * RS + c] = fmaf(a.lr, v - jcr * bp[qq], bp[qq]);
-                }
+                if (c < JP && jlast) L.Bb[sj * RS + c] = fmaf(a.lr, v[qq] - jcr * bp[qq], bp[qq]);
             }
         }
         prev_n = n;
