@@ -37,6 +37,9 @@ using namespace snect;
 namespace {
 
 constexpr size_t kAlign = 256;
+// Pinned request staging of a slot, allocated when the server is created
+// (requests of up to about 87,000 cells fit; larger ones grow it).
+constexpr size_t kStagingStart = size_t(1) << 20;
 
 size_t align_up(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
 
@@ -192,11 +195,23 @@ int snect_server_create(snect_ctx* ctx, int32_t I1, int32_t I2, int32_t I3, int3
             hipMalloc((void**)&sl.d_part, sizeof(float) * kServeMaxParts * ne) != hipSuccess ||
             hipMalloc((void**)&sl.d_scores, sizeof(float) * (size_t)I1) != hipSuccess ||
             hipMalloc((void**)&sl.d_out, sizeof(double) * (s->out_len() + 1)) != hipSuccess ||
-            hipHostMalloc((void**)&sl.h_out, sizeof(double) * (s->out_len() + 1), hipHostMallocDefault) != hipSuccess) {
+            hipHostMalloc((void**)&sl.h_out, sizeof(double) * (s->out_len() + 1), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&sl.h_in, kStagingStart, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             return fail(SNECT_E_OOM, "server slot allocation failed");
         }
+        sl.h_in_cap = kStagingStart;
     }
+    // the first command on a stream binds it to a hardware queue, which is
+    // slow: done here for every slot rather than on a request's path
+    for (auto& sl : s->slots) {
+        std::memset(sl.h_out, 0, sizeof(double) * (s->out_len() + 1));
+        if (hipMemcpyAsync(sl.d_out, sl.h_out, sizeof(double) * (s->out_len() + 1), hipMemcpyHostToDevice,
+                           sl.stream) != hipSuccess)
+            return fail(SNECT_E_HIP, "server slot set-up failed");
+    }
+    for (auto& sl : s->slots)
+        if (hipStreamSynchronize(sl.stream) != hipSuccess) return fail(SNECT_E_HIP, "server slot set-up failed");
     ctx->live_problems++;
     s->counted = true;
     *out = s;
@@ -249,14 +264,18 @@ static int submit_request(snect_server* s, int64_t nnz, const int32_t* j, const 
     Slot& sl = s->slots[free_slot];
     (void)hipSetDevice(s->device);
     if (sl.h_in_cap < bytes) {
+        // grows to the next power of two (pinned allocations and frees are
+        // slow and can wait for the device, so they are kept rare)
+        size_t cap = kStagingStart;
+        while (cap < bytes) cap *= 2;
         if (sl.h_in) (void)hipHostFree(sl.h_in);
         sl.h_in = nullptr;
         sl.h_in_cap = 0;
-        if (hipHostMalloc((void**)&sl.h_in, bytes, hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc((void**)&sl.h_in, cap, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             return srv_err(s, SNECT_E_OOM, "pinned staging allocation failed");
         }
-        sl.h_in_cap = bytes;
+        sl.h_in_cap = cap;
     }
     // copy the cells to the slot's pinned staging and check them in the same
     // branch-free pass, four cells per step.  The staging is written with
