@@ -11,6 +11,7 @@ reported separately.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import glob
 import hashlib
 import json
 import os
@@ -73,44 +74,74 @@ def parse():
     return ap.parse_args()
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "strata_persistent_pancan_25M_hbm_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1711_08095_amd", "csrc", "snect_kernels.hip")
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when that
-    summary was taken on another kernel or on other kernel source."""
+def workload_key(nnz, ranks, P, T):
+    return f"pancan-shaped {nnz} nonzeros, core {ranks[0]}x{ranks[1]}x{ranks[2]}, P={P}, T={T}"
+
+
+def profile_values(suffix: str, prefix: str, kernel: str, workload: str):
+    """The `<prefix>_*: value` lines of the committed rocprofv3 summary
+    (profiles/*<suffix>) taken on `kernel`, `workload` and the current kernel
+    source, or None when there is none."""
     try:
-        text = open(COUNTERS).read()
         sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     except OSError:
         return None
-    vals = dict(re.findall(r"^\s*(traffic_kernel|traffic_bytes_per_launch|kernel_source_sha256):\s*(.+?)\s*$",
-                           text, re.M))
-    if vals.get("kernel_source_sha256") != sha or vals.get("traffic_kernel") != kernel:
-        return None
-    return float(vals["traffic_bytes_per_launch"])
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*" + suffix))):
+        vals = dict(re.findall(r"^\s*(%s_\w+|kernel_source_sha256):\s*(.+?)\s*$" % prefix, open(path).read(),
+                               re.M))
+        if (vals.get("kernel_source_sha256") == sha and vals.get(f"{prefix}_kernel") == kernel
+                and vals.get(f"{prefix}_workload") == workload):
+            return vals
+    return None
 
 
-MFMA_COUNTERS = os.path.join(ROOT, "profiles", "strata_persistent_pancan_25M_mfma_counters.md")
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    v = profile_values("_hbm_counters.md", "traffic", kernel, workload)
+    return None if v is None else float(v["traffic_bytes_per_launch"])
 
 
-def measured_mfma(kernel: str):
-    """Matrix-core flops per launch and busy-cycle utilisation (percent) of
-    `kernel` from the committed rocprofv3 summary (MfmaFlopsF32, MfmaUtil),
-    or None when that summary was taken on another kernel or on other kernel
-    source."""
-    try:
-        text = open(MFMA_COUNTERS).read()
-        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    except OSError:
-        return None
-    vals = dict(re.findall(r"^\s*(mfma_kernel|mfma_flops_per_launch|mfma_util_pct|kernel_source_sha256):\s*(.+?)\s*$",
-                           text, re.M))
-    if vals.get("kernel_source_sha256") != sha or vals.get("mfma_kernel") != kernel:
-        return None
-    return float(vals["mfma_flops_per_launch"]), float(vals["mfma_util_pct"])
+def measured_mfma(kernel: str, workload: str):
+    """Matrix-core flops per launch and busy-cycle utilisation (percent)."""
+    v = profile_values("_mfma_counters.md", "mfma", kernel, workload)
+    return None if v is None else (float(v["mfma_flops_per_launch"]), float(v["mfma_util_pct"]))
+
+
+def stratum_roofline(kernel, workload, bf, persistent, nnz, dims, ranks, P, avg_launch_s):
+    """Roofline object of the stratum kernel: algorithmic bytes per launch
+    (8 B per nonzero record streamed once; the moving patient rows read and
+    written once per stratum; the stationary gene rows once per launch) over
+    the measured average launch time, against the HBM peak; with the
+    per-nonzero flops against the FP32 vector peak and the counter-measured
+    traffic and matrix-core work when a summary for this kernel exists."""
+    J1, J2, J3 = ranks
+    I1, I2, I3 = dims
+    strata_per_launch = P if persistent else 1
+    nnz_per_launch = nnz * strata_per_launch / P
+    bytes_per_launch = 8.0 * nnz_per_launch + strata_per_launch * 8.0 * I1 * J1 + 8.0 * I2 * J2
+    flops_per_nnz = 6 * J1 * J2 + 4 * (J1 + J2)
+    ok = avg_launch_s > 0
+    achieved = bytes_per_launch / avg_launch_s / 1e9 if ok else 0.0
+    tflops = flops_per_nnz * nnz_per_launch / avg_launch_s / 1e12 if ok else 0.0
+    mfma = measured_mfma(kernel, workload)
+    mpeak = BF16_MFMA_PEAK_TFLOPS if bf else FP32_MFMA_PEAK_TFLOPS
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kernel, workload),
+            "kernel": kernel, "avg_launch_us": avg_launch_s * 1e6, "bytes_per_launch": bytes_per_launch,
+            "alu_tflops": tflops, "alu_frac": tflops / FP32_VECTOR_PEAK_TFLOPS,
+            # counter-measured matrix-core work (padded tiles) over the live launch time
+            "mfma": None if mfma is None or not ok else {
+                "flops_per_launch": mfma[0], "tflops": mfma[0] / avg_launch_s / 1e12, "peak": mpeak,
+                "frac": mfma[0] / avg_launch_s / 1e12 / mpeak, "busy_util_pct": mfma[1]}}
+
+
+def stratum_kernel(jp_ranks, bf, waves, persistent):
+    jp = min(j for j in (2, 4, 5, 8, 10, 12, 16, 20, 24, 32) if j >= max(jp_ranks[0], jp_ranks[1]))
+    return (f"strata_persistent<{jp}, {'true' if bf else 'false'}, {waves or 8}>" if persistent
+            else f"block_step<{jp}>")
 
 
 def write_maps(path: str):
@@ -197,29 +228,13 @@ def main():
 
     # roofline of the dominant kernel: the stratum kernel (one launch per
     # epoch when persistent, one per stratum otherwise)
-    J1, J2, J3 = ranks
-    I1, I2, I3 = dims
     P = args.strata
-    launches = max(tm["kernel_launches"], 1)
-    avg_launch_s = tm["kernel_ms"] * 1e-3 / launches
+    avg_launch_s = tm["kernel_ms"] * 1e-3 / max(tm["kernel_launches"], 1)
     persistent = chosen == sn.PATH_PERSISTENT
-    strata_per_launch = P if persistent else 1
-    nnz_per_launch = nnz * strata_per_launch / P
-    # algorithmic bytes per stratum: 8 B per nonzero record streamed once; the
-    # moving (patient) rows read and written once per stratum; the stationary
-    # (gene) rows read and written once per launch
-    bytes_per_launch = (8.0 * nnz_per_launch + strata_per_launch * 8.0 * I1 * J1 + 8.0 * I2 * J2)
-    flops_per_nnz = 6 * J1 * J2 + 4 * (J1 + J2)
-    achieved_gbs = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
-    jp = min(j for j in (2, 4, 5, 8, 10, 12, 16, 20, 24, 32) if j >= max(J1, J2))
-    kernel = (f"strata_persistent<{jp}, {'true' if precision == sn.PRECISION_BF16 else 'false'}, "
-              f"{args.waves or 8}>"
-              if persistent else f"block_step<{jp}>")
-    # the counter summary covers the default workload only
-    default_workload = (nnz == 25_000_000 and ranks == (10, 10, 5) and P == 128 and args.tile == 64)
-    traffic = measured_traffic(kernel) if default_workload else None
-    mfma = measured_mfma(kernel) if default_workload else None
-    achieved_tf = flops_per_nnz * nnz_per_launch / avg_launch_s / 1e12 if avg_launch_s > 0 else 0.0
+    bf = precision == sn.PRECISION_BF16
+    kernel = stratum_kernel(ranks, bf, args.waves, persistent)
+    roof = stratum_roofline(kernel, workload_key(nnz, ranks, P, args.tile), bf, persistent, nnz, dims, ranks, P,
+                            avg_launch_s)
 
     out = {
         "metric": "nonzero SGD updates/s FP32 vs BF16-MFMA at equal RMSE; fold-in p50/p99 ms",
@@ -238,16 +253,7 @@ def main():
                    "ranks": list(ranks), "strata_P": P, "tile_T": args.tile,
                    "graph": "barabasi-albert m=10", "edges": int(eu.shape[0]),
                    "lambda": 0.01, "lambda_g": 0.1, "lr": 1e-3},
-        "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": kernel,
-                     "avg_launch_us": avg_launch_s * 1e6, "bytes_per_launch": bytes_per_launch,
-                     "alu_tflops": achieved_tf, "alu_frac": achieved_tf / FP32_VECTOR_PEAK_TFLOPS,
-                     # counter-measured matrix-core work (padded tiles) over the live launch time
-                     "mfma": None if mfma is None or avg_launch_s <= 0 else {
-                         "flops_per_launch": mfma[0], "tflops": mfma[0] / avg_launch_s / 1e12,
-                         "peak": FP32_MFMA_PEAK_TFLOPS, "frac": mfma[0] / avg_launch_s / 1e12 / FP32_MFMA_PEAK_TFLOPS,
-                         "busy_util_pct": mfma[1]}},
+        "roofline": roof,
         "phases_ms_per_step": {"graph": tm["graph_ms"] / args.steps,
                                "strata": tm["strata_ms"] / args.steps,
                                "loss": tm["loss_ms"] / args.steps},
@@ -404,8 +410,10 @@ def equal_rmse_leg(args, sn, synth, ctx, data, dims):
         hyper = sn.Hyper(ranks=ranks, lam=0.01, lam_g=0.1, lr=1e-3, core_lr_scale=1.0, P=args.strata,
                          T=args.tile, precision=prec, seed=synth.PLAN_SEED + 2)
         prob = sn.Problem(ctx, dims, i, j, k, x, eu, ev, None, hyper)
+        prob.set_exec(per_launch_timing=True)
         f = [torch.tensor(a.astype(np.float32), device="cuda:0").contiguous() for a in init]
         walls, rmses, snaps = [], [], {}
+        kern_ms, launches = 0.0, 0
         for ep in range(E if target is None else 2 * E):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -413,11 +421,15 @@ def equal_rmse_leg(args, sn, synth, ctx, data, dims):
             torch.cuda.synchronize()
             walls.append(time.perf_counter() - t0)
             rmses.append(float(rmse[0]))
+            tm = prob.last_timing()
+            kern_ms += tm["kernel_ms"]
+            launches += tm["kernel_launches"]
             if ep == 0 or ep == E - 1:
                 snaps[ep + 1] = [t.double().cpu().numpy() for t in f]
                 snaps[f"rmse_{ep + 1}"] = rmses[-1]
             if target is not None and ep + 1 >= E and rmses[-1] <= target:
                 break
+        persistent = prob.exec_path() == sn.PATH_PERSISTENT
         prob.close()
         if target is None:
             target = rmses[E - 1]
@@ -434,6 +446,10 @@ def equal_rmse_leg(args, sn, synth, ctx, data, dims):
                       "epochs_to_target": e_t, "wall_s_to_target": w_t,
                       "epochs_to_band": e_b, "wall_s_to_band": w_b,
                       "updates_per_s": nnz * len(rmses) / float(cum[-1])}
+        bf = prec == sn.PRECISION_BF16
+        runs[name]["roofline"] = stratum_roofline(
+            stratum_kernel(ranks, bf, 0, persistent), workload_key(nnz, ranks, args.strata, args.tile), bf,
+            persistent, nnz, dims, ranks, args.strata, kern_ms * 1e-3 / max(launches, 1))
         factors[name] = snaps
     out = {"workload": "pancan-shaped tensor, core 20x20x5, P=%d, T=%d" % (args.strata, args.tile),
            "target_rmse": target, "target": "FP32 training RMSE after %d epochs" % E,
