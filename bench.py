@@ -81,33 +81,37 @@ def workload_key(nnz, ranks, P, T):
     return f"pancan-shaped {nnz} nonzeros, core {ranks[0]}x{ranks[1]}x{ranks[2]}, P={P}, T={T}"
 
 
-def profile_values(suffix: str, prefix: str, kernel: str, workload: str):
-    """The `<prefix>_*: value` lines of the committed rocprofv3 summary
-    (profiles/*<suffix>) taken on `kernel`, `workload` and the current kernel
-    source, or None when there is none."""
+def profile_entry(suffix: str, prefix: str, kernel: str, workload: str):
+    """The fields after kernel and workload of a `<prefix>_entry: kernel |
+    workload | ...` line of a committed rocprofv3 summary (profiles/*<suffix>)
+    taken on the current kernel source (its `kernel_source_sha256:` line), or
+    None when there is none."""
     try:
         sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     except OSError:
         return None
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*" + suffix))):
-        vals = dict(re.findall(r"^\s*(%s_\w+|kernel_source_sha256):\s*(.+?)\s*$" % prefix, open(path).read(),
-                               re.M))
-        if (vals.get("kernel_source_sha256") == sha and vals.get(f"{prefix}_kernel") == kernel
-                and vals.get(f"{prefix}_workload") == workload):
-            return vals
+        text = open(path).read()
+        m = re.search(r"^\s*kernel_source_sha256:\s*(\S+)\s*$", text, re.M)
+        if not m or m.group(1) != sha:
+            continue
+        for line in re.findall(r"^\s*%s_entry:\s*(.+?)\s*$" % prefix, text, re.M):
+            parts = [f.strip() for f in line.split("|")]
+            if len(parts) >= 3 and parts[0] == kernel and parts[1] == workload:
+                return parts[2:]
     return None
 
 
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
-    v = profile_values("_hbm_counters.md", "traffic", kernel, workload)
-    return None if v is None else float(v["traffic_bytes_per_launch"])
+    v = profile_entry("_hbm_counters.md", "traffic", kernel, workload)
+    return None if v is None else float(v[0])
 
 
 def measured_mfma(kernel: str, workload: str):
     """Matrix-core flops per launch and busy-cycle utilisation (percent)."""
-    v = profile_values("_mfma_counters.md", "mfma", kernel, workload)
-    return None if v is None else (float(v["mfma_flops_per_launch"]), float(v["mfma_util_pct"]))
+    v = profile_entry("_mfma_counters.md", "mfma", kernel, workload)
+    return None if v is None else (float(v[0]), float(v[1]))
 
 
 def stratum_roofline(kernel, workload, bf, persistent, nnz, dims, ranks, P, avg_launch_s):
