@@ -55,7 +55,8 @@ def parse():
                     help="report the FP32 and BF16 errors against the FP64 oracle at the last FP32 epoch "
                          "of the core 20x20x5 run too, not only after epoch 1 (minutes of CPU)")
     ap.add_argument("--no-oracle-errors", action="store_true",
-                    help="skip the FP64 oracle epoch that the core 20x20x5 errors are measured against")
+                    help="skip the FP64 oracle epoch that the core 20x20x5 errors are measured against "
+                         "(--no-cpu-baseline skips every oracle run)")
     ap.add_argument("--sweep-epochs", type=int, default=0,
                     help="epochs of the 16-problem batched sweep (0 = skip; the batched launch is switched "
                          "off in this build)")
@@ -266,13 +267,17 @@ def main():
         "final_rmse": float(rmse[-1]), "final_loss": float(loss[-1]),
     }
 
+    later = {}  # inputs of the oracle runs of the CPU leg
     if args.serve_requests > 0:
-        out["serving"] = serve_leg(args, sn, synth, prob, f, dims, ranks)
+        out["serving"], later["serving"] = serve_leg(args, sn, synth, prob, f, dims, ranks)
     if args.equal_rmse_epochs > 0:
-        out["fp32_vs_bf16"] = equal_rmse_leg(args, sn, synth, ctx, (i, j, k, x, eu, ev), dims)
+        out["fp32_vs_bf16"], later["fp32_vs_bf16"] = equal_rmse_leg(args, sn, synth, ctx, (i, j, k, x, eu, ev),
+                                                                    dims)
     if args.sweep_epochs > 0:
         out["sweep"] = sweep_leg(args, sn, synth, ctx)
 
+    # the CPU leg: every use of the FP64 oracle (timed baselines, and the
+    # reference the GPU runs' errors are measured against)
     if not args.no_cpu_baseline:
         import oracle
         cores = oracle.num_threads()
@@ -305,6 +310,13 @@ def main():
                                      f"thread ({t1:.1f}s)"}}
         log(f"cpu oracle {tcpu:.1f}s on {cores} threads, {t1:.1f}s on one thread for {nnz1} nonzeros",
             args.quiet)
+        if "serving" in later:
+            out["serving"]["cpu_oracle_ms_per_request"] = serve_oracle_ms(later["serving"])
+        if "fp32_vs_bf16" in later and not args.no_oracle_errors:
+            q = later["fp32_vs_bf16"]
+            epochs = (1, q["E"]) if args.bf16_oracle else (1,)
+            out["fp32_vs_bf16"]["vs_oracle"] = bf16_oracle_errors(args, synth, q["data"], dims, q["ranks"],
+                                                                 q["init"], q["factors"], epochs)
     prob.close()
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -463,11 +475,8 @@ def equal_rmse_leg(args, sn, synth, ctx, data, dims):
         out["speedup_at_equal_rmse"] = runs["fp32"]["wall_s_to_target"] / runs["bf16"]["wall_s_to_target"]
     if runs["bf16"]["wall_s_to_band"] and runs["fp32"]["wall_s_to_band"]:
         out["speedup_at_band"] = runs["fp32"]["wall_s_to_band"] / runs["bf16"]["wall_s_to_band"]
-    if not args.no_oracle_errors:
-        epochs = (1, E) if args.bf16_oracle else (1,)
-        out["vs_oracle"] = bf16_oracle_errors(args, synth, data, dims, ranks, init, factors, epochs)
     log(f"fp32 vs bf16: {json.dumps(out)}", args.quiet)
-    return out
+    return out, {"data": data, "ranks": ranks, "init": init, "factors": factors, "E": E}
 
 
 def bf16_oracle_errors(args, synth, data, dims, ranks, init, factors, epochs):
@@ -544,19 +553,21 @@ def serve_leg(args, sn, synth, prob, f, dims, ranks):
     # the highest offered rate whose p99 stays within twice the p99 at 2,000/s
     ok = [lv["offered_per_s"] for lv in ladder[:-1] if lv["p99_ms"] <= 2.0 * out["p99_ms"]]
     out["p99_knee_offered_per_s"] = max(ok) if ok else None
-    if not args.no_cpu_baseline:
-        # the oracle's fold-in and top-k, one thread of numpy, on a few requests
-        import oracle
-        A, B, C, G = (t.double().cpu().numpy() for t in f)
-        tc = time.perf_counter()
-        nq = min(20, len(reqs))
-        for r in reqs[:nq]:
-            u = oracle.fold_in(B, C, G, r["j"], r["k"], r["x"].astype(np.float64), lam=0.01)
-            oracle.topk_cosine(A, u, 10)
-        out["cpu_oracle_ms_per_request"] = 1e3 * (time.perf_counter() - tc) / nq
     log(f"serving p50 {out['p50_ms']:.3f} ms p99 {out['p99_ms']:.3f} ms, {out['queries_per_s']:.0f} q/s, "
         f"GPU busy {out['gpu_busy_pct']:.1f}%, capacity {out['capacity_queries_per_s']:.0f} q/s", args.quiet)
-    return out
+    return out, {"factors": [t.double().cpu().numpy() for t in f], "reqs": reqs[:20]}
+
+
+def serve_oracle_ms(q):
+    """The oracle's fold-in and top-k (numpy, one request at a time) on the
+    first requests of the serving stream: ms per request."""
+    import oracle
+    A, B, C, G = q["factors"]
+    tc = time.perf_counter()
+    for r in q["reqs"]:
+        u = oracle.fold_in(B, C, G, r["j"], r["k"], r["x"].astype(np.float64), lam=0.01)
+        oracle.topk_cosine(A, u, 10)
+    return 1e3 * (time.perf_counter() - tc) / max(len(q["reqs"]), 1)
 
 
 if __name__ == "__main__":
