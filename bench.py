@@ -316,7 +316,7 @@ def main():
             q = later["fp32_vs_bf16"]
             epochs = (1, q["E"]) if args.bf16_oracle else (1,)
             out["fp32_vs_bf16"]["vs_oracle"] = bf16_oracle_errors(args, synth, q["data"], dims, q["ranks"],
-                                                                 q["init"], q["factors"], epochs)
+                                                                 q["init"], q["factors"], epochs, cores)
     prob.close()
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -479,7 +479,7 @@ def equal_rmse_leg(args, sn, synth, ctx, data, dims):
     return out, {"data": data, "ranks": ranks, "init": init, "factors": factors, "E": E}
 
 
-def bf16_oracle_errors(args, synth, data, dims, ranks, init, factors, epochs):
+def bf16_oracle_errors(args, synth, data, dims, ranks, init, factors, epochs, threads):
     """Relative Frobenius error of A, B, C, G and the training RMSE of both
     precisions against the FP64 oracle, after each epoch count in `epochs`."""
     import oracle
@@ -492,7 +492,7 @@ def bf16_oracle_errors(args, synth, data, dims, ranks, init, factors, epochs):
     for ep in sorted(set(epochs)):
         while done < ep:  # one epoch per call, so that progress shows
             t0 = time.perf_counter()
-            A, B, C, G, loss, rmse = oracle.run(prob_o, *cur, 1, start_epoch=done)
+            A, B, C, G, loss, rmse = oracle.run(prob_o, *cur, 1, start_epoch=done, threads=threads)
             cur, done = [A, B, C, G], done + 1
             log(f"oracle epoch {done}: rmse {rmse[-1]:.6f} ({time.perf_counter() - t0:.1f}s)", args.quiet)
         res[f"epoch_{ep}"] = {"oracle_rmse": float(rmse[-1])}
