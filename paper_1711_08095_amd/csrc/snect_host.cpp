@@ -162,14 +162,17 @@ struct snect_problem {
     int32_t* d_order = nullptr;  // [P]
     GridBar* d_bar = nullptr;
     double *d_sse = nullptr, *d_regp = nullptr, *d_net = nullptr, *d_lossout = nullptr;
-    double* h_lossout = nullptr;  // pinned
-    int32_t* h_order = nullptr;   // pinned [P]
-    float *d_bakA = nullptr, *d_bakB = nullptr, *d_bakC = nullptr, *d_bakG = nullptr;
+    // Per-epoch state comes in two slots (epoch parity), so that the next
+    // epoch can be queued before the previous one is checked.
+    double* h_lossout = nullptr;  // pinned [2][2]: f_opt, sum of squared errors
+    GridBar* h_bar = nullptr;     // pinned [2]: the grid barrier after the epoch
+    int32_t* h_order = nullptr;   // pinned [2][P]
+    float *d_bakA = nullptr, *d_bakB = nullptr, *d_bakC = nullptr, *d_bakG = nullptr;  // [2] each
     // execution
     int path = SNECT_PATH_AUTO;
     bool per_launch = false;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    std::vector<hipEvent_t> evl;  // per-launch timing events
+    hipEvent_t ev[2][4] = {{nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr}};
+    std::vector<hipEvent_t> evl;  // per-launch timing events, [2][2 * launches]
     double t_ms[5] = {0, 0, 0, 0, 0};
 
     template <class T_>
@@ -189,9 +192,11 @@ struct snect_problem {
     {
         for (auto& b : bufs) (void)hipFree(b.p);
         if (h_lossout) (void)hipHostFree(h_lossout);
+        if (h_bar) (void)hipHostFree(h_bar);
         if (h_order) (void)hipHostFree(h_order);
-        for (auto& e : ev)
-            if (e) (void)hipEventDestroy(e);
+        for (auto& es : ev)
+            for (auto& e : es)
+                if (e) (void)hipEventDestroy(e);
         for (auto& e : evl)
             if (e) (void)hipEventDestroy(e);
     }
@@ -605,16 +610,17 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         pr->d_regp = pr->alloc<double>(pr->n_reg_wg, rc);
         pr->d_net = pr->alloc<double>(I2, rc);
         pr->d_lossout = pr->alloc<double>(2, rc);
-        pr->d_bakA = pr->alloc<float>((size_t)I1 * J1, rc);
-        pr->d_bakB = pr->alloc<float>((size_t)I2 * J2, rc);
-        pr->d_bakC = pr->alloc<float>((size_t)I3 * J3, rc);
-        pr->d_bakG = pr->alloc<float>(ng, rc);
+        pr->d_bakA = pr->alloc<float>(2 * (size_t)I1 * J1, rc);
+        pr->d_bakB = pr->alloc<float>(2 * (size_t)I2 * J2, rc);
+        pr->d_bakC = pr->alloc<float>(2 * (size_t)I3 * J3, rc);
+        pr->d_bakG = pr->alloc<float>(2 * ng, rc);
         if (rc) {
             delete pr;
             return set_err(ctx, SNECT_E_OOM, "device allocation failed");
         }
-        if (hipHostMalloc((void**)&pr->h_lossout, 2 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void**)&pr->h_order, (size_t)P * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc((void**)&pr->h_lossout, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&pr->h_bar, 2 * sizeof(GridBar), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&pr->h_order, 2 * (size_t)P * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
             delete pr;
             return set_err(ctx, SNECT_E_OOM, "pinned host allocation failed");
         }
@@ -646,7 +652,7 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         he = he ? he : hipStreamSynchronize(st);
         he = he ? he : prepare_kernels(jp, llds, clds, pr->loss_cols_lds);
         he = he ? he : configure_exec(pr, kDefaultWaves, rec_cap);
-        for (int t = 0; t < 4 && he == hipSuccess; ++t) he = hipEventCreate(&pr->ev[t]);
+        for (int t = 0; t < 8 && he == hipSuccess; ++t) he = hipEventCreate(&pr->ev[t / 4][t % 4]);
         if (he != hipSuccess) {
             delete pr;
             return set_err(ctx, SNECT_E_HIP, std::string("upload: ") + hipGetErrorString(he));
@@ -716,8 +722,8 @@ static GraphArgs graph_args(const snect_problem* pr)
 }
 
 // Loss of the factors held in position order (d_Ap, d_Bp, C, G) into
-// pr->h_lossout (asynchronous; the caller synchronises).
-static int run_loss(snect_problem* pr, const float* C, const float* G)
+// slot `slot` of pr->h_lossout (asynchronous; the caller synchronises).
+static int run_loss(snect_problem* pr, const float* C, const float* G, int slot = 0)
 {
     snect_ctx* ctx = pr->ctx;
     LossArgs la;
@@ -734,7 +740,8 @@ static int run_loss(snect_problem* pr, const float* C, const float* G)
     la.lam = pr->lam; la.lam_g = pr->lam_g;
     GraphArgs ga = graph_args(pr);
     HIP_TRY(launch_loss(la, ga, pr->jp, pr->loss_lds, pr->loss_cols_lds, pr->loss_parts, ctx->stream));
-    HIP_TRY(hipMemcpyAsync(pr->h_lossout, pr->d_lossout, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(pr->h_lossout + 2 * slot, pr->d_lossout, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                           ctx->stream));
     return SNECT_OK;
 }
 
@@ -788,18 +795,19 @@ static StratArgs strat_args(const snect_problem* pr, const snect_factors* f)
 }
 
 // Start of an epoch: keep the factors (position order) for a divergence
-// rollback, then the network step (Jacobi sub-steps through Btmp).
-static int epoch_begin(snect_problem* pr, snect_factors* f)
+// rollback in backup slot `slot`, then the network step (Jacobi sub-steps
+// through Btmp).
+static int epoch_begin(snect_problem* pr, snect_factors* f, int slot = 0)
 {
     snect_ctx* ctx = pr->ctx;
     hipStream_t st = ctx->stream;
-    const size_t szA = (size_t)pr->I1 * pr->J1 * 4, szB = (size_t)pr->I2 * pr->J2 * 4,
-                 szC = (size_t)pr->I3 * pr->J3 * 4, szG = (size_t)pr->J1 * pr->J2 * pr->J3 * 4;
-    HIP_TRY(hipMemcpyAsync(pr->d_bakA, pr->d_Ap, szA, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(pr->d_bakB, pr->d_Bp, szB, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(pr->d_bakC, f->C, szC, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(pr->d_bakG, f->G, szG, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipEventRecord(pr->ev[0], st));
+    const size_t nA = (size_t)pr->I1 * pr->J1, nB = (size_t)pr->I2 * pr->J2, nC = (size_t)pr->I3 * pr->J3,
+                 nG = (size_t)pr->J1 * pr->J2 * pr->J3;
+    HIP_TRY(hipMemcpyAsync(pr->d_bakA + slot * nA, pr->d_Ap, 4 * nA, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(pr->d_bakB + slot * nB, pr->d_Bp, 4 * nB, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(pr->d_bakC + slot * nC, f->C, 4 * nC, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(pr->d_bakG + slot * nG, f->G, 4 * nG, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipEventRecord(pr->ev[slot][0], st));
     GraphArgs ga = graph_args(pr);
     for (int it = 0; it < pr->n_sub; ++it) {
         const bool even = (it % 2) == 0;
@@ -807,64 +815,68 @@ static int epoch_begin(snect_problem* pr, snect_factors* f)
         ga.Bout = even ? pr->d_Btmp : pr->d_Bp;
         HIP_TRY(launch_graph_step(ga, pr->jp, st));
     }
-    if (pr->n_sub % 2 == 1) HIP_TRY(hipMemcpyAsync(pr->d_Bp, pr->d_Btmp, szB, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipEventRecord(pr->ev[1], st));
+    if (pr->n_sub % 2 == 1) HIP_TRY(hipMemcpyAsync(pr->d_Bp, pr->d_Btmp, 4 * nB, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipEventRecord(pr->ev[slot][1], st));
     return SNECT_OK;
 }
 
-// The persistent driver's per-epoch inputs: the stratum order (through the
-// pinned buffer, free because the previous epoch ended with a stream
-// synchronisation) and a cleared grid barrier.
-static int persistent_inputs(snect_problem* pr, int32_t ep)
+// The persistent driver's per-epoch inputs: the stratum order (through
+// pinned slot `slot`, whose previous upload finished before the epoch two
+// back was checked) and a cleared grid barrier.
+static int persistent_inputs(snect_problem* pr, int32_t ep, int slot = 0)
 {
     snect_ctx* ctx = pr->ctx;
     const std::vector<int32_t> order = stratum_order(pr->P, pr->seed, ep);
-    std::memcpy(pr->h_order, order.data(), (size_t)pr->P * 4);
-    HIP_TRY(hipMemcpyAsync(pr->d_order, pr->h_order, (size_t)pr->P * 4, hipMemcpyHostToDevice, ctx->stream));
+    int32_t* h = pr->h_order + (size_t)slot * pr->P;
+    std::memcpy(h, order.data(), (size_t)pr->P * 4);
+    HIP_TRY(hipMemcpyAsync(pr->d_order, h, (size_t)pr->P * 4, hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(hipMemsetAsync(pr->d_bar, 0, sizeof(GridBar), ctx->stream));
     return SNECT_OK;
 }
 
-// After the strata: the loss launch (asynchronous).
-static int epoch_loss(snect_problem* pr, snect_factors* f)
+// After the strata: the loss launch and the downloads of the loss and of the
+// grid barrier's state into slot `slot` (asynchronous).
+static int epoch_loss(snect_problem* pr, snect_factors* f, int slot = 0)
 {
-    HIP_TRY_CTX(pr->ctx, hipEventRecord(pr->ev[2], pr->ctx->stream));
-    int rc = run_loss(pr, f->C, f->G);
+    HIP_TRY_CTX(pr->ctx, hipEventRecord(pr->ev[slot][2], pr->ctx->stream));
+    int rc = run_loss(pr, f->C, f->G, slot);
     if (rc) return rc;
-    HIP_TRY_CTX(pr->ctx, hipEventRecord(pr->ev[3], pr->ctx->stream));
+    HIP_TRY_CTX(pr->ctx, hipMemcpyAsync(pr->h_bar + slot, pr->d_bar, sizeof(GridBar), hipMemcpyDeviceToHost,
+                                        pr->ctx->stream));
+    HIP_TRY_CTX(pr->ctx, hipEventRecord(pr->ev[slot][3], pr->ctx->stream));
     return SNECT_OK;
 }
 
-// After the stream synchronisation: barrier health, timings, the epoch's
-// loss, and the rollback of a non-finite epoch (SNECT_E_DIVERGED).
+// Once the epoch in slot `slot` has finished (this waits for it): barrier
+// health, timings, the epoch's loss, and the rollback of a non-finite epoch
+// (SNECT_E_DIVERGED) from the slot's backup, after everything queued behind
+// it has finished too.
 static int epoch_finish(snect_problem* pr, snect_factors* f, int32_t ep, bool persistent, double* loss,
-                        double* rmse)
+                        double* rmse, int slot = 0)
 {
     snect_ctx* ctx = pr->ctx;
     hipStream_t st = ctx->stream;
-    if (persistent) {
-        GridBar hb;
-        HIP_TRY(hipMemcpy(&hb, pr->d_bar, sizeof(GridBar), hipMemcpyDeviceToHost));
-        if (hb.err) return set_err(ctx, SNECT_E_HIP, "grid barrier timed out in the stratum kernel");
-    }
+    HIP_TRY(hipEventSynchronize(pr->ev[slot][3]));
+    if (persistent && pr->h_bar[slot].err) return set_err(ctx, SNECT_E_HIP, "grid barrier timed out in the stratum kernel");
     float m0 = 0, m1 = 0, m2 = 0;
-    HIP_TRY(hipEventElapsedTime(&m0, pr->ev[0], pr->ev[1]));
-    HIP_TRY(hipEventElapsedTime(&m1, pr->ev[1], pr->ev[2]));
-    HIP_TRY(hipEventElapsedTime(&m2, pr->ev[2], pr->ev[3]));
+    HIP_TRY(hipEventElapsedTime(&m0, pr->ev[slot][0], pr->ev[slot][1]));
+    HIP_TRY(hipEventElapsedTime(&m1, pr->ev[slot][1], pr->ev[slot][2]));
+    HIP_TRY(hipEventElapsedTime(&m2, pr->ev[slot][2], pr->ev[slot][3]));
     pr->t_ms[0] += m0;
     pr->t_ms[1] += m1;
     pr->t_ms[2] += m2;
-    const double fl = pr->h_lossout[0];
-    const double r = pr->nnz > 0 ? std::sqrt(pr->h_lossout[1] / (double)pr->nnz) : 0.0;
+    const double fl = pr->h_lossout[2 * slot];
+    const double r = pr->nnz > 0 ? std::sqrt(pr->h_lossout[2 * slot + 1] / (double)pr->nnz) : 0.0;
     if (loss) *loss = fl;
     if (rmse) *rmse = r;
     if (!std::isfinite(fl) || !std::isfinite(r)) {
-        const size_t szA = (size_t)pr->I1 * pr->J1 * 4, szB = (size_t)pr->I2 * pr->J2 * 4,
-                     szC = (size_t)pr->I3 * pr->J3 * 4, szG = (size_t)pr->J1 * pr->J2 * pr->J3 * 4;
-        HIP_TRY(hipMemcpyAsync(pr->d_Ap, pr->d_bakA, szA, hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipMemcpyAsync(pr->d_Bp, pr->d_bakB, szB, hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipMemcpyAsync(f->C, pr->d_bakC, szC, hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipMemcpyAsync(f->G, pr->d_bakG, szG, hipMemcpyDeviceToDevice, st));
+        const size_t nA = (size_t)pr->I1 * pr->J1, nB = (size_t)pr->I2 * pr->J2, nC = (size_t)pr->I3 * pr->J3,
+                     nG = (size_t)pr->J1 * pr->J2 * pr->J3;
+        HIP_TRY(hipStreamSynchronize(st));
+        HIP_TRY(hipMemcpyAsync(pr->d_Ap, pr->d_bakA + slot * nA, 4 * nA, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(pr->d_Bp, pr->d_bakB + slot * nB, 4 * nB, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(f->C, pr->d_bakC + slot * nC, 4 * nC, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(f->G, pr->d_bakG + slot * nG, 4 * nG, hipMemcpyDeviceToDevice, st));
         return set_err(ctx, SNECT_E_DIVERGED, "loss not finite at epoch " + std::to_string(ep));
     }
     return SNECT_OK;
@@ -883,56 +895,69 @@ int snect_train(snect_problem* pr, snect_factors* f, int32_t start_epoch, int32_
     hipStream_t st = ctx->stream;
     const int P = pr->P;
     const int path = pr->chosen_path();
-    if (path == SNECT_PATH_PERSISTENT && !pr->persistent_ok())
+    const bool persistent = path == SNECT_PATH_PERSISTENT;
+    if (persistent && !pr->persistent_ok())
         return set_err(ctx, SNECT_E_UNSUPPORTED, "the persistent stratum kernel cannot be resident for this P");
     for (double& t : pr->t_ms) t = 0.0;
-    const int nlaunch = path == SNECT_PATH_PERSISTENT ? 1 : P;
-    if (pr->per_launch && (int)pr->evl.size() < 2 * nlaunch) {
+    const int nlaunch = persistent ? 1 : P;
+    if (pr->per_launch && (int)pr->evl.size() < 4 * nlaunch) {
         const size_t have = pr->evl.size();
-        pr->evl.resize(2 * (size_t)nlaunch, nullptr);
+        pr->evl.resize(4 * (size_t)nlaunch, nullptr);
         for (size_t t = have; t < pr->evl.size(); ++t) HIP_TRY(hipEventCreate(&pr->evl[t]));
     }
     StratArgs sa = strat_args(pr, f);
     if ((rc = to_positions(pr, f))) return rc;
-    for (int32_t ep = start_epoch; ep < start_epoch + epochs; ++ep) {
-        if ((rc = epoch_begin(pr, f))) return rc;
-        if (path == SNECT_PATH_PERSISTENT) {
-            if ((rc = persistent_inputs(pr, ep))) return rc;
-            if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[0], st));
-            HIP_TRY(launch_strata_persistent(sa, pr->jp, pr->bf, pr->nw, pr->strata_lds, st));
-            if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[1], st));
-        } else {
-            const std::vector<int32_t> order = stratum_order(P, pr->seed, ep);
-            for (int si = 0; si < P; ++si) {
-                sa.s = order[si];
-                if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[2 * si], st));
-                HIP_TRY(launch_block(sa, pr->jp, pr->bf, pr->nw, pr->block_lds, st));
-                if (pr->per_launch) HIP_TRY(hipEventRecord(pr->evl[2 * si + 1], st));
-                HIP_TRY(launch_core_step(sa, pr->core_lds, st));
-            }
-        }
-        if ((rc = epoch_loss(pr, f))) return rc;
-        HIP_TRY(hipStreamSynchronize(st));
+    // Epoch ep is queued before epoch ep - 1 is checked, so the host's work
+    // between epochs overlaps the device's; per-epoch state alternates
+    // between two slots.  A non-finite epoch rolls back to its own start once
+    // the epoch queued behind it has finished.
+    auto finish = [&](int32_t e) -> int {
+        const int slot = e & 1;
         if (pr->per_launch) {
+            hipEvent_t* el = pr->evl.data() + (size_t)slot * 2 * nlaunch;
+            HIP_TRY(hipEventSynchronize(pr->ev[slot][3]));
             for (int l = 0; l < nlaunch; ++l) {
                 float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, pr->evl[2 * l], pr->evl[2 * l + 1]));
+                HIP_TRY(hipEventElapsedTime(&ms, el[2 * l], el[2 * l + 1]));
                 pr->t_ms[3] += ms;
             }
             pr->t_ms[4] += nlaunch;
         }
-        rc = epoch_finish(pr, f, ep, path == SNECT_PATH_PERSISTENT, loss ? loss + (ep - start_epoch) : nullptr,
-                          rmse ? rmse + (ep - start_epoch) : nullptr);
-        if (rc) {
+        int r = epoch_finish(pr, f, e, persistent, loss ? loss + (e - start_epoch) : nullptr,
+                             rmse ? rmse + (e - start_epoch) : nullptr, slot);
+        if (r) {
             const std::string msg = ctx->err;
-            if (rc == SNECT_E_DIVERGED) {
-                int r2 = from_positions(pr, f);
-                if (r2 == SNECT_OK) (void)hipStreamSynchronize(st);
-            }
+            (void)hipStreamSynchronize(st);
+            if (r == SNECT_E_DIVERGED && from_positions(pr, f) == SNECT_OK) (void)hipStreamSynchronize(st);
             ctx->err = msg;
-            return rc;
         }
+        return r;
+    };
+    int32_t pending = -1;
+    for (int32_t ep = start_epoch; ep < start_epoch + epochs; ++ep) {
+        const int slot = ep & 1;
+        hipEvent_t* el = pr->per_launch ? pr->evl.data() + (size_t)slot * 2 * nlaunch : nullptr;
+        if ((rc = epoch_begin(pr, f, slot))) return rc;
+        if (persistent) {
+            if ((rc = persistent_inputs(pr, ep, slot))) return rc;
+            if (el) HIP_TRY(hipEventRecord(el[0], st));
+            HIP_TRY(launch_strata_persistent(sa, pr->jp, pr->bf, pr->nw, pr->strata_lds, st));
+            if (el) HIP_TRY(hipEventRecord(el[1], st));
+        } else {
+            const std::vector<int32_t> order = stratum_order(P, pr->seed, ep);
+            for (int si = 0; si < P; ++si) {
+                sa.s = order[si];
+                if (el) HIP_TRY(hipEventRecord(el[2 * si], st));
+                HIP_TRY(launch_block(sa, pr->jp, pr->bf, pr->nw, pr->block_lds, st));
+                if (el) HIP_TRY(hipEventRecord(el[2 * si + 1], st));
+                HIP_TRY(launch_core_step(sa, pr->core_lds, st));
+            }
+        }
+        if ((rc = epoch_loss(pr, f, slot))) return rc;
+        if (pending >= 0 && (rc = finish(pending))) return rc;
+        pending = ep;
     }
+    if (pending >= 0 && (rc = finish(pending))) return rc;
     if ((rc = from_positions(pr, f))) return rc;
     HIP_TRY(hipStreamSynchronize(st));
     return SNECT_OK;

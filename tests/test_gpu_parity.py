@@ -184,15 +184,32 @@ def test_evaluate_per_block_loss_kernel(ctx):
 
 
 def test_divergence_returns_last_finite(ctx):
+    import torch
     import paper_1711_08095_amd as sn
     case = planted_case(lr=5.0, P=4, T=16)
     prob = gpu_problem(ctx, case)
     f = gpu_factors(case)
     with pytest.raises(sn.SnectError) as e:
-        prob.train(*f, epochs=3)
+        prob.train(*f, epochs=6)
     assert e.value.code == -7
     for t in f:
         assert bool(t.isfinite().all())
+    # the same factors as training one epoch per call up to the first
+    # non-finite epoch (whose call rolls back to its own start); later epochs
+    # may already have been queued when the divergence is seen
+    g = gpu_factors(case)
+    first_bad = None
+    for ep in range(6):
+        try:
+            prob.train(*g, epochs=1, start_epoch=ep)
+        except sn.SnectError as err:
+            assert err.code == -7
+            first_bad = ep
+            break
+    assert first_bad is not None
+    print(f"first non-finite epoch {first_bad}", flush=True)
+    for x, y in zip(f, g):
+        assert torch.equal(x, y)
 
 
 def test_validation_errors(ctx):
