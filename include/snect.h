@@ -264,23 +264,26 @@ typedef struct {
 
 int snect_set_exec(snect_problem *prob, const snect_exec *exec);
 
-/* NOTE: in this build snect_sweep_train and snect_sweep_autotune validate
- * their arguments and then return SNECT_E_UNSUPPORTED: the batched launch
- * is switched off until the cause of a GPU memory fault seen in its kernel
- * is established.
+/* Sweep: trains n independent problems of one context together (the
+ * rank and lambda_g grids of Section 3.1), each following exactly the
+ * schedule snect_train would run for it, so its factors and losses are
+ * bit-identical to snect_train's (Algorithm 1 per problem, as read in
+ * snect_train).  fs[i] are problem i's factors (device, caller owned);
+ * loss and rmse (host, may be NULL) receive n * epochs values,
+ * problem-major.  The problems must share a precision.
  *
- * Batched sweep: trains n independent problems of one context together,
- * each epoch's strata of all of them in ONE cooperative launch (problem i
- * takes P_i workgroups and synchronises on its own grid barrier).  Each
- * problem follows
- * exactly the schedule snect_train would run for it, so its factors and
- * losses are bit-identical to snect_train's (Algorithm 1 per problem, as
- * read in snect_train).  fs[i] are problem i's factors (device, caller
- * owned); loss and rmse (host, may be NULL) receive n * epochs values,
- * problem-major.  The problems must share a precision; every problem runs
- * the code of its own core size in workgroups of eight wavefronts with the
- * record chunk snect_sweep_autotune chose (default: the largest that fits).  Errors: E_ARG, E_UNSUPPORTED (sum of P_i above the
- * co-resident workgroups), E_OOM, E_HIP, E_DIVERGED (the message names the problem;
+ * In this build every problem runs on a stream of its own, created for the
+ * call, with the multi-launch driver (a block-step launch and a core-step
+ * launch per stratum, the code of its own core size, workgroups of eight
+ * wavefronts, the record chunk snect_sweep_autotune chose up to the
+ * problem's own), the problems' epochs queued side by side so that they
+ * run concurrently; the streams start after the work already queued on the
+ * context's stream, and the call waits for them before it returns.  The
+ * single cooperative launch per epoch for all problems (problem i on P_i
+ * workgroups with its own grid barrier) is switched off until the cause of
+ * a GPU memory fault seen in its kernel is established.
+ *
+ * Errors: E_ARG, E_OOM, E_HIP, E_DIVERGED (the message names the problem;
  * that problem's factors are rolled back to the start of the failing
  * epoch, the others end after it; later loss entries are undefined). */
 int snect_sweep_train(snect_ctx *ctx, int32_t n, snect_problem *const *probs, snect_factors *fs,
@@ -298,7 +301,7 @@ int snect_sweep_train(snect_ctx *ctx, int32_t n, snect_problem *const *probs, sn
 int snect_autotune(snect_problem *prob, const snect_factors *f, int32_t trials, snect_exec *best,
                    double *best_ms);
 
-/* Autotuner of a batched sweep: times `trials` sweep epochs on scratch
+/* Autotuner of a sweep: times `trials` sweep epochs on scratch
  * copies of fs for every problem's record chunk scaled by 1, 1/2 and 1/4
  * (not below 256) and keeps the fastest for later snect_sweep_train calls
  * on these problems; *best_ms (may be NULL) receives its epoch time.

@@ -300,9 +300,10 @@ def _sweep_args(problems, factors):
 
 
 def sweep_train(ctx: "Context", problems, factors, epochs: int, start_epoch: int = 0):
-    """snect_sweep_train: all problems' strata of each epoch in one launch;
-    factors[i] = (A, B, C, G) torch tensors of problem i (updated in place).
-    Returns (loss, rmse), arrays of shape (n, epochs)."""
+    """snect_sweep_train: the problems trained together (bit-identical to
+    training each alone); factors[i] = (A, B, C, G) torch tensors of
+    problem i (updated in place).  Returns (loss, rmse), arrays of shape
+    (n, epochs)."""
     n, hs, fs = _sweep_args(problems, factors)
     loss = np.zeros((n, max(epochs, 1)))
     rmse = np.zeros((n, max(epochs, 1)))

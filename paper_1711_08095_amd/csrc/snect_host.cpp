@@ -171,6 +171,7 @@ struct snect_problem {
     // execution
     int path = SNECT_PATH_AUTO;
     bool per_launch = false;
+    hipStream_t stream_override = nullptr;  // a sweep's per-problem stream (else the context's)
     hipEvent_t ev[2][4] = {{nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr}};
     std::vector<hipEvent_t> evl;  // per-launch timing events, [2][2 * launches]
     double t_ms[5] = {0, 0, 0, 0, 0};
@@ -705,6 +706,12 @@ static int check_factors(snect_ctx* ctx, const snect_factors* f)
     return SNECT_OK;
 }
 
+// The stream a problem's work is queued on.
+static hipStream_t pstream(const snect_problem* pr)
+{
+    return pr->stream_override ? pr->stream_override : pr->ctx->stream;
+}
+
 static GraphArgs graph_args(const snect_problem* pr)
 {
     GraphArgs ga;
@@ -739,25 +746,25 @@ static int run_loss(snect_problem* pr, const float* C, const float* G, int slot 
     la.n_reg_wg = pr->n_reg_wg;
     la.lam = pr->lam; la.lam_g = pr->lam_g;
     GraphArgs ga = graph_args(pr);
-    HIP_TRY(launch_loss(la, ga, pr->jp, pr->loss_lds, pr->loss_cols_lds, pr->loss_parts, ctx->stream));
+    HIP_TRY(launch_loss(la, ga, pr->jp, pr->loss_lds, pr->loss_cols_lds, pr->loss_parts, pstream(pr)));
     HIP_TRY(hipMemcpyAsync(pr->h_lossout + 2 * slot, pr->d_lossout, 2 * sizeof(double), hipMemcpyDeviceToHost,
-                           ctx->stream));
+                           pstream(pr)));
     return SNECT_OK;
 }
 
 static int to_positions(snect_problem* pr, const snect_factors* f)
 {
     snect_ctx* ctx = pr->ctx;
-    HIP_TRY(launch_permute(f->A, pr->d_Ap, pr->d_perm1, pr->I1, pr->J1, 1, ctx->stream));
-    HIP_TRY(launch_permute(f->B, pr->d_Bp, pr->d_perm2, pr->I2, pr->J2, 1, ctx->stream));
+    HIP_TRY(launch_permute(f->A, pr->d_Ap, pr->d_perm1, pr->I1, pr->J1, 1, pstream(pr)));
+    HIP_TRY(launch_permute(f->B, pr->d_Bp, pr->d_perm2, pr->I2, pr->J2, 1, pstream(pr)));
     return SNECT_OK;
 }
 
 static int from_positions(snect_problem* pr, snect_factors* f)
 {
     snect_ctx* ctx = pr->ctx;
-    HIP_TRY(launch_permute(pr->d_Ap, f->A, pr->d_perm1, pr->I1, pr->J1, 0, ctx->stream));
-    HIP_TRY(launch_permute(pr->d_Bp, f->B, pr->d_perm2, pr->I2, pr->J2, 0, ctx->stream));
+    HIP_TRY(launch_permute(pr->d_Ap, f->A, pr->d_perm1, pr->I1, pr->J1, 0, pstream(pr)));
+    HIP_TRY(launch_permute(pr->d_Bp, f->B, pr->d_perm2, pr->I2, pr->J2, 0, pstream(pr)));
     return SNECT_OK;
 }
 
@@ -800,7 +807,7 @@ static StratArgs strat_args(const snect_problem* pr, const snect_factors* f)
 static int epoch_begin(snect_problem* pr, snect_factors* f, int slot = 0)
 {
     snect_ctx* ctx = pr->ctx;
-    hipStream_t st = ctx->stream;
+    hipStream_t st = pstream(pr);
     const size_t nA = (size_t)pr->I1 * pr->J1, nB = (size_t)pr->I2 * pr->J2, nC = (size_t)pr->I3 * pr->J3,
                  nG = (size_t)pr->J1 * pr->J2 * pr->J3;
     HIP_TRY(hipMemcpyAsync(pr->d_bakA + slot * nA, pr->d_Ap, 4 * nA, hipMemcpyDeviceToDevice, st));
@@ -829,8 +836,8 @@ static int persistent_inputs(snect_problem* pr, int32_t ep, int slot = 0)
     const std::vector<int32_t> order = stratum_order(pr->P, pr->seed, ep);
     int32_t* h = pr->h_order + (size_t)slot * pr->P;
     std::memcpy(h, order.data(), (size_t)pr->P * 4);
-    HIP_TRY(hipMemcpyAsync(pr->d_order, h, (size_t)pr->P * 4, hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(hipMemsetAsync(pr->d_bar, 0, sizeof(GridBar), ctx->stream));
+    HIP_TRY(hipMemcpyAsync(pr->d_order, h, (size_t)pr->P * 4, hipMemcpyHostToDevice, pstream(pr)));
+    HIP_TRY(hipMemsetAsync(pr->d_bar, 0, sizeof(GridBar), pstream(pr)));
     return SNECT_OK;
 }
 
@@ -838,12 +845,12 @@ static int persistent_inputs(snect_problem* pr, int32_t ep, int slot = 0)
 // grid barrier's state into slot `slot` (asynchronous).
 static int epoch_loss(snect_problem* pr, snect_factors* f, int slot = 0)
 {
-    HIP_TRY_CTX(pr->ctx, hipEventRecord(pr->ev[slot][2], pr->ctx->stream));
+    HIP_TRY_CTX(pr->ctx, hipEventRecord(pr->ev[slot][2], pstream(pr)));
     int rc = run_loss(pr, f->C, f->G, slot);
     if (rc) return rc;
     HIP_TRY_CTX(pr->ctx, hipMemcpyAsync(pr->h_bar + slot, pr->d_bar, sizeof(GridBar), hipMemcpyDeviceToHost,
-                                        pr->ctx->stream));
-    HIP_TRY_CTX(pr->ctx, hipEventRecord(pr->ev[slot][3], pr->ctx->stream));
+                                        pstream(pr)));
+    HIP_TRY_CTX(pr->ctx, hipEventRecord(pr->ev[slot][3], pstream(pr)));
     return SNECT_OK;
 }
 
@@ -855,7 +862,7 @@ static int epoch_finish(snect_problem* pr, snect_factors* f, int32_t ep, bool pe
                         double* rmse, int slot = 0)
 {
     snect_ctx* ctx = pr->ctx;
-    hipStream_t st = ctx->stream;
+    hipStream_t st = pstream(pr);
     HIP_TRY(hipEventSynchronize(pr->ev[slot][3]));
     if (persistent && pr->h_bar[slot].err) return set_err(ctx, SNECT_E_HIP, "grid barrier timed out in the stratum kernel");
     float m0 = 0, m1 = 0, m2 = 0;
@@ -963,6 +970,79 @@ int snect_train(snect_problem* pr, snect_factors* f, int32_t start_epoch, int32_
     return SNECT_OK;
 }
 
+// The sweep while its single batched launch is switched off: every problem
+// on a stream of its own (default priority), with the multi-launch driver
+// (a block-step launch and a core-step launch per stratum), the problems'
+// epochs queued side by side so that they run concurrently; the host checks
+// each epoch of every problem as snect_train does.  The results are those
+// of snect_train on each problem, bit for bit.  The sweep's record chunk
+// (snect_sweep_autotune) applies up to the problem's own.
+static int sweep_concurrent(snect_ctx* ctx, int32_t n, snect_problem* const* probs, snect_factors* fs,
+                            int32_t start_epoch, int32_t epochs, double* loss, double* rmse)
+{
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::vector<hipStream_t> sts(n, nullptr);
+    hipEvent_t start_ev = nullptr;
+    struct Cleanup {
+        std::vector<hipStream_t>& s;
+        snect_problem* const* p;
+        int32_t n;
+        hipEvent_t& e;
+        ~Cleanup()
+        {
+            for (int32_t i = 0; i < n; ++i) {
+                if (s[i]) (void)hipStreamSynchronize(s[i]);
+                p[i]->stream_override = nullptr;
+                if (s[i]) (void)hipStreamDestroy(s[i]);
+            }
+            if (e) (void)hipEventDestroy(e);
+        }
+    } cleanup{sts, probs, n, start_ev};
+    // the problem streams start after the work already queued on the
+    // context's stream (the callers' factors are written there)
+    HIP_TRY(hipEventCreateWithFlags(&start_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(start_ev, ctx->stream));
+    std::vector<StratArgs> sa(n);
+    for (int32_t i = 0; i < n; ++i) {
+        HIP_TRY(hipStreamCreateWithFlags(&sts[i], hipStreamNonBlocking));
+        HIP_TRY(hipStreamWaitEvent(sts[i], start_ev, 0));
+        snect_problem* pr = probs[i];
+        pr->stream_override = sts[i];
+        for (double& t : pr->t_ms) t = 0.0;
+        sa[i] = strat_args(pr, &fs[i]);
+        if (pr->sweep_rec_cap) sa[i].rec_cap = std::min(pr->sweep_rec_cap, pr->rec_cap);
+        int rc = to_positions(pr, &fs[i]);
+        if (rc) return rc;
+    }
+    int rc = SNECT_OK;
+    for (int32_t ep = start_epoch; ep < start_epoch + epochs && !rc; ++ep) {
+        for (int32_t i = 0; i < n && !rc; ++i) {
+            snect_problem* pr = probs[i];
+            if ((rc = epoch_begin(pr, &fs[i]))) break;
+            const std::vector<int32_t> order = stratum_order(pr->P, pr->seed, ep);
+            for (int si = 0; si < pr->P; ++si) {
+                sa[i].s = order[si];
+                HIP_TRY(launch_block(sa[i], pr->jp, pr->bf, pr->nw, pr->block_lds, sts[i]));
+                HIP_TRY(launch_core_step(sa[i], pr->core_lds, sts[i]));
+            }
+            rc = epoch_loss(pr, &fs[i]);
+        }
+        for (int32_t i = 0; i < n && !rc; ++i) {
+            const size_t o = (size_t)i * epochs + (ep - start_epoch);
+            rc = epoch_finish(probs[i], &fs[i], ep, false, loss ? loss + o : nullptr, rmse ? rmse + o : nullptr);
+            if (rc == SNECT_E_DIVERGED) ctx->err = "problem " + std::to_string(i) + ": " + ctx->err;
+        }
+    }
+    const std::string msg = ctx->err;
+    for (int32_t i = 0; i < n; ++i) (void)from_positions(probs[i], &fs[i]);
+    for (int32_t i = 0; i < n; ++i) {
+        const hipError_t e = hipStreamSynchronize(sts[i]);
+        if (e != hipSuccess && !rc) rc = set_err(ctx, SNECT_E_HIP, std::string("sweep: ") + hipGetErrorString(e));
+    }
+    if (rc != SNECT_E_HIP) ctx->err = msg;
+    return rc;
+}
+
 int snect_sweep_train(snect_ctx* ctx, int32_t n, snect_problem* const* probs, snect_factors* fs, int32_t start_epoch,
                       int32_t epochs, double* loss, double* rmse)
 {
@@ -982,11 +1062,8 @@ int snect_sweep_train(snect_ctx* ctx, int32_t n, snect_problem* const* probs, sn
         bf = pr->bf;
         nwg += pr->P;
     }
+    if (!kSweepEnabled) return sweep_concurrent(ctx, n, probs, fs, start_epoch, epochs, loss, rmse);
     if (!ctx->coop) return set_err(ctx, SNECT_E_UNSUPPORTED, "cooperative launches not available");
-    if (!kSweepEnabled)
-        return set_err(ctx, SNECT_E_UNSUPPORTED,
-                       "the batched sweep launch is switched off: its kernel took a GPU memory fault whose cause "
-                       "is not established; train the problems one by one with snect_train");
     // one launch of kDefaultWaves-wavefront workgroups; each problem keeps
     // its own core-size code, LDS layout and largest record chunk
     std::vector<int> rcap(n);

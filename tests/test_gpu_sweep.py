@@ -1,5 +1,5 @@
 """Execution choices (record chunk, driver), the autotuners and
-the batched sweep: every one of them must leave the results bit-identical
+the sweep: every one of them must leave the results bit-identical
 to a plain snect_train of the same problem."""
 import numpy as np
 import pytest
@@ -77,10 +77,11 @@ def _sweep_cases():
     return out
 
 
-@pytest.mark.skip(reason="batched sweep launch switched off: its first FP32 run after the LDS-layout change "
-                         "took a GPU memory-aperture fault with no established cause; kept off the GPU")
+@pytest.mark.skip(reason="the single batched sweep launch is switched off (the library's kSweepEnabled): its "
+                         "first FP32 run after the LDS-layout change took a GPU memory-aperture fault with no "
+                         "established cause; kept off the GPU")
 @pytest.mark.parametrize("precision", [0, 1])
-def test_sweep_equals_individual_training(ctx, precision):
+def test_batched_launch_equals_individual_training(ctx, precision):
     import paper_1711_08095_amd as sn
     cases = _sweep_cases()
     probs = [gpu_problem(ctx, c, precision=precision) for c in cases]
@@ -102,13 +103,38 @@ def test_sweep_equals_individual_training(ctx, precision):
             assert bool((x == y).all())
 
 
-def test_sweep_is_switched_off(ctx):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_concurrent_sweep_equals_individual_training(ctx, precision):
+    # with the batched launch switched off, the sweep runs every problem on
+    # its own stream with the multi-launch driver, concurrently
     import paper_1711_08095_amd as sn
-    cases = _sweep_cases()[:2]
-    probs = [gpu_problem(ctx, c) for c in cases]
-    with pytest.raises(sn.SnectError) as e:
-        sn.sweep_train(ctx, probs, [gpu_factors(c) for c in cases], 1)
-    assert e.value.code == -9
+    cases = _sweep_cases()
+    probs = [gpu_problem(ctx, c, precision=precision) for c in cases]
+    solo = [run_gpu(ctx, c, 3, prob=p) for c, p in zip(cases, probs)]
+    fs = [gpu_factors(c) for c in cases]
+    print(f"concurrent sweep, precision {precision}", flush=True)
+    loss, rmse = sn.sweep_train(ctx, probs, fs, 3)
+    for n, (c, s) in enumerate(zip(cases, solo)):
+        got = [t.double().cpu().numpy() for t in fs[n]]
+        _same(s, (got, loss[n], rmse[n]))
+    # resumed: 2 + 1 epochs equal 3
+    fs2 = [gpu_factors(c) for c in cases]
+    l1, _ = sn.sweep_train(ctx, probs, fs2, 2)
+    l2, _ = sn.sweep_train(ctx, probs, fs2, 1, start_epoch=2)
+    np.testing.assert_array_equal(np.concatenate([l1, l2], axis=1), loss)
+    for a, b in zip(fs, fs2):
+        for x, y in zip(a, b):
+            assert bool((x == y).all())
+    # the sweep autotuner changes execution only, and leaves the factors
+    fs3 = [gpu_factors(c) for c in cases]
+    before = [[t.clone() for t in f] for f in fs3]
+    ms = sn.sweep_autotune(ctx, probs, fs3, trials=1)
+    assert ms > 0
+    for a, b in zip(fs3, before):
+        for x, y in zip(a, b):
+            assert bool((x == y).all())
+    loss3, _ = sn.sweep_train(ctx, probs, fs3, 3)
+    np.testing.assert_array_equal(loss, loss3)
 
 
 def test_sweep_validation(ctx):
@@ -122,8 +148,6 @@ def test_sweep_validation(ctx):
     with pytest.raises(sn.SnectError) as e:
         sn.sweep_train(ctx, [p32, p32], [gpu_factors(cases[0]), gpu_factors(cases[0])], 1)
     assert e.value.code == -1
-    big = planted_case(seed=50, dims=(300, 900, 5), ranks=(5, 5, 2), nnz=20000, edges=100, P=200, T=64)
-    pbig = gpu_problem(ctx, big)
     with pytest.raises(sn.SnectError) as e:
-        sn.sweep_train(ctx, [pbig, gpu_problem(ctx, big)], [gpu_factors(big), gpu_factors(big)], 1)
-    assert e.value.code == -9
+        sn.sweep_train(ctx, [p32], [gpu_factors(cases[0])], -1)
+    assert e.value.code == -1
