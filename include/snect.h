@@ -280,7 +280,7 @@ int snect_set_exec(snect_problem *prob, const snect_exec *exec);
  * run concurrently; the streams start after the work already queued on the
  * context's stream, and the call waits for them before it returns.  The
  * single cooperative launch per epoch for all problems (problem i on P_i
- * workgroups with its own grid barrier) is switched off until the cause of
+ * workgroups with its own exchange words) is switched off until the cause of
  * a GPU memory fault seen in its kernel is established.
  *
  * Errors: E_ARG, E_OOM, E_HIP, E_DIVERGED (the message names the problem;

@@ -22,6 +22,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -157,6 +158,8 @@ struct snect_problem {
     float *d_adj_w = nullptr, *d_deg = nullptr;
     float *d_Ap = nullptr, *d_Bp = nullptr, *d_Btmp = nullptr;
     float *d_Spart = nullptr, *d_Ssum = nullptr;
+    unsigned long long* d_Sx = nullptr;  // the persistent kernel's tagged exchange words
+    uint32_t tag_next = 0;               // tags handed out so far (see take_tags)
     int32_t* d_blk_rec = nullptr;  // [P*P+1] first record of each block
     float* d_ccst = nullptr;       // [P][kCstHead+I3] core-step constants per stratum
     int32_t* d_order = nullptr;  // [P]
@@ -165,7 +168,7 @@ struct snect_problem {
     // Per-epoch state comes in two slots (epoch parity), so that the next
     // epoch can be queued before the previous one is checked.
     double* h_lossout = nullptr;  // pinned [2][2]: f_opt, sum of squared errors
-    GridBar* h_bar = nullptr;     // pinned [2]: the grid barrier after the epoch
+    GridBar* h_bar = nullptr;     // pinned [2]: the exchange's error word after the epoch
     int32_t* h_order = nullptr;   // pinned [2][P]
     float *d_bakA = nullptr, *d_bakB = nullptr, *d_bakC = nullptr, *d_bakG = nullptr;  // [2] each
     // execution
@@ -603,6 +606,7 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         pr->d_Btmp = pr->alloc<float>((size_t)I2 * J2, rc);
         pr->d_Spart = pr->alloc<float>((size_t)P * ni, rc);
         pr->d_Ssum = pr->alloc<float>(std::max(ni, ng), rc);
+        pr->d_Sx = pr->alloc<unsigned long long>((size_t)(P + 1) * ni + P, rc);
         pr->d_blk_rec = pr->alloc<int32_t>((size_t)P * P + 1, rc);
         pr->d_ccst = pr->alloc<float>((size_t)P * (kCstHead + I3), rc);
         pr->d_order = pr->alloc<int32_t>(P, rc);
@@ -650,6 +654,8 @@ int snect_problem_create(snect_ctx* ctx, const snect_tensor* X, const snect_grap
         he = he ? he : up(pr->d_adj_nbr, adj_nbr.data(), adj_nbr.size() * 4);
         he = he ? he : up(pr->d_adj_w, adj_w.data(), adj_w.size() * 4);
         he = he ? he : up(pr->d_deg, deg.data(), (size_t)I2 * 4);
+        // exchange words start with tag 0, which no stratum uses
+        he = he ? he : hipMemsetAsync(pr->d_Sx, 0, ((size_t)(P + 1) * ni + P) * sizeof(unsigned long long), st);
         he = he ? he : hipStreamSynchronize(st);
         he = he ? he : prepare_kernels(jp, llds, clds, pr->loss_cols_lds);
         he = he ? he : configure_exec(pr, kDefaultWaves, rec_cap);
@@ -784,6 +790,18 @@ int snect_evaluate(snect_problem* pr, const snect_factors* f, double* loss, doub
     return SNECT_OK;
 }
 
+// Tags of the next persistent launch of a problem: its strata write tags
+// t0 + 1 .. t0 + P (returned: t0).  Consecutive launches get disjoint ranges
+// and 0 is never handed out, so no exchange word left by an earlier launch
+// (or by the initial clear) carries a tag of the current one.
+static uint32_t take_tags(snect_problem* pr)
+{
+    if (pr->tag_next > UINT32_MAX - (uint32_t)pr->P) pr->tag_next = 0;
+    const uint32_t t0 = pr->tag_next;
+    pr->tag_next += (uint32_t)pr->P;
+    return t0;
+}
+
 static StratArgs strat_args(const snect_problem* pr, const snect_factors* f)
 {
     StratArgs sa;
@@ -792,6 +810,7 @@ static StratArgs strat_args(const snect_problem* pr, const snect_factors* f)
     sa.reg1 = pr->d_reg1; sa.reg2 = pr->d_reg2; sa.cnt3 = pr->d_cnt3;
     sa.Ap = pr->d_Ap; sa.Bp = pr->d_Bp; sa.C = f->C; sa.G = f->G;
     sa.Spart = pr->d_Spart; sa.blk_rec = pr->d_blk_rec; sa.ccst = pr->d_ccst; sa.Ssum = pr->d_Ssum;
+    sa.Sx = pr->d_Sx; sa.tag0 = 0;
     sa.order = pr->d_order; sa.bar = pr->d_bar; sa.jp = pr->jp;
     sa.P = pr->P; sa.s = 0; sa.I3 = pr->I3; sa.J1 = pr->J1; sa.J2 = pr->J2; sa.J3 = pr->J3;
     sa.rows1_max = pr->rows1_max; sa.rows2_max = pr->rows2_max; sa.bits_i = pr->bits_i; sa.bits_j = pr->bits_j;
@@ -829,7 +848,7 @@ static int epoch_begin(snect_problem* pr, snect_factors* f, int slot = 0)
 
 // The persistent driver's per-epoch inputs: the stratum order (through
 // pinned slot `slot`, whose previous upload finished before the epoch two
-// back was checked) and a cleared grid barrier.
+// back was checked) and a cleared error word.
 static int persistent_inputs(snect_problem* pr, int32_t ep, int slot = 0)
 {
     snect_ctx* ctx = pr->ctx;
@@ -842,7 +861,7 @@ static int persistent_inputs(snect_problem* pr, int32_t ep, int slot = 0)
 }
 
 // After the strata: the loss launch and the downloads of the loss and of the
-// grid barrier's state into slot `slot` (asynchronous).
+// exchange's error word into slot `slot` (asynchronous).
 static int epoch_loss(snect_problem* pr, snect_factors* f, int slot = 0)
 {
     HIP_TRY_CTX(pr->ctx, hipEventRecord(pr->ev[slot][2], pstream(pr)));
@@ -864,7 +883,7 @@ static int epoch_finish(snect_problem* pr, snect_factors* f, int32_t ep, bool pe
     snect_ctx* ctx = pr->ctx;
     hipStream_t st = pstream(pr);
     HIP_TRY(hipEventSynchronize(pr->ev[slot][3]));
-    if (persistent && pr->h_bar[slot].err) return set_err(ctx, SNECT_E_HIP, "grid barrier timed out in the stratum kernel");
+    if (persistent && pr->h_bar[slot].err) return set_err(ctx, SNECT_E_HIP, "the stratum kernel timed out waiting for another workgroup");
     float m0 = 0, m1 = 0, m2 = 0;
     HIP_TRY(hipEventElapsedTime(&m0, pr->ev[slot][0], pr->ev[slot][1]));
     HIP_TRY(hipEventElapsedTime(&m1, pr->ev[slot][1], pr->ev[slot][2]));
@@ -948,6 +967,7 @@ int snect_train(snect_problem* pr, snect_factors* f, int32_t start_epoch, int32_
         if (persistent) {
             if ((rc = persistent_inputs(pr, ep, slot))) return rc;
             if (el) HIP_TRY(hipEventRecord(el[0], st));
+            sa.tag0 = take_tags(pr);
             HIP_TRY(launch_strata_persistent(sa, pr->jp, pr->bf, pr->nw, pr->strata_lds, st));
             if (el) HIP_TRY(hipEventRecord(el[1], st));
         } else {
@@ -1113,6 +1133,12 @@ int snect_sweep_train(snect_ctx* ctx, int32_t n, snect_problem* const* probs, sn
     for (int32_t ep = start_epoch; ep < start_epoch + epochs && !rc; ++ep) {
         for (int i = 0; i < n && !rc; ++i) rc = epoch_begin(probs[i], &fs[i]);
         for (int i = 0; i < n && !rc; ++i) rc = persistent_inputs(probs[i], ep);
+        // fresh tags: the arguments again (a pageable copy, done with the
+        // host array when it returns)
+        for (int i = 0; i < n; ++i) args[i].tag0 = take_tags(probs[i]);
+        if (!rc && (e = hipMemcpyAsync(d_args, args.data(), sizeof(StratArgs) * n, hipMemcpyHostToDevice, st)) !=
+                       hipSuccess)
+            rc = set_err(ctx, SNECT_E_HIP, std::string("sweep arguments: ") + hipGetErrorString(e));
         if (!rc) {
             e = launch_strata_sweep(static_cast<const StratArgs*>(d_args), d_wg, n, nwg, bf, lds, st);
             if (e != hipSuccess) rc = set_err(ctx, SNECT_E_HIP, std::string("sweep launch: ") + hipGetErrorString(e));

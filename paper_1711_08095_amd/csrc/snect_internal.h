@@ -46,12 +46,11 @@ __host__ __device__ constexpr int row_stride(int jp) { return (jp + 3) & ~3; }
 __host__ __device__ constexpr int strat_row_stride(int jp, int bf) { return bf ? ((jp + 3) & ~3) : (jp | 1); }
 __host__ __device__ constexpr int mfma_dim(int jp) { return jp <= 16 ? 16 : 32; }
 
-// Grid barrier state of the persistent kernel (zeroed before each launch).
+// Error word of the persistent kernel's exchange (zeroed before each launch;
+// nonzero once a workgroup gave up waiting).
 struct GridBar {
-    unsigned int count;
-    unsigned int gen;
     unsigned int err;
-    unsigned int pad;
+    unsigned int pad[3];
 };
 
 // Everything the stratum kernels read or write.  Factor rows are in plan
@@ -74,9 +73,15 @@ struct StratArgs {
     float* Spart;              // [P][I3*J1*J2] per-block sums of e a (x) b
     const int32_t* blk_rec;    // [P*P+1] first record of each block (and nnz at the end)
     const float* ccst;         // [P][I3+3] core-step constants of each stratum (fixed by the plan)
-    float* Ssum;               // [I3*J1*J2] stratum sums (persistent kernel)
+    float* Ssum;               // [max(I3*J1*J2, J1*J2*J3)] the multi-launch core step's new G
+    // persistent kernel: tagged exchange words (high half the stratum's tag,
+    // low half a float): [P][I3*J1*J2] block sums, [I3*J1*J2] stratum sums,
+    // [P] "rows stored" word of each patient block; stratum si of the launch
+    // writes tag tag0 + si + 1
+    unsigned long long* Sx;
     const int32_t* order;      // [P] stratum order of this epoch
     GridBar* bar;
+    uint32_t tag0;
     int32_t jp;                // kernel instantiation of this problem's core
     int32_t P, s, I3, J1, J2, J3;
     int32_t rows1_max, rows2_max;

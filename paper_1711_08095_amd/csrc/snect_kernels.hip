@@ -32,10 +32,10 @@
 // Two drivers share that block step and all of the arithmetic:
 //   strata_persistent: one cooperative launch per epoch; P workgroups stay
 //     resident, workgroup q keeps gene block q in LDS for the whole epoch and
-//     visits patient block (q - s) mod P in stratum s; two grid barriers per
-//     stratum bracket a distributed reduction of the blocks' sums, after
-//     which every workgroup applies the same core step to its LDS copy of C
-//     and G;
+//     visits patient block (q - s) mod P in stratum s; the blocks' sums are
+//     reduced by all workgroups (each its share), handed over in tagged
+//     words that the readers poll, after which every workgroup applies the
+//     same core step to its LDS copy of C and G;
 //   block_step + core_step: one launch per stratum plus one for the core step
 //     (used when the persistent kernel cannot be co-resident).
 // Both give bit-identical results.
@@ -60,11 +60,16 @@ __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~size_t(
 // (bounds how many LDS values the scheduler keeps in flight).
 __device__ inline void lds_order_fence() { asm volatile("" ::: "memory"); }
 
+// wg_count call sites (each with its own slots): chunk loads, the two polls,
+// the reduction passes, the prefetched chunk's tile count
+constexpr int kWgSites = 5;
+enum { kWgChunk = 0, kWgPoll1 = 1, kWgPoll2 = 2, kWgReduce = 3, kWgPre = 4 };
+
 // ---------------------------------------------------------------------------
 // LDS carve-up of the stratum kernels (in 4-byte words).
 // ---------------------------------------------------------------------------
 struct StratLds {
-    int a, b, ra, rb, c, g, h, ht, as, es, xtp, stg, sk, tco, tck, red, cst, cgt, flag, sch, rec;
+    int a, b, ra, rb, c, g, h, ht, as, es, xtp, stg, sk, tco, tck, red, cst, cgt, sch, rec, wgs;
     int hb, sw1, sw2, xts, esl, a16, e16;  // BF16 path only (zero-sized otherwise)
     int total;
 };
@@ -104,9 +109,9 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int P, int rows1_ma
     L.red = o;   o = up4(o + 64 * nw);
     L.cst = o;   o = up4(o + kCstHead + I3);        // core-step constants of the stratum
     L.cgt = o;   o = up4(o + I3 * J3 + j12 * J3);
-    L.flag = o;  o = up4(o + 1);
     L.sch = o;   o = up4(o + 7 * P);                // the epoch's schedule of this workgroup
     L.rec = o;   o = up4(o + 2 * rec_cap);
+    L.wgs = o;   o = up4(o + kWgSites * kDefaultWaves);  // slots of wg_count
     L.total = o;
     return L;
 }
@@ -165,7 +170,8 @@ __device__ void build_hb(__bf16* Hb, const float* Hs, int I3, int J1, int J2, in
 // Device-coherent accesses, for data that other workgroups of the same
 // launch write or read: agent-scope relaxed atomics, which bypass the
 // non-coherent L2 of the accessing XCD (global_load / global_store with sc1).
-// With them the grid barrier needs no L2 writeback or invalidation.
+// With them the persistent kernel's exchanges need no L2 writeback or
+// invalidation.
 __device__ inline float ld_coh(const float* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 __device__ inline void st_coh(float* p, float v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
@@ -194,10 +200,9 @@ __device__ inline float chunk_sum(const float* Spart, int ni, int item, int p0, 
 }
 
 // Sums items [i0, i1) of the stratum into dst[item - i0] using the whole
-// workgroup (red: nthr floats of LDS); dst_coh: dst is read by other
-// workgroups of the launch (device-coherent stores).
-__device__ void reduce_items(const float* Spart, int P, int ni, int i0, int i1, float* dst, bool dst_coh, float* red,
-                             int tid, int nthr)
+// workgroup (red: nthr floats of LDS).
+__device__ void reduce_items(const float* Spart, int P, int ni, int i0, int i1, float* dst, float* red, int tid,
+                             int nthr)
 {
     const int nch = (P + kRedChunk - 1) / kRedChunk;
     const int per_pass = nthr / nch > 0 ? nthr / nch : 1;
@@ -213,10 +218,7 @@ __device__ void reduce_items(const float* Spart, int P, int ni, int i0, int i1, 
         if (tid < items) {
             float s = 0.f;
             for (int ch = 0; ch < nch; ++ch) s += red[tid * nch + ch];
-            if (dst_coh)
-                st_coh(dst + base + tid - i0, s);
-            else
-                dst[base + tid - i0] = s;
+            dst[base + tid - i0] = s;
         }
     }
     __syncthreads();
@@ -251,6 +253,7 @@ __device__ void core_update(const float* C0, const float* G0, const float* S, co
         float v = 0.f;
         if (item < nc) {
             const int k = item / J3, c = item - k * J3;
+#pragma unroll 8
             for (int ab = g16; ab < J12; ab += 16) v = fmaf(-G0[ab * J3 + c], S[k * J12 + ab], v);
         }
         v = row_sum16(v);
@@ -263,6 +266,7 @@ __device__ void core_update(const float* C0, const float* G0, const float* S, co
     for (int idx = tid; idx < J12 * J3; idx += nthr) {
         const int ab = idx / J3, c = idx - ab * J3;
         float g = 0.f;
+#pragma unroll 8
         for (int k = 0; k < I3; ++k) g = fmaf(-S[k * J12 + ab], C0[k * J3 + c], g);
         g = fmaf(greg, G0[idx], g);
         newG[idx] = fmaf(-etac, g * inv_m, G0[idx]);
@@ -573,7 +577,25 @@ struct TileLds {
     float* St;    // [kMfmaWaves][J1*J2] staged partial sums of one platform
     int *tco, *tck;
     uint2* rec;   // [rec_cap] staged records
+    int* wgs;     // [kWgSites][kDefaultWaves] slots of wg_count
 };
+
+// Number of threads of the workgroup (NW wavefronts) whose pred holds, in
+// every thread: one workgroup barrier; each wavefront posts the population
+// count of its ballot to its own word of slots[NW].  Every call site has its
+// own slots, and a workgroup barrier separates the reads of one call from
+// the writes of the next at the same site.
+template <int NW>
+__device__ inline int wg_count(bool pred, int* slots)
+{
+    const unsigned long long b = __ballot(pred);
+    if ((threadIdx.x & 63) == 0) slots[threadIdx.x >> 6] = __popcll(b);
+    __syncthreads();
+    int n = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) n += slots[w];
+    return n;
+}
 
 // Tile metadata and records of the chunk of tiles starting at `base` (up to
 // kTileCache tiles whose records fit in rec_cap) into LDS; returns the
@@ -583,7 +605,8 @@ __device__ inline int load_chunk(const StratArgs& a, const TileLds& L, int base,
     load_tile_cache(a, L.tco, L.tck, base, t1, tid, nthr);
     __syncthreads();
     const int ntc = (t1 - base) < kTileCache ? (t1 - base) : kTileCache;
-    const int cend = __syncthreads_count(tid < ntc && L.tco[tid + 1] - L.tco[0] <= a.rec_cap);
+    const int cend =
+        wg_count<kDefaultWaves>(tid < ntc && L.tco[tid + 1] - L.tco[0] <= a.rec_cap, L.wgs + kWgChunk * kDefaultWaves);
     const int z0 = L.tco[0], nrec = L.tco[cend] - z0;
     load_records(L.rec, a.nz + z0, nrec, tid, nthr);
     __syncthreads();
@@ -1286,49 +1309,120 @@ __device__ void block_tiles_bf(const StratArgs& a, int t0, int t1, const TileLds
 }
 
 // ---------------------------------------------------------------------------
-// Grid barrier for the persistent kernel: a monotone arrival counter (zeroed
-// before the launch).  Barrier number b of the launch is passed when the
-// counter reaches nblocks * b; nobody resets anything, so the last arrival
-// releases the others by itself.  Everything workgroups exchange across it
-// (patient rows, block sums, stratum sums) is written and read with the
-// device-coherent accesses above, and every wavefront waits for its stores
-// (coh_stores_done) before the workgroup barrier that precedes the arrival;
-// so the arrival and the polls are relaxed atomics and no L2 writeback or
-// invalidation is needed (those cost about 4 us per barrier on this chip).
-// Global loads issued before the barrier stay in flight across it.  Returns
-// false (for every thread of the workgroup) if the barrier gave up: another
-// workgroup timed out, or this one waited far longer than any stratum can
-// take.
+// Tagged exchange of the persistent kernel.  What workgroups hand to each
+// other within a stratum (the blocks' sums, the reduced stratum sums and a
+// "rows stored" word per patient block) travels in 64-bit words: the float's
+// bits in the low half and the stratum's tag in the high half, written by
+// one device-coherent 64-bit store, so a reader that sees the tag sees the
+// value.  Readers poll the words they need (reloading only those that still
+// carry an older tag) instead of meeting at a grid barrier: no writer waits
+// for its stores to be performed before it goes on, and a reader's wait and
+// its load are one round trip.  Tags are unique per stratum and launch (the
+// host hands every launch a fresh range), and every word is rewritten in
+// every stratum, so an old word never carries a current tag.  A word is
+// rewritten only after everyone who reads it has read it: block sums of the
+// next stratum follow their writer's read of all stratum sums, which follow
+// every reducer's read of the block sums; stratum sums of the next stratum
+// follow every workgroup's next block sums.
+//
+// Patient rows are plain device-coherent stores; their writer stores the
+// block's "rows stored" word only after its rows have been performed
+// (coh_stores_done, after the reduction, when they long have been), and the
+// next stratum's reader loads them only after it has seen that word.
+//
+// Every poll is bounded: after kSpinLimit rounds (far longer than any
+// stratum can take) the poller sets the error word and gives up, and every
+// poller gives up once it sees the error word set (checked every 128
+// rounds); the workgroup then leaves the launch.
 // ---------------------------------------------------------------------------
 constexpr unsigned kSpinLimit = 1u << 25;
+constexpr int kSumPoll = 4;  // stratum sums each thread polls per round
+constexpr int kRowPre = 2;   // patient-row values per thread requested before the core step
 
-__device__ bool grid_sync(GridBar* bar, unsigned nblocks, unsigned& nbar, int* flag)
+__device__ inline void st_tag(unsigned long long* p, float v, unsigned tag)
 {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        const unsigned target = nblocks * ++nbar;
-        __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // one coherent load per poll; the error flag (another workgroup gave
-        // up) every 128 polls
-        unsigned spins = 0;
-        while (__hip_atomic_load(&bar->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if ((++spins & 127u) == 0u) {
-                if (spins > kSpinLimit) {
-                    atomicOr(&bar->err, 1u);
-                    ok = 0;
-                    break;
-                }
-                if (__hip_atomic_load(&bar->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                    ok = 0;
-                    break;
-                }
+    __hip_atomic_store(p, ((unsigned long long)tag << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline unsigned long long ld_tag(unsigned long long* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline float tag_value(unsigned long long x) { return __uint_as_float((unsigned)x); }
+
+// Polls the words x[u] = p[u * stride] (u < n <= N, bit u of skip clear)
+// and xe = *pe (unless pe is null) until each carries `tag`; the others
+// read as 0.0 with the tag.  Every round reloads, in flight together, the
+// words still behind.  False if the poll gave up (see above).
+template <int N>
+__device__ bool poll_tagged(unsigned long long (&x)[N], unsigned long long* p, int stride, int n, unsigned skip,
+                            unsigned long long& xe, unsigned long long* pe, unsigned tag, GridBar* bar)
+{
+    const unsigned long long fresh = (unsigned long long)tag << 32;
+#pragma unroll
+    for (int u = 0; u < N; ++u) x[u] = u < n && !((skip >> u) & 1u) ? ld_tag(p + (size_t)u * stride) : fresh;
+    xe = pe ? ld_tag(pe) : fresh;
+    unsigned spins = 0;
+    for (;;) {
+        bool done = (unsigned)(xe >> 32) == tag;
+#pragma unroll
+        for (int u = 0; u < N; ++u) done = done && (unsigned)(x[u] >> 32) == tag;
+        if (done) return true;
+        if ((++spins & 127u) == 0u) {
+            if (spins > kSpinLimit) {
+                atomicOr(&bar->err, 1u);
+                return false;
             }
+            if (__hip_atomic_load(&bar->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
         }
-        *flag = ok;
+#pragma unroll
+        for (int u = 0; u < N; ++u)
+            if ((unsigned)(x[u] >> 32) != tag) x[u] = ld_tag(p + (size_t)u * stride);
+        if ((unsigned)(xe >> 32) != tag) xe = ld_tag(pe);
+    }
+}
+
+// Items [i0, i1) of the stratum sums from the tagged block sums Sx ([P][ni])
+// into dst (tagged, device-coherent) and own[i0..i1), in the order of
+// reduce_items, using the whole workgroup (red: nthr floats of LDS, slots:
+// those of a wg_count site, kDefaultWaves wavefronts).  The
+// sums of block pown are not polled but read from own (this workgroup's
+// block).  False (for every thread) if a poll gave up.
+__device__ bool reduce_items_tagged(unsigned long long* Sx, int P, int ni, int i0, int i1, unsigned long long* dst,
+                                    float* own, int pown, unsigned tag, GridBar* bar, float* red, int* slots, int tid,
+                                    int nthr)
+{
+    const int nch = (P + kRedChunk - 1) / kRedChunk;
+    const int per_pass = nthr / nch > 0 ? nthr / nch : 1;
+    for (int base = i0; base < i1; base += per_pass) {
+        const int items = (i1 - base) < per_pass ? (i1 - base) : per_pass;
+        const bool act = tid < items * nch;
+        const int it = act ? tid / nch : 0, ch = act ? tid - it * nch : 0;
+        const int p0 = ch * kRedChunk;
+        // four words per poll (this path serves large cores only)
+        float s = 0.f;
+        bool ok = true;
+        for (int g = 0; g < kRedChunk; g += 4) {
+            const int n = act ? (P - p0 - g < 4 ? (P - p0 - g > 0 ? P - p0 - g : 0) : 4) : 0;
+            const int so = pown - p0 - g;  // the own block's word in this group
+            const unsigned skip = so >= 0 && so < 4 ? 1u << so : 0u;
+            unsigned long long x[4], xe;
+            ok = ok && poll_tagged<4>(x, Sx + (size_t)(p0 + g) * ni + base + it, ni, n, skip, xe, nullptr, tag, bar);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s += u == so && u < n ? own[base + it] : tag_value(x[u]);
+        }
+        if (wg_count<kDefaultWaves>(!ok, slots) != 0) return false;
+        if (act) red[tid] = s;
+        __syncthreads();
+        if (tid < items) {
+            float s = 0.f;
+            for (int c = 0; c < nch; ++c) s += red[tid * nch + c];
+            st_tag(dst + base + tid - i0, s, tag);
+            own[base + tid] = s;
+        }
     }
     __syncthreads();
-    return *flag != 0;
+    return true;
 }
 
 // Workgroups are dispatched to the XCDs round-robin (workgroup q runs on XCD
@@ -1366,6 +1460,7 @@ __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
     L.tco = reinterpret_cast<int*>(lds + S.tco);
     L.tck = reinterpret_cast<int*>(lds + S.tck);
     L.rec = reinterpret_cast<uint2*>(lds + S.rec);
+    L.wgs = reinterpret_cast<int*>(lds + S.wgs);
     return L;
 }
 
@@ -1373,12 +1468,12 @@ __device__ inline TileLds tile_lds(float* lds, const StratLds& S)
 // by other workgroups of this launch, into LDS rows of stride RS
 // (device-coherent loads, eight in flight per thread).
 __device__ inline void load_rows_coh(float* dst, const float* src, int row0, int nrows, int J, int RS, int tid,
-                                     int nthr)
+                                     int nthr, int from = 0)
 {
     constexpr int U = 8;
     const float* s = src + (size_t)row0 * J;
     const int total = nrows * J;
-    for (int base = tid; base < total; base += U * nthr) {
+    for (int base = from + tid; base < total; base += U * nthr) {
         float v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1412,24 +1507,25 @@ __device__ inline void store_rows_coh(float* dst, const float* src, int row0, in
 // Every stratum of one epoch of one problem, run by its workgroup q (gene
 // block q) of the problem's P co-resident workgroups.  The epoch's schedule
 // (stratum order, and for each stratum the block's tile range, record range
-// and patient rows) is read into LDS once.  Per stratum:
+// and patient rows) is read into LDS once.  Per stratum (exchanges tagged,
+// see poll_tagged):
 //   H_k from the current C, G; the block's tiles (its first record chunk and
-//   tile metadata already in LDS); its patient rows and sums of e a (x) b out
-//   (coherent stores); the next block's tile metadata and first record chunk
-//   requested (read-only data, in flight across the barrier);
-//   -- grid barrier --
-//   this workgroup's share of the stratum sums (coherent loads of the
-//   partials, fixed order) and the next block's patient rows in one round of
-//   loads; the prefetched chunk into LDS; the share out (coherent stores);
-//   -- grid barrier --
-//   the stratum sums in (coherent loads) and the same C/G step in every
+//   tile metadata already in LDS); its patient rows (coherent stores) and
+//   sums of e a (x) b (tagged) out; the next block's tile metadata and first
+//   record chunk requested (read-only data, in flight during the waits);
+//   this workgroup's share of the stratum sums: the blocks' sums polled, then
+//   added in a fixed order; the prefetched chunk and the stratum's core-step
+//   constants into LDS; the share (tagged) and, once this workgroup's rows
+//   have been performed, its "rows stored" word out;
+//   every stratum sum and the next block's "rows stored" word polled; that
+//   block's patient rows in (coherent loads); the same C/G step in every
 //   workgroup, on its LDS copy.
 template <int JP, bool BF, int NW>
 __device__ void strata_body(const StratArgs& a, int q, float* lds)
 {
     constexpr int RS = strat_row_stride(JP, BF ? 1 : 0);
     constexpr int NT = 64 * NW;
-    const int tid = threadIdx.x;
+    const int tid0 = threadIdx.x;
     const int P = a.P, I3 = a.I3, J1 = a.J1, J2 = a.J2, J3 = a.J3, J12 = J1 * J2;
     const int ni = I3 * J12;
     const StratLds S = strat_lds_layout(JP, P, a.rows1_max, a.rows2_max, I3, J1, J2, J3, a.rec_cap, BF ? 1 : 0, NW);
@@ -1443,15 +1539,14 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
     float* cgt = lds + S.cgt;
     float* Cn = cgt;            // C and G after the stratum's core step
     float* Gn = cgt + I3 * J3;
-    int* flag = reinterpret_cast<int*>(lds + S.flag);
     // schedule of stratum index si: [0] first tile, [1] tile end, [2] first
     // record, [3] record end, [4] first patient row, [5] patient row end,
     // [6] the stratum s (at sch[x * P + si])
     int* sch = reinterpret_cast<int*>(lds + S.sch);
 
-    for (int idx = tid; idx < a.rows1_max * RS; idx += NT) lds[S.a + idx] = 0.f;
-    for (int idx = tid; idx < a.rows2_max * RS; idx += NT) lds[S.b + idx] = 0.f;
-    for (int si = tid; si < P; si += NT) {
+    for (int idx = tid0; idx < a.rows1_max * RS; idx += NT) lds[S.a + idx] = 0.f;
+    for (int idx = tid0; idx < a.rows2_max * RS; idx += NT) lds[S.b + idx] = 0.f;
+    for (int si = tid0; si < P; si += NT) {
         const int s = a.order[si], p = (q - s + P) % P, b = p * P + q;
         sch[si] = a.blk_tile[b];
         sch[P + si] = a.blk_tile[b + 1];
@@ -1463,17 +1558,21 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
     }
     __syncthreads();
     const int s2 = a.start2[q], r2 = a.start2[q + 1] - s2;
-    load_rows(L.Bb, a.Bp, s2, r2, J2, RS, tid, NT);
-    for (int l = tid; l < r2; l += NT) lds[S.rb + l] = a.reg2[s2 + l];
-    for (int idx = tid; idx < I3 * J3; idx += NT) Cs[idx] = a.C[idx];
-    for (int idx = tid; idx < J12 * J3; idx += NT) Gs[idx] = a.G[idx];
+    load_rows(L.Bb, a.Bp, s2, r2, J2, RS, tid0, NT);
+    for (int l = tid0; l < r2; l += NT) lds[S.rb + l] = a.reg2[s2 + l];
+    for (int idx = tid0; idx < I3 * J3; idx += NT) Cs[idx] = a.C[idx];
+    for (int idx = tid0; idx < J12 * J3; idx += NT) Gs[idx] = a.G[idx];
     {
         const int s1 = sch[4 * P], r1 = sch[5 * P] - s1;
-        load_rows_coh(L.Ab, a.Ap, s1, r1, J1, RS, tid, NT);
-        for (int l = tid; l < r1; l += NT) lds[S.ra + l] = a.reg1[s1 + l];
+        load_rows_coh(L.Ab, a.Ap, s1, r1, J1, RS, tid0, NT);
+        for (int l = tid0; l < r1; l += NT) lds[S.ra + l] = a.reg1[s1 + l];
     }
-    unsigned nbar = 0;  // grid barriers passed so far (thread 0)
     __syncthreads();
+    // tagged exchange words: the blocks' sums [P][ni], the stratum sums [ni],
+    // the "rows stored" word of each patient block [P]
+    unsigned long long* Xpart = a.Sx;
+    unsigned long long* Xsum = a.Sx + (size_t)P * ni;
+    unsigned long long* Xrows = Xsum + ni;
 
     // this workgroup's share of the stratum reduction: consecutive shares go
     // to workgroups on the same XCD, so each XCD fetches its own contiguous
@@ -1481,22 +1580,30 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
     const int r = xcd_slot(q, P);
     const int i0 = (int)(((long long)ni * r) / P), i1 = (int)(((long long)ni * (r + 1)) / P);
     const int nchr = (P + kRedChunk - 1) / kRedChunk;
-    // item and chunk of this thread's share: consecutive lanes take
-    // consecutive items of one chunk (coalesced loads)
     const int nitems = i1 - i0 > 0 ? i1 - i0 : 1;
-    const int rch = tid / nitems, rit = tid - rch * nitems;
     const bool one = (i1 - i0) * nchr <= NT;
-    // the next stratum's first chunk is requested by wavefronts 1.. (wavefront
-    // 0 arrives at the grid barrier and polls it)
-    constexpr int kPreRec = (kMaxRecCap + NT - 65) / (NT - 64);  // records per thread
-    constexpr int kPreTc = (kTileCache + NT - 64) / (NT - 64);    // tile entries per thread (of kTileCache + 1)
-    const int pt = tid - 64;
+    // the next stratum's first chunk is requested by wavefronts 2.. (the
+    // reduction share is polled by its first (i1 - i0) * nchr threads:
+    // wavefronts 0 and 1 at the PanCan-sized cores)
+    constexpr int kPreRec = (kMaxRecCap + NT - 129) / (NT - 128);  // records per thread
+    constexpr int kPreTc = (kTileCache + NT - 128) / (NT - 128);    // tile entries per thread (of kTileCache + 1)
     int pre_cend = 0;  // tiles of this stratum's first chunk already in LDS
 
     for (int si = 0; si < P; ++si) {
+        // the thread index, opaque to the compiler in every stratum: what is
+        // derived from it is formed here, not hoisted out of the loop and
+        // held (spilled) across the tiles (the BF16 tile step, measured
+        // faster with its values hoisted, takes the plain index)
+        int tid = tid0;
+        asm volatile("" : "+v"(tid));
+        // item and chunk of this thread's share of the reduction: consecutive
+        // lanes take consecutive items of one chunk (coalesced loads)
+        const int rch = tid / nitems, rit = tid - rch * nitems;
+        const int pt = tid - 128;
         const int s = sch[6 * P + si];
         const int p = (q - s + P) % P;
         const int s1 = sch[4 * P + si], r1 = sch[5 * P + si] - s1;
+        const unsigned tg = a.tag0 + (unsigned)si + 1u;  // this stratum's tag
         build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT, (!BF && JP > 12) ? lds + S.ht : nullptr);
         if constexpr (BF) {
             __syncthreads();
@@ -1505,16 +1612,15 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
         for (int idx = tid; idx < ni; idx += NT) Sk[idx] = 0.f;
         __syncthreads();
         if constexpr (BF)
-            block_tiles_bf<JP, NW>(a, sch[si], sch[P + si], L, tid, pre_cend);
+            block_tiles_bf<JP, NW>(a, sch[si], sch[P + si], L, tid0, pre_cend);
         else
             block_tiles<JP, NW>(a, sch[si], sch[P + si], L, tid, pre_cend);
         pre_cend = 0;
         store_rows_coh(a.Ap, L.Ab, s1, r1, J1, RS, tid, NT);
-        float* Sp = a.Spart + (size_t)p * ni;
-        for (int idx = tid; idx < ni; idx += NT) st_coh(Sp + idx, Sk[idx]);
-        coh_stores_done();
+        unsigned long long* Xp = Xpart + (size_t)p * ni;
+        for (int idx = tid; idx < ni; idx += NT) st_tag(Xp + idx, Sk[idx], tg);
         // the next stratum's tile metadata (as load_tile_cache lays it out) and
-        // first record chunk: read-only, requested now, used after the barrier
+        // first record chunk: read-only, requested now, used after the polls
         const bool more = si + 1 < P;
         const int tn0 = more ? sch[si + 1] : 0, tn1 = more ? sch[P + si + 1] : 0;
         const int zn0 = more ? sch[2 * P + si + 1] : 0, zn1 = more ? sch[3 * P + si + 1] : 0;
@@ -1524,47 +1630,55 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
         uint2 rr[kPreRec];
 #pragma unroll
         for (int h = 0; h < kPreTc; ++h) {
-            const int u = pt + h * (NT - 64);
+            const int u = pt + h * (NT - 128);
             tov[h] = pt >= 0 && u <= ntc ? a.tile_off[tn0 + u] : 0;
             tkv[h] = pt >= 0 && u < ntc ? a.tile_k[tn0 + u] : 0;
         }
 #pragma unroll
         for (int h = 0; h < kPreRec; ++h) {
-            const int i = pt + h * (NT - 64);
+            const int i = pt + h * (NT - 128);
             rr[h] = pt >= 0 && i < nrec ? a.nz[zn0 + i] : make_uint2(0u, 0u);
         }
-        if (!grid_sync(a.bar, P, nbar, flag)) return;
+        float cv = tid < kCstHead + I3 ? a.ccst[(size_t)s * (kCstHead + I3) + tid] : 0.f;
 
-        // every block of this stratum has stored its rows and sums: this
-        // workgroup's share of the sums (one chunk of kRedChunk blocks per
-        // thread when the share allows) and the next stratum's patient rows,
-        // in one round of loads
+        // this workgroup's share of the stratum sums: with one chunk of
+        // kRedChunk blocks per thread when the share allows, all blocks'
+        // sums polled in one round
         float rv[kRedChunk];
-        {
-            const bool rt = one && tid < (i1 - i0) * nchr;
+        if (one) {
+            const bool rt = tid < (i1 - i0) * nchr;
             const int p0 = rch * kRedChunk;
+            const int n = rt ? (P - p0 < kRedChunk ? P - p0 : kRedChunk) : 0;
+            // this workgroup's own block sums come from LDS
+            const int so = p - p0;
+            const unsigned skip = so >= 0 && so < kRedChunk ? 1u << so : 0u;
+            unsigned long long x[kRedChunk], xe;
+            const bool ok = poll_tagged<kRedChunk>(x, Xpart + (rt ? p0 * ni + i0 + rit : 0), ni, n, skip, xe,
+                                                   nullptr, tg, a.bar);
+            const float mine = rt && skip ? Sk[i0 + rit] : 0.f;
 #pragma unroll
-            for (int u = 0; u < kRedChunk; ++u)
-                rv[u] = rt && p0 + u < P ? ld_coh(a.Spart + (size_t)(p0 + u) * ni + i0 + rit) : 0.f;
-        }
-        if (more) {
-            const int s1n = sch[4 * P + si + 1], r1n = sch[5 * P + si + 1] - s1n;
-            load_rows_coh(L.Ab, a.Ap, s1n, r1n, J1, RS, tid, NT);
-            for (int l = tid; l < r1n; l += NT) lds[S.ra + l] = a.reg1[s1n + l];
+            for (int u = 0; u < kRedChunk; ++u) rv[u] = u == so ? mine : tag_value(x[u]);
+            if (wg_count<NW>(!ok, L.wgs + kWgPoll1 * kDefaultWaves) != 0) return;
         }
         if (pt >= 0) {
 #pragma unroll
             for (int h = 0; h < kPreTc; ++h) {
-                const int u = pt + h * (NT - 64);
+                const int u = pt + h * (NT - 128);
                 if (u <= kTileCache) L.tco[u] = tov[h];
                 if (u < kTileCache) L.tck[u] = tkv[h];
             }
 #pragma unroll
             for (int h = 0; h < kPreRec; ++h) {
-                const int i = pt + h * (NT - 64);
+                const int i = pt + h * (NT - 128);
                 if (i < nrec) L.rec[i] = rr[h];
             }
         }
+        if (tid < kCstHead + I3) cst[tid] = cv;
+        for (int idx = tid + NT; idx < kCstHead + I3; idx += NT) cst[idx] = a.ccst[(size_t)s * (kCstHead + I3) + idx];
+        // this wavefront's patient rows (stored before the polls) have been
+        // performed; once every wavefront has passed this, the block's "rows
+        // stored" word goes out with the share
+        coh_stores_done();
         if (one) {
             // the order of reduce_items: each chunk's blocks ascending, then
             // the chunks ascending
@@ -1575,23 +1689,68 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
                 red[rit * nchr + rch] = cs;
             }
             __syncthreads();
+            if (tid == 0) st_tag(Xrows + p, 0.f, tg);
             if (tid < i1 - i0) {
                 float t = 0.f;
+#pragma unroll 8
                 for (int ch = 0; ch < nchr; ++ch) t += red[tid * nchr + ch];
-                st_coh(a.Ssum + i0 + tid, t);
+                st_tag(Xsum + i0 + tid, t, tg);
+                Sk[i0 + tid] = t;
             }
         } else {
-            reduce_items(a.Spart, P, ni, i0, i1, a.Ssum + i0, true, red, tid, NT);
+            if (!reduce_items_tagged(Xpart, P, ni, i0, i1, Xsum + i0, Sk, p, tg, a.bar, red,
+                                     L.wgs + kWgReduce * kDefaultWaves, tid, NT))
+                return;
+            if (tid == 0) st_tag(Xrows + p, 0.f, tg);
         }
         // the tiles of the prefetched chunk whose records fit in it
-        pre_cend = __syncthreads_count(tid < ntc && L.tco[tid + 1] - L.tco[0] <= a.rec_cap);
-        coh_stores_done();
-        if (!grid_sync(a.bar, P, nbar, flag)) return;
+        pre_cend = wg_count<NW>(tid < ntc && L.tco[tid + 1] - L.tco[0] <= a.rec_cap, L.wgs + kWgPre * kDefaultWaves);
 
-        for (int idx = tid; idx < ni; idx += NT) Sk[idx] = ld_coh(a.Ssum + idx);
-        for (int idx = tid; idx < kCstHead + I3; idx += NT) cst[idx] = a.ccst[(size_t)s * (kCstHead + I3) + idx];
-        __syncthreads();
+        // every stratum sum (this workgroup's own share is in Sk already),
+        // and the "rows stored" word of the patient block the next stratum
+        // visits (stored in this stratum by the workgroup that visited it),
+        // kSumPoll sums per thread and round
+        {
+            const int pn = more ? (q - sch[6 * P + si + 1] + P) % P : 0;
+            bool ok = true;
+            for (int base = 0; base < ni; base += kSumPoll * NT) {
+                const int i = base + tid;
+                const int n = i < ni ? ((ni - i + NT - 1) / NT < kSumPoll ? (ni - i + NT - 1) / NT : kSumPoll) : 0;
+                unsigned skip = 0u;
+#pragma unroll
+                for (int u = 0; u < kSumPoll; ++u)
+                    if (i + u * NT >= i0 && i + u * NT < i1) skip |= 1u << u;
+                unsigned long long x[kSumPoll], xe;
+                ok = ok && poll_tagged<kSumPoll>(x, Xsum + i, NT, n, skip, xe,
+                                                 more && base == 0 && tid == NT - 1 ? Xrows + pn : nullptr, tg,
+                                                 a.bar);
+#pragma unroll
+                for (int u = 0; u < kSumPoll; ++u)
+                    if (u < n && !((skip >> u) & 1u)) Sk[i + u * NT] = tag_value(x[u]);
+            }
+            if (wg_count<NW>(!ok, L.wgs + kWgPoll2 * kDefaultWaves) != 0) return;
+        }
+        // the next block's patient rows: the first kRowPre values per thread
+        // requested before the core step, stored after it
+        const int s1n = more ? sch[4 * P + si + 1] : 0, r1n = more ? sch[5 * P + si + 1] - s1n : 0;
+        const int nrv = r1n * J1;
+        const float* rsrc = a.Ap + (size_t)s1n * J1;
+        float rwv[kRowPre];
+#pragma unroll
+        for (int u = 0; u < kRowPre; ++u) rwv[u] = tid + u * NT < nrv ? ld_coh(rsrc + tid + u * NT) : 0.f;
+        const float rg = tid < r1n ? a.reg1[s1n + tid] : 0.f;
         core_update(Cs, Gs, Sk, cst, I3, J12, J3, a.etac, Cn, Gn, tid, NT);
+#pragma unroll
+        for (int u = 0; u < kRowPre; ++u) {
+            const int idx = tid + u * NT;
+            if (idx < nrv) {
+                const int l = idx / J1, c = idx - l * J1;
+                L.Ab[l * RS + c] = rwv[u];
+            }
+        }
+        if (tid < r1n) lds[S.ra + tid] = rg;
+        if (nrv > kRowPre * NT) load_rows_coh(L.Ab, a.Ap, s1n, r1n, J1, RS, tid, NT, kRowPre * NT);
+        for (int l = tid + NT; l < r1n; l += NT) lds[S.ra + l] = a.reg1[s1n + l];
         __syncthreads();
         // the new C and G become current; the old buffers take the next step
         float* t = Cs;
@@ -1601,10 +1760,10 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
         Gs = Gn;
         Gn = t;
     }
-    store_rows(a.Bp, L.Bb, s2, r2, J2, RS, tid, NT);
+    store_rows(a.Bp, L.Bb, s2, r2, J2, RS, tid0, NT);
     if (q == 0) {
-        for (int idx = tid; idx < I3 * J3; idx += NT) a.C[idx] = Cs[idx];
-        for (int idx = tid; idx < J12 * J3; idx += NT) a.G[idx] = Gs[idx];
+        for (int idx = tid0; idx < I3 * J3; idx += NT) a.C[idx] = Cs[idx];
+        for (int idx = tid0; idx < J12 * J3; idx += NT) a.G[idx] = Gs[idx];
     }
 }
 
@@ -1618,7 +1777,7 @@ __global__ __launch_bounds__(64 * NW) void strata_persistent(StratArgs a)
 // Batched sweep: the workgroups [wg_start[i], wg_start[i+1]) of one
 // cooperative launch run problem i with the code of its own core size
 // (a.jp), exactly as the single-problem kernel would; each problem
-// synchronises on its own grid barrier.
+// exchanges through its own tagged words.
 template <bool BF>
 __global__ __launch_bounds__(64 * kDefaultWaves) void strata_sweep(const StratArgs* args, const int32_t* wg_start,
                                                                    int n)
@@ -1733,7 +1892,7 @@ __global__ __launch_bounds__(kCoreThreads) void core_step(StratArgs a, float* Gt
     float* cst = lds + L.cst;
     for (int idx = tid; idx < kCstHead + I3; idx += NT) cst[idx] = a.ccst[(size_t)a.s * (kCstHead + I3) + idx];
     for (int idx = tid; idx < I3 * J3; idx += NT) C0[idx] = a.C[idx];
-    reduce_items(a.Spart, P, ni, 0, ni, S, false, red, tid, NT);
+    reduce_items(a.Spart, P, ni, 0, ni, S, red, tid, NT);
     core_update(C0, a.G, S, cst, I3, J12, J3, a.etac, cgt, Gtmp, tid, NT);
     __syncthreads();
     for (int idx = tid; idx < I3 * J3; idx += NT) a.C[idx] = cgt[idx];

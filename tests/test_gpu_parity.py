@@ -108,6 +108,25 @@ def test_core_sizes(ctx, ranks):
     np.testing.assert_allclose(loss2, orc[4], rtol=LOSS_TOL)
 
 
+def test_fewer_core_items_than_blocks(ctx):
+    # core 1x1x1 over 3 platforms: 3 items of the stratum sums for 8 blocks,
+    # so five of the workgroups reduce nothing and hand over only their rows
+    import paper_1711_08095_amd as sn
+    case = planted_case(seed=21, dims=(120, 160, 3), ranks=(1, 1, 1), nnz=6000, edges=400, P=8, T=64)
+    prob = gpu_problem(ctx, case)
+    assert prob.exec_path() == sn.PATH_PERSISTENT
+    orc = run_oracle(case, 3)
+    gpu, loss, _, _ = run_gpu(ctx, case, 3, prob=prob)
+    _check_factors(gpu, orc[:4])
+    np.testing.assert_allclose(loss, orc[4], rtol=LOSS_TOL)
+    # and bit for bit the multi-launch driver's result
+    prob.set_exec(path=sn.PATH_MULTI)
+    gpu2, loss2, _, _ = run_gpu(ctx, case, 3, prob=prob)
+    for a, b in zip(gpu, gpu2):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(loss, loss2)
+
+
 def test_empty_rows_and_platforms(ctx):
     # rows with no nonzeros stay put (except B through the graph), a platform
     # with no nonzeros keeps its C row
