@@ -89,7 +89,7 @@ __host__ __device__ inline StratLds strat_lds_layout(int jp, int P, int rows1_ma
     L.c = o;     o = up4(o + I3 * J3);
     L.g = o;     o = up4(o + j12 * J3);
     const int f32 = bf ? 0 : 1;
-    L.h = o;     o = up4(o + I3 * jp * jp);              // FP32 H_k (both paths)
+    L.h = o;     o = up4(o + f32 * I3 * jp * jp);        // FP32 H_k (FP32 path)
     const int tr = (!bf && jp > 12) ? 1 : 0;
     L.ht = o;    o = up4(o + tr * I3 * jp * jp);         // H_k^T (FP32 path, JP > 12)
     L.as = o;    o = up4(o + f32 * mp * kTS);
@@ -134,36 +134,43 @@ int jp_for(int J1, int J2)
 // Shared arithmetic (identical instruction sequence in every driver)
 // ---------------------------------------------------------------------------
 
-// H_k[x][y] = sum_c G[x,y,c] C[k,c], zero padded to JP x JP.
+// H_k[x][y] = sum_c G[x,y,c] C[k,c], zero padded to JP x JP, into any of:
+// Hs (FP32, row x), Ht (FP32 H_k^T, row y) and Hb, the BF16 B operands of
+// the matrix-core products W1 = B_tile H_k^T and W2 = A_tile H_k: for
+// platform k, Hb[(2k)(MP)(32)] holds H_k[c][y] at (c, y) and
+// Hb[(2k+1)(MP)(32)] holds H_k[x][c] at (c, x) (row c is read as 8 values
+// per lane).  Hb's entries beyond JP (in c or in the other index) are never
+// written here: clear_hb_pad zeroes them once.
 template <int JP>
 __device__ void build_h(float* Hs, const float* Cs, const float* Gs, int I3, int J1, int J2, int J3, int tid,
-                        int nthr, float* Ht = nullptr)
+                        int nthr, float* Ht = nullptr, __bf16* Hb = nullptr)
 {
+    constexpr int MP = mfma_dim(JP);
     for (int idx = tid; idx < I3 * JP * JP; idx += nthr) {
         const int k = idx / (JP * JP), xy = idx - k * JP * JP, x = xy / JP, y = xy - x * JP;
         float h = 0.f;
         if (x < J1 && y < J2)
             for (int c = 0; c < J3; ++c) h = fmaf(Gs[(x * J2 + y) * J3 + c], Cs[k * J3 + c], h);
-        Hs[idx] = h;
+        if (Hs) Hs[idx] = h;
         if (Ht) Ht[(k * JP + y) * JP + x] = h;  // H_k^T, row y
+        if (Hb) {
+            Hb[((2 * k) * MP + x) * kKB + y] = (__bf16)h;
+            Hb[((2 * k + 1) * MP + y) * kKB + x] = (__bf16)h;
+        }
     }
 }
 
-// BF16 copies of H_k as the B operands of the matrix-core products
-// W1 = B_tile H_k^T and W2 = A_tile H_k: for platform k, Hb[(2k)(MP)(32)]
-// holds H_k[c][y] at (c, y) and Hb[(2k+1)(MP)(32)] holds H_k[x][c] at
-// (c, x), zero outside J1 x J2.  Row c is read as 8 values per lane.  The
-// values are converted from the FP32 H_k that build_h formed.
+// Zeroes the entries of the BF16 operands Hb (see build_h) that lie beyond
+// JP in either index.
 template <int JP>
-__device__ void build_hb(__bf16* Hb, const float* Hs, int I3, int J1, int J2, int tid, int nthr)
+__device__ void clear_hb_pad(__bf16* Hb, int I3, int tid, int nthr)
 {
     constexpr int MP = mfma_dim(JP);
-    for (int idx = tid; idx < I3 * 2 * MP * kKB; idx += nthr) {
-        const int y = idx % kKB, c = (idx / kKB) % MP, kw = idx / (kKB * MP), k = kw >> 1;
-        // entry (c, y) of H_k (kw even) or of H_k^T (kw odd)
-        const int x0 = (kw & 1) ? y : c, y0 = (kw & 1) ? c : y;
-        const float h = (x0 < J1 && y0 < J2) ? Hs[(k * JP + x0) * JP + y0] : 0.f;
-        Hb[idx] = (__bf16)h;
+    if constexpr (MP > JP || kKB > JP) {
+        for (int idx = tid; idx < I3 * 2 * MP * kKB; idx += nthr) {
+            const int y = idx % kKB, c = (idx / kKB) % MP;
+            if (c >= JP || y >= JP) Hb[idx] = (__bf16)0.f;
+        }
     }
 }
 
@@ -1546,6 +1553,7 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
 
     for (int idx = tid0; idx < a.rows1_max * RS; idx += NT) lds[S.a + idx] = 0.f;
     for (int idx = tid0; idx < a.rows2_max * RS; idx += NT) lds[S.b + idx] = 0.f;
+    if constexpr (BF) clear_hb_pad<JP>(reinterpret_cast<__bf16*>(lds + S.hb), I3, tid0, NT);
     for (int si = tid0; si < P; si += NT) {
         const int s = a.order[si], p = (q - s + P) % P, b = p * P + q;
         sch[si] = a.blk_tile[b];
@@ -1604,11 +1612,10 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
         const int p = (q - s + P) % P;
         const int s1 = sch[4 * P + si], r1 = sch[5 * P + si] - s1;
         const unsigned tg = a.tag0 + (unsigned)si + 1u;  // this stratum's tag
-        build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT, (!BF && JP > 12) ? lds + S.ht : nullptr);
-        if constexpr (BF) {
-            __syncthreads();
-            build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Hs, I3, J1, J2, tid, NT);
-        }
+        if constexpr (BF)
+            build_h<JP>(nullptr, Cs, Gs, I3, J1, J2, J3, tid, NT, nullptr, reinterpret_cast<__bf16*>(lds + S.hb));
+        else
+            build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT, JP > 12 ? lds + S.ht : nullptr);
         for (int idx = tid; idx < ni; idx += NT) Sk[idx] = 0.f;
         __syncthreads();
         if constexpr (BF)
@@ -1836,10 +1843,11 @@ __global__ __launch_bounds__(64 * NW) void block_step(StratArgs a)
     for (int idx = tid; idx < J12 * J3; idx += NT) Gs[idx] = a.G[idx];
     for (int idx = tid; idx < ni; idx += NT) Sk[idx] = 0.f;
     __syncthreads();
-    build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT, (!BF && JP > 12) ? lds + S.ht : nullptr);
     if constexpr (BF) {
-        __syncthreads();
-        build_hb<JP>(reinterpret_cast<__bf16*>(lds + S.hb), Hs, I3, J1, J2, tid, NT);
+        clear_hb_pad<JP>(reinterpret_cast<__bf16*>(lds + S.hb), I3, tid, NT);
+        build_h<JP>(nullptr, Cs, Gs, I3, J1, J2, J3, tid, NT, nullptr, reinterpret_cast<__bf16*>(lds + S.hb));
+    } else {
+        build_h<JP>(Hs, Cs, Gs, I3, J1, J2, J3, tid, NT, JP > 12 ? lds + S.ht : nullptr);
     }
     __syncthreads();
     const int t0 = a.blk_tile[p * P + q], t1 = a.blk_tile[p * P + q + 1];
