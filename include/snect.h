@@ -251,7 +251,9 @@ int snect_last_timing(const snect_problem *prob, double *ms5);
  * kernels is taken in an order fixed by the problem alone, so both drivers
  * and every record-chunk size give bit-identical factors and losses.  per_launch_timing records a pair of HIP events around
  * every stratum-kernel launch (no extra host synchronisation); path selects
- * the stratum driver; waves and rec_cap shape the stratum workgroups.
+ * the stratum driver; waves and rec_cap shape the stratum workgroups;
+ * wait_limit bounds the persistent kernel's waits (the factors are undefined
+ * after an epoch that failed that way).
  * SNECT_PATH_PERSISTENT fails with E_UNSUPPORTED at snect_train if the P
  * workgroups cannot all be resident.  Errors: E_ARG, E_HIP. */
 typedef struct {
@@ -260,6 +262,11 @@ typedef struct {
     int32_t waves;   /* wavefronts per stratum workgroup: 0 or 8 (the only size) */
     int32_t rec_cap; /* nonzero records staged in LDS per chunk: 0 (the largest
                         that fits) or a power of two from 64 up to that */
+    int32_t wait_limit; /* poll rounds after which a workgroup of the persistent
+                           kernel stops waiting for another one and the epoch
+                           fails with E_HIP: 0 (the default, 2^25 rounds, far
+                           longer than any stratum) or a positive count; a
+                           small one forces that failure path (tests) */
 } snect_exec;
 
 int snect_set_exec(snect_problem *prob, const snect_exec *exec);

@@ -74,7 +74,7 @@ class Factors(ctypes.Structure):
 
 class Exec(ctypes.Structure):
     _fields_ = [("per_launch_timing", ctypes.c_int32), ("path", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("rec_cap", ctypes.c_int32)]
+                ("rec_cap", ctypes.c_int32), ("wait_limit", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -502,14 +502,16 @@ class Problem:
                     bits_i=int(inf["bits_i"]), bits_j=int(inf["bits_j"]))
 
     def set_exec(self, per_launch_timing: bool = False, path: int = PATH_AUTO, waves: int = 0,
-                 rec_cap: int = 0):
+                 rec_cap: int = 0, wait_limit: int = 0):
         """snect_set_exec: per-launch timing events, the stratum driver, the
-        wavefronts per workgroup and the record chunk (results unchanged)."""
+        wavefronts per workgroup and the record chunk (results unchanged),
+        and the persistent kernel's wait limit (0: the default)."""
         e = Exec()
         e.per_launch_timing = 1 if per_launch_timing else 0
         e.path = int(path)
         e.waves = int(waves)
         e.rec_cap = int(rec_cap)
+        e.wait_limit = int(wait_limit)
         _check(load().snect_set_exec(self.h, ctypes.byref(e)), self.ctx.h)
 
     def autotune(self, A, B, C, G, trials: int = 1):

@@ -160,6 +160,7 @@ struct snect_problem {
     float *d_Spart = nullptr, *d_Ssum = nullptr;
     unsigned long long* d_Sx = nullptr;  // the persistent kernel's tagged exchange words
     uint32_t tag_next = 0;               // tags handed out so far (see take_tags)
+    int32_t wait_limit = 0;              // snect_exec.wait_limit
     int32_t* d_blk_rec = nullptr;  // [P*P+1] first record of each block
     float* d_ccst = nullptr;       // [P][kCstHead+I3] core-step constants per stratum
     int32_t* d_order = nullptr;  // [P]
@@ -810,7 +811,7 @@ static StratArgs strat_args(const snect_problem* pr, const snect_factors* f)
     sa.reg1 = pr->d_reg1; sa.reg2 = pr->d_reg2; sa.cnt3 = pr->d_cnt3;
     sa.Ap = pr->d_Ap; sa.Bp = pr->d_Bp; sa.C = f->C; sa.G = f->G;
     sa.Spart = pr->d_Spart; sa.blk_rec = pr->d_blk_rec; sa.ccst = pr->d_ccst; sa.Ssum = pr->d_Ssum;
-    sa.Sx = pr->d_Sx; sa.tag0 = 0;
+    sa.Sx = pr->d_Sx; sa.tag0 = 0; sa.spin_limit = (uint32_t)pr->wait_limit;
     sa.order = pr->d_order; sa.bar = pr->d_bar; sa.jp = pr->jp;
     sa.P = pr->P; sa.s = 0; sa.I3 = pr->I3; sa.J1 = pr->J1; sa.J2 = pr->J2; sa.J3 = pr->J3;
     sa.rows1_max = pr->rows1_max; sa.rows2_max = pr->rows2_max; sa.bits_i = pr->bits_i; sa.bits_j = pr->bits_j;
@@ -1210,7 +1211,7 @@ int snect_autotune(snect_problem* pr, const snect_factors* f, int32_t trials, sn
     const int keep_path = pr->path, keep_nw = pr->nw, keep_rc = pr->rec_cap;
     const bool keep_pl = pr->per_launch;
     pr->per_launch = false;
-    snect_exec b{0, keep_path, keep_nw, keep_rc};
+    snect_exec b{0, keep_path, keep_nw, keep_rc, pr->wait_limit};
     double bt = -1.0;
     for (int path : {SNECT_PATH_PERSISTENT, SNECT_PATH_MULTI})
         for (int nw : {kDefaultWaves})
@@ -1234,7 +1235,7 @@ int snect_autotune(snect_problem* pr, const snect_factors* f, int32_t trials, sn
                 }
                 if (bt < 0 || t < bt) {
                     bt = t;
-                    b = snect_exec{0, path, nw, rcap};
+                    b = snect_exec{0, path, nw, rcap, pr->wait_limit};
                 }
             }
     pr->per_launch = keep_pl;
@@ -1421,6 +1422,7 @@ int snect_set_exec(snect_problem* pr, const snect_exec* ex)
         return set_err(pr->ctx, SNECT_E_ARG, "unknown path");
     const int nw = ex->waves == 0 ? kDefaultWaves : ex->waves;
     if (nw != kDefaultWaves) return set_err(pr->ctx, SNECT_E_ARG, "waves must be 0 or 8");
+    if (ex->wait_limit < 0) return set_err(pr->ctx, SNECT_E_ARG, "wait_limit must be 0 or positive");
     const int rc = ex->rec_cap == 0 ? pr->rec_cap_max : ex->rec_cap;
     if (rc < kTileMax || rc > pr->rec_cap_max || (rc & (rc - 1)) != 0)
         return set_err(pr->ctx, SNECT_E_ARG,
@@ -1430,6 +1432,7 @@ int snect_set_exec(snect_problem* pr, const snect_exec* ex)
     HIP_TRY(configure_exec(pr, nw, rc));
     pr->per_launch = ex->per_launch_timing != 0;
     pr->path = ex->path;
+    pr->wait_limit = ex->wait_limit;
     return SNECT_OK;
 }
 

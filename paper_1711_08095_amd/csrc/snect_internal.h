@@ -82,6 +82,7 @@ struct StratArgs {
     const int32_t* order;      // [P] stratum order of this epoch
     GridBar* bar;
     uint32_t tag0;
+    uint32_t spin_limit;       // poll rounds before a wait gives up (0: the kernel's default)
     int32_t jp;                // kernel instantiation of this problem's core
     int32_t P, s, I3, J1, J2, J3;
     int32_t rows1_max, rows2_max;

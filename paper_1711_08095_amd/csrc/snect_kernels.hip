@@ -1338,9 +1338,10 @@ __device__ void block_tiles_bf(const StratArgs& a, int t0, int t1, const TileLds
 // next stratum's reader loads them only after it has seen that word.
 //
 // Every poll is bounded: after kSpinLimit rounds (far longer than any
-// stratum can take) the poller sets the error word and gives up, and every
-// poller gives up once it sees the error word set (checked every 128
-// rounds); the workgroup then leaves the launch.
+// stratum can take; the host may set fewer, to test this path) the poller
+// sets the error word and gives up, and every poller gives up once it sees
+// the error word set (checked every 128 rounds); the workgroup then leaves
+// the launch.
 // ---------------------------------------------------------------------------
 constexpr unsigned kSpinLimit = 1u << 25;
 constexpr int kSumPoll = 4;  // stratum sums each thread polls per round
@@ -1360,10 +1361,12 @@ __device__ inline float tag_value(unsigned long long x) { return __uint_as_float
 // Polls the words x[u] = p[u * stride] (u < n <= N, bit u of skip clear)
 // and xe = *pe (unless pe is null) until each carries `tag`; the others
 // read as 0.0 with the tag.  Every round reloads, in flight together, the
-// words still behind.  False if the poll gave up (see above).
+// words still behind.  False if the poll gave up after `limit` rounds or
+// saw the error word set (see above).
 template <int N>
 __device__ bool poll_tagged(unsigned long long (&x)[N], unsigned long long* p, int stride, int n, unsigned skip,
-                            unsigned long long& xe, unsigned long long* pe, unsigned tag, GridBar* bar)
+                            unsigned long long& xe, unsigned long long* pe, unsigned tag, GridBar* bar,
+                            unsigned limit)
 {
     const unsigned long long fresh = (unsigned long long)tag << 32;
 #pragma unroll
@@ -1375,13 +1378,13 @@ __device__ bool poll_tagged(unsigned long long (&x)[N], unsigned long long* p, i
 #pragma unroll
         for (int u = 0; u < N; ++u) done = done && (unsigned)(x[u] >> 32) == tag;
         if (done) return true;
-        if ((++spins & 127u) == 0u) {
-            if (spins > kSpinLimit) {
-                atomicOr(&bar->err, 1u);
-                return false;
-            }
-            if (__hip_atomic_load(&bar->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
+        if (++spins > limit) {
+            atomicOr(&bar->err, 1u);
+            return false;
         }
+        if ((spins & 127u) == 0u &&
+            __hip_atomic_load(&bar->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+            return false;
 #pragma unroll
         for (int u = 0; u < N; ++u)
             if ((unsigned)(x[u] >> 32) != tag) x[u] = ld_tag(p + (size_t)u * stride);
@@ -1396,8 +1399,8 @@ __device__ bool poll_tagged(unsigned long long (&x)[N], unsigned long long* p, i
 // sums of block pown are not polled but read from own (this workgroup's
 // block).  False (for every thread) if a poll gave up.
 __device__ bool reduce_items_tagged(unsigned long long* Sx, int P, int ni, int i0, int i1, unsigned long long* dst,
-                                    float* own, int pown, unsigned tag, GridBar* bar, float* red, int* slots, int tid,
-                                    int nthr)
+                                    float* own, int pown, unsigned tag, GridBar* bar, unsigned limit, float* red,
+                                    int* slots, int tid, int nthr)
 {
     const int nch = (P + kRedChunk - 1) / kRedChunk;
     const int per_pass = nthr / nch > 0 ? nthr / nch : 1;
@@ -1414,7 +1417,8 @@ __device__ bool reduce_items_tagged(unsigned long long* Sx, int P, int ni, int i
             const int so = pown - p0 - g;  // the own block's word in this group
             const unsigned skip = so >= 0 && so < 4 ? 1u << so : 0u;
             unsigned long long x[4], xe;
-            ok = ok && poll_tagged<4>(x, Sx + (size_t)(p0 + g) * ni + base + it, ni, n, skip, xe, nullptr, tag, bar);
+            ok = ok &&
+                 poll_tagged<4>(x, Sx + (size_t)(p0 + g) * ni + base + it, ni, n, skip, xe, nullptr, tag, bar, limit);
 #pragma unroll
             for (int u = 0; u < 4; ++u) s += u == so && u < n ? own[base + it] : tag_value(x[u]);
         }
@@ -1581,6 +1585,7 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
     unsigned long long* Xpart = a.Sx;
     unsigned long long* Xsum = a.Sx + (size_t)P * ni;
     unsigned long long* Xrows = Xsum + ni;
+    const unsigned wlim = a.spin_limit ? a.spin_limit : kSpinLimit;  // poll rounds before a wait gives up
 
     // this workgroup's share of the stratum reduction: consecutive shares go
     // to workgroups on the same XCD, so each XCD fetches its own contiguous
@@ -1661,7 +1666,7 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
             const unsigned skip = so >= 0 && so < kRedChunk ? 1u << so : 0u;
             unsigned long long x[kRedChunk], xe;
             const bool ok = poll_tagged<kRedChunk>(x, Xpart + (rt ? p0 * ni + i0 + rit : 0), ni, n, skip, xe,
-                                                   nullptr, tg, a.bar);
+                                                   nullptr, tg, a.bar, wlim);
             const float mine = rt && skip ? Sk[i0 + rit] : 0.f;
 #pragma unroll
             for (int u = 0; u < kRedChunk; ++u) rv[u] = u == so ? mine : tag_value(x[u]);
@@ -1705,7 +1710,7 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
                 Sk[i0 + tid] = t;
             }
         } else {
-            if (!reduce_items_tagged(Xpart, P, ni, i0, i1, Xsum + i0, Sk, p, tg, a.bar, red,
+            if (!reduce_items_tagged(Xpart, P, ni, i0, i1, Xsum + i0, Sk, p, tg, a.bar, wlim, red,
                                      L.wgs + kWgReduce * kDefaultWaves, tid, NT))
                 return;
             if (tid == 0) st_tag(Xrows + p, 0.f, tg);
@@ -1730,7 +1735,7 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
                 unsigned long long x[kSumPoll], xe;
                 ok = ok && poll_tagged<kSumPoll>(x, Xsum + i, NT, n, skip, xe,
                                                  more && base == 0 && tid == NT - 1 ? Xrows + pn : nullptr, tg,
-                                                 a.bar);
+                                                 a.bar, wlim);
 #pragma unroll
                 for (int u = 0; u < kSumPoll; ++u)
                     if (u < n && !((skip >> u) & 1u)) Sk[i + u * NT] = tag_value(x[u]);

@@ -127,6 +127,35 @@ def test_fewer_core_items_than_blocks(ctx):
     np.testing.assert_array_equal(loss, loss2)
 
 
+def test_exchange_time_out_is_reported_and_leaves_no_trace(ctx):
+    # a wait limit of one poll round forces the persistent kernel's time-out
+    # path from the host: the waiting workgroups give up, the epoch fails
+    # with the time-out error and every workgroup leaves the launch; the
+    # exchange words that launch left behind carry tags no later launch uses,
+    # so the next epochs are bit for bit those of a fresh problem
+    import paper_1711_08095_amd as sn
+    case = planted_case(P=8, T=64)
+    ref, lref, _, _ = run_gpu(ctx, case, 2)
+    prob = gpu_problem(ctx, case)
+    assert prob.exec_path() == sn.PATH_PERSISTENT
+    prob.set_exec(wait_limit=1)
+    failed = 0
+    for _ in range(3):
+        try:
+            run_gpu(ctx, case, 1, prob=prob)
+        except sn.SnectError as e:
+            assert "timed out" in str(e)
+            failed += 1
+    assert failed > 0
+    with pytest.raises(sn.SnectError):
+        prob.set_exec(wait_limit=-1)
+    prob.set_exec()
+    got, lgot, _, _ = run_gpu(ctx, case, 2, prob=prob)
+    for a, b in zip(ref, got):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(lref, lgot)
+
+
 def test_empty_rows_and_platforms(ctx):
     # rows with no nonzeros stay put (except B through the graph), a platform
     # with no nonzeros keeps its C row
