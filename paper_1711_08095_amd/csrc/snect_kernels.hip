@@ -1672,21 +1672,6 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
             for (int u = 0; u < kRedChunk; ++u) rv[u] = u == so ? mine : tag_value(x[u]);
             if (wg_count<NW>(!ok, L.wgs + kWgPoll1 * kDefaultWaves) != 0) return;
         }
-        if (pt >= 0) {
-#pragma unroll
-            for (int h = 0; h < kPreTc; ++h) {
-                const int u = pt + h * (NT - 128);
-                if (u <= kTileCache) L.tco[u] = tov[h];
-                if (u < kTileCache) L.tck[u] = tkv[h];
-            }
-#pragma unroll
-            for (int h = 0; h < kPreRec; ++h) {
-                const int i = pt + h * (NT - 128);
-                if (i < nrec) L.rec[i] = rr[h];
-            }
-        }
-        if (tid < kCstHead + I3) cst[tid] = cv;
-        for (int idx = tid + NT; idx < kCstHead + I3; idx += NT) cst[idx] = a.ccst[(size_t)s * (kCstHead + I3) + idx];
         // this wavefront's patient rows (stored before the polls) have been
         // performed; once every wavefront has passed this, the block's "rows
         // stored" word goes out with the share
@@ -1715,8 +1700,28 @@ __device__ void strata_body(const StratArgs& a, int q, float* lds)
                 return;
             if (tid == 0) st_tag(Xrows + p, 0.f, tg);
         }
-        // the tiles of the prefetched chunk whose records fit in it
-        pre_cend = wg_count<NW>(tid < ntc && L.tco[tid + 1] - L.tco[0] <= a.rec_cap, L.wgs + kWgPre * kDefaultWaves);
+        // the tiles of the prefetched chunk whose records fit in it, from the
+        // offsets in registers (tile u + 1 starts at tov of thread u + 1; the
+        // chunk starts at the block's first record zn0)
+        static_assert(kPreTc == 1, "one prefetched tile offset per thread");
+        pre_cend = wg_count<NW>(pt >= 1 && pt <= ntc && tov[0] - zn0 <= a.rec_cap, L.wgs + kWgPre * kDefaultWaves);
+        // the prefetched chunk and the stratum's core-step constants into LDS
+        // (read after the next workgroup barrier)
+        if (pt >= 0) {
+#pragma unroll
+            for (int h = 0; h < kPreTc; ++h) {
+                const int u = pt + h * (NT - 128);
+                if (u <= kTileCache) L.tco[u] = tov[h];
+                if (u < kTileCache) L.tck[u] = tkv[h];
+            }
+#pragma unroll
+            for (int h = 0; h < kPreRec; ++h) {
+                const int i = pt + h * (NT - 128);
+                if (i < nrec) L.rec[i] = rr[h];
+            }
+        }
+        if (tid < kCstHead + I3) cst[tid] = cv;
+        for (int idx = tid + NT; idx < kCstHead + I3; idx += NT) cst[idx] = a.ccst[(size_t)s * (kCstHead + I3) + idx];
 
         // every stratum sum (this workgroup's own share is in Sk already),
         // and the "rows stored" word of the patient block the next stratum
